@@ -1,0 +1,249 @@
+"""Plain FP64 CPU oracle for the two-site MPS gate update -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  It shares no code with the HIP library
+(``paper_2505_06119_amd``) and never imports it; inputs come from the seeded
+generators in ``paper_2505_06119_amd.synth`` and are passed in as arrays.
+
+Pieces and the passages they follow (arXiv 2505.06119):
+
+* ``theta``             -- Sec. III-B.1 bond contraction and Sec. III-C.2
+  tensor application: the two sites are contracted over their shared bond and
+  the gate over the two physical indices.
+* ``qrcp``              -- Table III, QR with pivoting M = Q R P^T; the greedy
+  definition with exact residual norms, in plain C (``qrcp_oracle.c``).
+* ``two_site_update``   -- Sec. III-C.2: contract, truncated pivoted-QR
+  decomposition, split back into two sites.
+* ``MPS``               -- Sec. III-C.1 canonicalisation (QR / LQ moves of the
+  orthogonality centre) and Sec. III-C.2 application of two-site gates; the
+  state is kept unnormalised so that ``norm_fidelity`` is the paper's
+  norm fidelity <Psi_T|Psi_T> (Sec. III-E) by its definition.
+* ``amplitude``         -- Eq. (2): product of the site matrices selected by
+  the bits.
+* ``overlap``           -- Sec. III-E overlap fidelity, by transfer matrices.
+* ``statevector`` / ``brute_force`` -- Sec. II-A statevector and gates, for
+  exact comparison on small registers.
+
+Where the paper is silent the oracle takes these readings: site 0 is the most
+significant qubit; the gate's row index is 2a'+b' with a on the lower site;
+equal residual norms go to the smallest original column; the truncation rank
+is k = min(chi_cap, m, n) with no tolerance cut-off; the orthogonality centre
+is moved to site i (or i+1 when it lies right of i) before each update and the
+split leaves Q on the left site.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the C part of the oracle with gcc (FP64, OpenMP)."""
+    if force or not os.path.exists(_SO):
+        src = os.path.join(_HERE, "qrcp_oracle.c")
+        tmp = _SO + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               src, "-o", tmp, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_SO)
+        p = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        lib.orc_qrcp.restype = ctypes.c_int
+        lib.orc_qrcp.argtypes = [i64, i64, i64, ctypes.c_int, p, i64, p, i64, p, i64,
+                                 p, p, p, p]
+        lib.orc_num_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+# --- factorisation -------------------------------------------------------------
+
+def qrcp(a: np.ndarray, kmax: int, pivoting: bool = True) -> dict:
+    """Greedy column-pivoted Householder QR of ``a`` stopped after k steps.
+
+    Returns a dict with Q (m x k), R (k x n, pivoted column order), piv (n),
+    diagR (k), err (||R22||_F), k.  See ``qrcp_oracle.c``."""
+    lib = _load()
+    a = np.asfortranarray(a, dtype=np.complex128)
+    m, n = a.shape
+    k = max(0, min(int(kmax), m, n))
+    q = np.zeros((m, k), dtype=np.complex128, order="F")
+    r = np.zeros((k, n), dtype=np.complex128, order="F")
+    piv = np.zeros(n, dtype=np.int32)
+    diag = np.zeros(max(k, 1), dtype=np.float64)
+    err = np.zeros(1, dtype=np.float64)
+    kout = np.zeros(1, dtype=np.int64)
+    rc = lib.orc_qrcp(m, n, int(kmax), 1 if pivoting else 0,
+                      a.ctypes.data, max(m, 1), q.ctypes.data, max(m, 1),
+                      r.ctypes.data, max(k, 1), piv.ctypes.data, diag.ctypes.data,
+                      err.ctypes.data, kout.ctypes.data)
+    if rc != 0:
+        raise ValueError("orc_qrcp rejected its arguments")
+    return {"Q": q, "R": r, "piv": piv.astype(np.int64), "diagR": diag[:k],
+            "err": float(err[0]), "k": int(kout[0])}
+
+
+def r_unpivot(r: np.ndarray, piv: np.ndarray) -> np.ndarray:
+    """R P^T: column j of R goes back to original column piv[j]."""
+    out = np.empty_like(r)
+    out[:, piv] = r
+    return out
+
+
+# --- two-site update -----------------------------------------------------------
+
+def theta(a: np.ndarray, b: np.ndarray, g: np.ndarray) -> np.ndarray:
+    """theta[(l,a'),(b',r)] = sum_{a,b} G[a'b',ab] sum_m A[l,a,m] B[m,b,r].
+
+    Returned as a (2*chi_l) x (2*chi_r) matrix with row index 2*l + a' and
+    column index chi_r*b' + r."""
+    chi_l, chi_r = a.shape[0], b.shape[2]
+    t0 = np.tensordot(a, b, axes=(2, 0))                 # [l, a, b, r]
+    g4 = np.asarray(g, dtype=np.complex128).reshape(2, 2, 2, 2)
+    t = np.einsum("xyab,labr->lxyr", g4, t0)
+    return t.reshape(2 * chi_l, 2 * chi_r)
+
+
+def two_site_update(a: np.ndarray, b: np.ndarray, g: np.ndarray, chi_cap: int) -> dict:
+    """Contract, factorise by truncated pivoted QR, split (Sec. III-C.2).
+
+    The new left site is Q_k reshaped (chi_l, 2, k); the new right site is
+    R_k P^T reshaped (k, 2, chi_r).  Nothing is renormalised."""
+    chi_l, chi_r = a.shape[0], b.shape[2]
+    th = theta(a, b, g)
+    f = qrcp(th, chi_cap, pivoting=True)
+    k = f["k"]
+    a2 = f["Q"].reshape(chi_l, 2, k)
+    rp = r_unpivot(f["R"], f["piv"])
+    b2 = rp.reshape(k, 2, chi_r)
+    return {"A": np.ascontiguousarray(a2), "B": np.ascontiguousarray(b2), "k": k,
+            "err": f["err"], "norm2": float(np.vdot(th, th).real), "theta": th,
+            "piv": f["piv"], "diagR": f["diagR"]}
+
+
+class MPS:
+    """Matrix product state with sites [l, s, r] (Eq. (2)), kept unnormalised."""
+
+    def __init__(self, sites, chi_cap: int, centre: int = 0):
+        self.sites = [np.array(s, dtype=np.complex128) for s in sites]
+        self.chi_cap = int(chi_cap)
+        self.centre = int(centre)
+        self.history = []
+
+    @property
+    def n(self) -> int:
+        return len(self.sites)
+
+    def _move_right(self):
+        c = self.centre
+        a = self.sites[c]
+        chi_l, _, chi_r = a.shape
+        f = qrcp(a.reshape(2 * chi_l, chi_r), min(2 * chi_l, chi_r), pivoting=False)
+        k = f["k"]
+        self.sites[c] = f["Q"].reshape(chi_l, 2, k)
+        self.sites[c + 1] = np.tensordot(f["R"], self.sites[c + 1], axes=(1, 0))
+        self.centre = c + 1
+
+    def _move_left(self):
+        c = self.centre
+        a = self.sites[c]
+        chi_l, _, chi_r = a.shape
+        # LQ of the chi_l x (2 chi_r) matrix as the QR of its conjugate transpose
+        f = qrcp(a.reshape(chi_l, 2 * chi_r).conj().T, min(chi_l, 2 * chi_r), pivoting=False)
+        k = f["k"]
+        self.sites[c] = np.ascontiguousarray(f["Q"].conj().T).reshape(k, 2, chi_r)
+        lmat = f["R"].conj().T                                   # chi_l x k
+        self.sites[c - 1] = np.tensordot(self.sites[c - 1], lmat, axes=(2, 0))
+        self.centre = c - 1
+
+    def move_centre(self, target: int):
+        while self.centre < target:
+            self._move_right()
+        while self.centre > target:
+            self._move_left()
+
+    def apply_gate(self, i: int, g: np.ndarray, chi_cap: int | None = None) -> dict:
+        self.move_centre(i if self.centre <= i else i + 1)
+        cap = self.chi_cap if chi_cap is None else int(chi_cap)
+        u = two_site_update(self.sites[i], self.sites[i + 1], g, cap)
+        self.sites[i], self.sites[i + 1] = u["A"], u["B"]
+        self.centre = i + 1
+        rec = {"i": i, "k": u["k"], "err": u["err"], "norm2": u["norm2"]}
+        self.history.append(rec)
+        return rec
+
+    def apply_layers(self, layers):
+        for layer in layers:
+            for i, g in layer:
+                self.apply_gate(i, g)
+
+    def bond_dims(self):
+        return [s.shape[2] for s in self.sites[:-1]]
+
+
+# --- read-out ------------------------------------------------------------------
+
+def amplitude(sites, bits) -> complex:
+    """<x|Psi> = A_0[:, x_0, :] A_1[:, x_1, :] ... (Eq. (2)); site 0 is the MSB."""
+    v = np.ones((1,), dtype=np.complex128)
+    for s, x in zip(sites, bits):
+        v = v @ s[:, int(x), :]
+    return complex(v[0])
+
+
+def overlap(phi_sites, psi_sites) -> complex:
+    """<Phi|Psi> by left transfer matrices."""
+    e = np.ones((1, 1), dtype=np.complex128)
+    for p, q in zip(phi_sites, psi_sites):
+        t = np.tensordot(e, q, axes=(1, 0))                     # [l', s, r]
+        e = np.tensordot(p.conj(), t, axes=([0, 1], [0, 1]))    # [r', r]
+    return complex(e[0, 0])
+
+
+def norm_fidelity(sites) -> float:
+    """Norm fidelity <Psi_T|Psi_T> (Sec. III-E) of an unnormalised state."""
+    return overlap(sites, sites).real
+
+
+def overlap_fidelity(exact_sv: np.ndarray, sites) -> float:
+    """|<Psi_E|Psi_T>|^2 / <Psi_T|Psi_T> for a normalised exact statevector."""
+    sv = statevector(sites)
+    return float(abs(np.vdot(exact_sv, sv)) ** 2 / np.vdot(sv, sv).real)
+
+
+def statevector(sites) -> np.ndarray:
+    """Dense 2^n statevector of an MPS (site 0 = most significant bit)."""
+    t = sites[0]
+    for s in sites[1:]:
+        t = np.tensordot(t, s, axes=(t.ndim - 1, 0))
+    return t.reshape(-1)
+
+
+def brute_force(n: int, layers, bits=None) -> np.ndarray:
+    """Apply the circuit to a dense statevector (Sec. II-A)."""
+    psi = np.zeros((2,) * n, dtype=np.complex128)
+    psi[tuple(int(b) for b in (bits if bits is not None else [0] * n))] = 1.0
+    for layer in layers:
+        for i, g in layer:
+            g4 = np.asarray(g, dtype=np.complex128).reshape(2, 2, 2, 2)
+            psi = np.tensordot(g4, psi, axes=([2, 3], [i, i + 1]))
+            psi = np.moveaxis(psi, [0, 1], [i, i + 1])
+    return psi.reshape(-1)

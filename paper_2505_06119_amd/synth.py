@@ -1,0 +1,255 @@
+"""Seeded synthetic inputs for the two-site update (gates, site pairs, circuits).
+
+These generators serve both the HIP path and the CPU oracle, so they contain
+none of the update's own arithmetic (no contraction, no factorisation of theta,
+no truncation).  Random orthonormal factors are drawn with numpy's QR of a
+complex Gaussian, which is part of *drawing* the input, not of the method.
+
+Conventions
+-----------
+* A site tensor is a numpy array of shape ``(chi_left, 2, chi_right)`` indexed
+  ``[l, s, r]`` (paper Sec. II-B, matrix product state, Eq. (2)).
+* A 4x4 two-qubit gate ``G`` has row index ``2*a' + b'`` and column index
+  ``2*a + b`` where ``a`` is the qubit on the lower site index.  Site 0 is the
+  most significant bit of a basis state label (paper Sec. II-A, ket notation).
+* All randomness comes from ``numpy.random.Generator(PCG64(seed))``.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SQ2 = 1.0 / np.sqrt(2.0)
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def cgauss(r: np.random.Generator, shape) -> np.ndarray:
+    """Standard complex Gaussian entries (unit variance)."""
+    return (r.standard_normal(shape) + 1j * r.standard_normal(shape)) * SQ2
+
+
+def haar_isometry(r: np.random.Generator, rows: int, cols: int) -> np.ndarray:
+    """Haar-distributed matrix with orthonormal columns (rows >= cols).
+
+    QR of a complex Gaussian with the phases of R's diagonal moved into Q
+    (Mezzadri, "How to generate random matrices from the classical compact
+    groups", 2007)."""
+    assert rows >= cols
+    z = cgauss(r, (rows, cols))
+    q, rr = np.linalg.qr(z)
+    d = np.diagonal(rr)
+    ph = d / np.where(np.abs(d) == 0, 1.0, np.abs(d))
+    return q * ph[None, :]
+
+
+def haar_unitary(r: np.random.Generator, d: int = 4) -> np.ndarray:
+    return haar_isometry(r, d, d)
+
+
+# --- gates printed in the paper (Appendix A and Sec. III-D) -----------------
+
+def gate_h() -> np.ndarray:
+    return SQ2 * np.array([[1, 1], [1, -1]], dtype=np.complex128)
+
+
+def gate_rk(k: int) -> np.ndarray:
+    return np.array([[1, 0], [0, np.exp(2j * np.pi / 2 ** k)]], dtype=np.complex128)
+
+
+def gate_sqrt_x() -> np.ndarray:
+    return SQ2 * np.array([[1, -1j], [-1j, 1]], dtype=np.complex128)
+
+
+def gate_sqrt_y() -> np.ndarray:
+    return SQ2 * np.array([[1, -1], [1, 1]], dtype=np.complex128)
+
+
+def gate_sqrt_w() -> np.ndarray:
+    return SQ2 * np.array([[1, -(1 + 1j) * SQ2], [(1 - 1j) * SQ2, 1]], dtype=np.complex128)
+
+
+def gate_fsim() -> np.ndarray:
+    """fSim(theta=pi/2, phi=pi/6) as printed in Sec. III-D, Eq. (fsim)."""
+    g = np.zeros((4, 4), dtype=np.complex128)
+    g[0, 0] = 1
+    g[1, 2] = -1j
+    g[2, 1] = -1j
+    g[3, 3] = np.exp(-1j * np.pi / 6)
+    return g
+
+
+def gate_swap() -> np.ndarray:
+    g = np.zeros((4, 4), dtype=np.complex128)
+    g[0, 0] = g[1, 2] = g[2, 1] = g[3, 3] = 1
+    return g
+
+
+def gate_cnot() -> np.ndarray:
+    g = np.zeros((4, 4), dtype=np.complex128)
+    g[0, 0] = g[1, 1] = g[2, 3] = g[3, 2] = 1
+    return g
+
+
+def gate_cphase(phi: float) -> np.ndarray:
+    return np.diag([1, 1, 1, np.exp(1j * phi)]).astype(np.complex128)
+
+
+def kron1(g1: np.ndarray, on_lower: bool) -> np.ndarray:
+    """Lift a one-qubit gate to the 4x4 two-site form acting on one qubit."""
+    eye = np.eye(2, dtype=np.complex128)
+    return np.kron(g1, eye) if on_lower else np.kron(eye, g1)
+
+
+# --- site tensors ------------------------------------------------------------
+
+def product_state_sites(n: int, bits=None) -> list:
+    """|b_0 b_1 ... b_{n-1}> as bond-dimension-1 sites."""
+    sites = []
+    for j in range(n):
+        a = np.zeros((1, 2, 1), dtype=np.complex128)
+        a[0, 0 if bits is None else int(bits[j]), 0] = 1.0
+        sites.append(a)
+    return sites
+
+
+def canonical_pair(r: np.random.Generator, chi_l: int, chi_m: int, chi_r: int,
+                   sigma: np.ndarray):
+    """Two neighbouring sites with the orthogonality centre on the middle bond.
+
+    A_i viewed as a (2*chi_l) x chi_m matrix (rows indexed l + chi_l*s) has
+    orthonormal columns (left-canonical); A_{i+1} viewed as a chi_m x (2*chi_r)
+    matrix (columns indexed s + 2*r) equals diag(sigma/|sigma|) W^H with W
+    orthonormal, so the middle bond carries the spectrum sigma and the pair
+    has unit Frobenius norm.  Requires 2*chi_l >= chi_m and 2*chi_r >= chi_m.
+    """
+    assert len(sigma) == chi_m
+    u = haar_isometry(r, 2 * chi_l, chi_m)              # rows l + chi_l*s
+    a = u.reshape(2, chi_l, chi_m).transpose(1, 0, 2)   # [l, s, m]
+    w = haar_isometry(r, 2 * chi_r, chi_m)
+    s = np.asarray(sigma, dtype=np.float64)
+    s = s / np.linalg.norm(s)
+    mm = s[:, None] * w.conj().T                        # chi_m x (2*chi_r), cols s + 2*r
+    b = mm.reshape(chi_m, chi_r, 2).transpose(0, 2, 1)  # [m, s, r]
+    return np.ascontiguousarray(a), np.ascontiguousarray(b)
+
+
+def exp_spectrum(chi: int, scale: float) -> np.ndarray:
+    """sigma_k = exp(-k/scale), k = 0..chi-1."""
+    return np.exp(-np.arange(chi, dtype=np.float64) / scale)
+
+
+def well_separated(r: np.random.Generator, m: int, n: int):
+    """Matrix whose column-pivoted QR has a known, well separated pivot order.
+
+    theta[:, P[j]] = (Q0 T)[:, j] with Q0 (m x n) Haar-orthonormal, T upper
+    triangular with T_jj = 1 - j/(2n) and tiny off-diagonal entries, and P a
+    random permutation.  Greedy pivoting then picks P[0], P[1], ... with a
+    relative gap of about 1/(2n) at every step.  Returns (theta, P)."""
+    assert m >= n
+    q0 = haar_isometry(r, m, n)
+    t = np.zeros((n, n), dtype=np.complex128)
+    diag = 1.0 - np.arange(n) / (2.0 * n)
+    for c in range(n):
+        t[:c, c] = cgauss(r, c) * (1e-3 * diag[c] / (2.0 * n * np.sqrt(n)))
+        t[c, c] = diag[c]
+    p = r.permutation(n)
+    theta = np.empty((m, n), dtype=np.complex128)
+    theta[:, p] = q0 @ t
+    return theta, p
+
+
+# --- circuits ----------------------------------------------------------------
+
+def brickwork(r: np.random.Generator, n: int, depth: int):
+    """1D brickwork of Haar-random two-qubit gates.
+
+    Layer d acts on bonds (0,1),(2,3),... when d is even and (1,2),(3,4),...
+    when d is odd.  Returns a list of layers, each a list of (i, G)."""
+    layers = []
+    for d in range(depth):
+        layer = [(i, haar_unitary(r, 4)) for i in range(d % 2, n - 1, 2)]
+        layers.append(layer)
+    return layers
+
+
+def ghz_circuit(n: int):
+    """H on qubit 0 then a CNOT chain: gives (|0..0> + |1..1>)/sqrt(2)."""
+    layers = [[(0, gate_cnot() @ kron1(gate_h(), True))]]
+    for i in range(1, n - 1):
+        layers.append([(i, gate_cnot())])
+    return layers
+
+
+def bubble_swaps(order_from, order_to):
+    """Adjacent transpositions that turn one site order into another.
+
+    ``order_from[j]`` is the qubit held by site j.  Bubble sort on the target
+    positions of the held qubits (paper Sec. III-C, site permutation): returns
+    the list of bond indices i at which sites i and i+1 are swapped, in order."""
+    pos = {q: j for j, q in enumerate(order_to)}
+    key = [pos[q] for q in order_from]
+    swaps = []
+    n = len(key)
+    changed = True
+    while changed:
+        changed = False
+        for i in range(n - 1):
+            if key[i] > key[i + 1]:
+                key[i], key[i + 1] = key[i + 1], key[i]
+                swaps.append(i)
+                changed = True
+    return swaps
+
+
+def grid_snakes(rows: int, cols: int):
+    """Row-snake and column-snake embeddings of a rows x cols grid.
+
+    Qubit (y, x) has label y*cols + x.  Returns (row_order, col_order), each a
+    list of qubit labels by chain position."""
+    row_order = []
+    for y in range(rows):
+        xs = range(cols) if y % 2 == 0 else range(cols - 1, -1, -1)
+        row_order += [y * cols + x for x in xs]
+    col_order = []
+    for x in range(cols):
+        ys = range(rows) if x % 2 == 0 else range(rows - 1, -1, -1)
+        col_order += [y * cols + x for y in ys]
+    return row_order, col_order
+
+
+def one_qubit_as_two_site(n: int, q: int, g1: np.ndarray):
+    """A one-qubit gate on qubit q written as a two-site gate on a bond."""
+    if q < n - 1:
+        return (q, kron1(g1, True))
+    return (q - 1, kron1(g1, False))
+
+
+def qft_circuit(n: int, inverse: bool = False):
+    """Quantum Fourier transform on a 1D chain with SWAP routing.
+
+    Textbook circuit (H on qubit j, controlled R_{t-j+1} from every later
+    qubit t, final bit reversal), with R_k = diag(1, exp(2 pi i / 2^k)) as in
+    Appendix A.  A controlled phase between non-neighbours is applied by
+    swapping qubit t next to j and back.  The inverse uses the adjoint gates in
+    reverse order.  Returns a flat list of layers with one gate each."""
+    gates = []
+    for j in range(n):
+        gates.append(one_qubit_as_two_site(n, j, gate_h()))
+        for t in range(j + 1, n):
+            phi = 2 * np.pi / 2 ** (t - j + 1)
+            for s in range(t - 1, j, -1):          # bring qubit t down to j+1
+                gates.append((s, gate_swap()))
+            gates.append((j, gate_cphase(phi)))
+            for s in range(j + 1, t):              # and back
+                gates.append((s, gate_swap()))
+    for i in range(n // 2):                          # bit reversal
+        a, b = i, n - 1 - i
+        for s in range(a, b):
+            gates.append((s, gate_swap()))
+        for s in range(b - 2, a - 1, -1):
+            gates.append((s, gate_swap()))
+    if inverse:
+        gates = [(i, g.conj().T) for i, g in reversed(gates)]
+    return [[g] for g in gates]

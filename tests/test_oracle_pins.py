@@ -1,0 +1,285 @@
+"""Pins of the CPU oracle against facts fixed outside it (no GPU).
+
+Each test checks the oracle against something other than itself: the greedy
+definition of pivoting computed by projections, LAPACK's zgeqp3 (scipy), the
+Eckart-Young bound, exact statevectors, closed forms, and the gate matrices
+printed in the paper (tests/golden/gates.txt).
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle
+from paper_2505_06119_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def greedy_by_projection(a, k):
+    """Pivot j = column with the largest distance to span(chosen columns).
+
+    Literal definition with numpy least squares; independent of Householder."""
+    m, n = a.shape
+    chosen, dists = [], []
+    for _ in range(k):
+        if chosen:
+            basis = a[:, chosen]
+            coef, *_ = np.linalg.lstsq(basis, a, rcond=None)
+            res = a - basis @ coef
+        else:
+            res = a
+        d = np.linalg.norm(res, axis=0)
+        d[chosen] = -1.0
+        best = int(np.argmax(d))
+        chosen.append(best)
+        dists.append(d[best])
+    basis = a[:, chosen]
+    coef, *_ = np.linalg.lstsq(basis, a, rcond=None)
+    err = np.linalg.norm(a - basis @ coef)
+    return chosen, np.array(dists), err
+
+
+@pytest.mark.parametrize("m,n,k,seed", [(7, 5, 5, 0), (6, 9, 4, 1), (9, 9, 6, 2),
+                                         (12, 8, 3, 3), (5, 12, 5, 4)])
+def test_greedy_definition(m, n, k, seed):
+    a = synth.cgauss(synth.rng(seed), (m, n))
+    f = oracle.qrcp(a, k)
+    chosen, dists, err = greedy_by_projection(a, f["k"])
+    assert list(f["piv"][:f["k"]]) == chosen
+    np.testing.assert_allclose(np.abs(f["diagR"]), dists, rtol=1e-12)
+    assert abs(f["err"] - err) <= 1e-12 * max(1.0, err) + 1e-13
+
+
+@pytest.mark.parametrize("m,n,seed", [(64, 64, 5), (200, 100, 6), (256, 256, 7)])
+def test_lapack_zgeqp3_well_separated(m, n, seed):
+    a, p = synth.well_separated(synth.rng(seed), m, n)
+    f = oracle.qrcp(a, n)
+    q_l, r_l, p_l = sla.qr(a, pivoting=True, mode="economic")
+    assert list(p_l) == list(p)
+    assert list(f["piv"]) == list(p)
+    # same Householder convention: R agrees entry by entry, not only up to phases
+    np.testing.assert_allclose(f["R"], r_l[:n, :], atol=1e-12)
+    np.testing.assert_allclose(f["Q"], q_l[:, :n], atol=1e-12)
+
+
+def _check_invariants(a, f):
+    m, n = a.shape
+    k = f["k"]
+    r = f["R"]
+    d = np.abs(f["diagR"])
+    assert np.all(d[1:] <= d[:-1] * (1 + 1e-12) + 1e-14)
+    # |R_jj|^2 >= sum_{t=j..i} |R_ti|^2 for all i >= j (QRCP column property)
+    for j in range(k):
+        tail = np.cumsum(np.abs(r[j:, j:]) ** 2, axis=0)[-1] if j == k - 1 else None
+        colsum = np.sum(np.abs(r[j:k, j:]) ** 2, axis=0)
+        assert np.all(colsum <= d[j] ** 2 * (1 + 1e-10) + 1e-14)
+        del tail
+    q = f["Q"]
+    np.testing.assert_allclose(q.conj().T @ q, np.eye(k), atol=1e-12)
+    rp = oracle.r_unpivot(r, f["piv"])
+    e1 = np.linalg.norm(a - q @ rp)
+    e2 = np.linalg.norm(a - q @ (q.conj().T @ a))
+    scale = np.linalg.norm(a)
+    assert abs(e1 - f["err"]) <= 1e-12 * scale
+    assert abs(e2 - f["err"]) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("m,n,k,seed", [(40, 40, 40, 8), (64, 48, 20, 9), (30, 70, 25, 10)])
+def test_qrcp_invariants_gaussian(m, n, k, seed):
+    a = synth.cgauss(synth.rng(seed), (m, n))
+    _check_invariants(a, oracle.qrcp(a, k))
+
+
+def test_qrcp_invariants_decaying_spectrum():
+    r = synth.rng(11)
+    u = synth.haar_isometry(r, 96, 48)
+    w = synth.haar_isometry(r, 80, 48)
+    s = synth.exp_spectrum(48, 6.0)
+    a = (u * s) @ w.conj().T
+    f = oracle.qrcp(a, 24)
+    _check_invariants(a, f)
+
+
+@pytest.mark.parametrize("seed", [12, 13])
+def test_eckart_young_bound(seed):
+    a = synth.cgauss(synth.rng(seed), (80, 80))
+    k = 40
+    f = oracle.qrcp(a, k)
+    sv = np.linalg.svd(a, compute_uv=False)
+    best = np.sqrt(np.sum(sv[k:] ** 2))
+    assert f["err"] >= best * (1 - 1e-12)
+    assert f["err"] <= 3.0 * best   # QRCP is a reasonable, not optimal, truncation
+
+
+def test_tie_break_smallest_original_index():
+    perm = synth.rng(14).permutation(9)
+    a = np.eye(9, dtype=np.complex128)[:, perm]
+    f = oracle.qrcp(a, 9)
+    assert list(f["piv"]) == list(range(9))     # every step is an exact tie
+    b = np.zeros((4, 5), dtype=np.complex128)
+    b[0, 3] = b[1, 1] = 2.0                       # two equal largest columns
+    b[2, 0] = b[3, 4] = 1.0
+    f = oracle.qrcp(b, 4)
+    assert list(f["piv"][:4]) == [1, 3, 0, 4]
+
+
+def test_rank_deficient_gives_zero_reflectors():
+    r = synth.rng(15)
+    a = synth.cgauss(r, (10, 2)) @ synth.cgauss(r, (2, 8))   # rank 2
+    f = oracle.qrcp(a, 6)
+    q = f["Q"]
+    np.testing.assert_allclose(q.conj().T @ q, np.eye(6), atol=1e-12)
+    assert np.all(np.abs(f["diagR"][2:]) < 1e-12)
+    assert f["err"] < 1e-12
+
+
+# --- two-site update and MPS ------------------------------------------------------
+
+def test_brickwork_exact_matches_statevector():
+    """12-qubit brickwork, depth 10, chi cap 64 = 2^(n/2): no truncation."""
+    n = 12
+    layers = synth.brickwork(synth.rng(100), n, 10)
+    assert sum(len(l) for l in layers) == 55
+    m = oracle.MPS(synth.product_state_sites(n), chi_cap=64)
+    m.apply_layers(layers)
+    sv = oracle.statevector(m.sites)
+    ref = oracle.brute_force(n, layers)
+    np.testing.assert_allclose(sv, ref, atol=1e-12)
+    assert abs(oracle.norm_fidelity(m.sites) - 1.0) < 1e-12
+    assert max(h["err"] for h in m.history) < 1e-12
+    bits = synth.rng(101).integers(0, 2, size=(20, n))
+    for b in bits:
+        idx = int("".join(map(str, b)), 2)
+        assert abs(oracle.amplitude(m.sites, b) - ref[idx]) < 1e-12
+
+
+def test_single_truncation_overlap_equals_norm_fidelity():
+    """One truncation at the orthogonality centre is an orthogonal projection,
+    so overlap fidelity |<E|T>|^2/<T|T> equals norm fidelity <T|T>."""
+    n = 8
+    layers = synth.brickwork(synth.rng(102), n, 6)
+    m = oracle.MPS(synth.product_state_sites(n), chi_cap=16)
+    m.apply_layers(layers)
+    g = synth.haar_unitary(synth.rng(103), 4)
+    exact = oracle.brute_force(n, layers + [[(3, g)]])
+    rec = m.apply_gate(3, g, chi_cap=5)
+    assert rec["err"] > 1e-3
+    fbar = oracle.norm_fidelity(m.sites)
+    f = oracle.overlap_fidelity(exact, m.sites)
+    assert abs(fbar - f) < 1e-12
+    assert abs(fbar - (1.0 - rec["err"] ** 2)) < 1e-12
+
+
+def test_truncated_circuit_fidelity_close_to_overlap():
+    """Sec. III-E: norm fidelity tracks overlap fidelity over many truncations."""
+    n = 10
+    layers = synth.brickwork(synth.rng(104), n, 8)
+    m = oracle.MPS(synth.product_state_sites(n), chi_cap=8)
+    m.apply_layers(layers)
+    exact = oracle.brute_force(n, layers)
+    fbar = oracle.norm_fidelity(m.sites)
+    f = oracle.overlap_fidelity(exact, m.sites)
+    assert 0.05 < fbar < 0.999
+    assert abs(np.log(fbar) - np.log(f)) < 0.25
+
+
+def test_ghz_state():
+    n = 7
+    m = oracle.MPS(synth.product_state_sites(n), chi_cap=2)
+    m.apply_layers(synth.ghz_circuit(n))
+    assert max(m.bond_dims()) <= 2
+    s2 = 1 / np.sqrt(2)
+    assert abs(oracle.amplitude(m.sites, [0] * n) - s2) < 1e-13
+    assert abs(oracle.amplitude(m.sites, [1] * n) - s2) < 1e-13
+    assert abs(oracle.amplitude(m.sites, [1, 0, 0, 0, 0, 0, 0])) < 1e-13
+
+
+@pytest.mark.parametrize("x", [0, 5, 19, 31])
+def test_qft_closed_form(x):
+    n = 5
+    N = 2 ** n
+    bits = [(x >> (n - 1 - j)) & 1 for j in range(n)]
+    m = oracle.MPS(synth.product_state_sites(n, bits), chi_cap=32)
+    m.apply_layers(synth.qft_circuit(n))
+    ref = np.exp(2j * np.pi * x * np.arange(N) / N) / np.sqrt(N)
+    np.testing.assert_allclose(oracle.statevector(m.sites), ref, atol=1e-12)
+    m.apply_layers(synth.qft_circuit(n, inverse=True))
+    sv = oracle.statevector(m.sites)
+    assert abs(abs(sv[x]) - 1.0) < 1e-12
+
+
+def test_swap_permutation_roundtrip():
+    """Bubble-sort embedding change and its inverse restore the state."""
+    n = 6
+    layers = synth.brickwork(synth.rng(105), n, 4)
+    m = oracle.MPS(synth.product_state_sites(n), chi_cap=8)
+    m.apply_layers(layers)
+    before = oracle.statevector(m.sites)
+    order = [0, 1, 2, 3, 4, 5]
+    target = [3, 0, 5, 1, 4, 2]
+    fwd = synth.bubble_swaps(order, target)
+    back = synth.bubble_swaps(target, order)
+    for i in fwd + back:
+        m.apply_gate(i, synth.gate_swap())
+    np.testing.assert_allclose(oracle.statevector(m.sites), before, atol=1e-12)
+
+
+def test_two_site_update_projection():
+    """theta_T = Q_k Q_k^H theta and err = ||theta - theta_T||_F."""
+    r = synth.rng(106)
+    a, b = synth.canonical_pair(r, 6, 12, 6, synth.exp_spectrum(12, 4.0))
+    g = synth.haar_unitary(r, 4)
+    u = oracle.two_site_update(a, b, g, 8)
+    th = u["theta"]
+    tt = np.tensordot(u["A"], u["B"], axes=(2, 0)).reshape(th.shape)
+    q = u["A"].reshape(-1, u["k"])
+    np.testing.assert_allclose(tt, q @ (q.conj().T @ th), atol=1e-13)
+    assert abs(np.linalg.norm(th - tt) - u["err"]) < 1e-13
+    assert abs(u["norm2"] - 1.0) < 1e-13     # unit-norm pair, unitary gate
+
+
+# --- gates printed in the paper ---------------------------------------------------
+
+def _golden_gates():
+    out, name, rows = {}, None, []
+    env = {"s2": 1 / np.sqrt(2), "pi": np.pi, "exp": np.exp}
+    with open(os.path.join(GOLDEN, "gates.txt")) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#") or line.startswith("cite"):
+                continue
+            if line.startswith("name"):
+                if name:
+                    out[name] = np.array(rows, dtype=np.complex128)
+                name, rows = line.split()[1], []
+                continue
+            rows.append([complex(eval(tok, env)) for tok in line.split()])
+    out[name] = np.array(rows, dtype=np.complex128)
+    return out
+
+
+def test_golden_gates_match_generators():
+    g = _golden_gates()
+    np.testing.assert_allclose(g["H"], synth.gate_h(), atol=1e-15)
+    np.testing.assert_allclose(g["R3"], synth.gate_rk(3), atol=1e-15)
+    np.testing.assert_allclose(g["SQRT_X"], synth.gate_sqrt_x(), atol=1e-15)
+    np.testing.assert_allclose(g["SQRT_Y"], synth.gate_sqrt_y(), atol=1e-15)
+    np.testing.assert_allclose(g["SQRT_W"], synth.gate_sqrt_w(), atol=1e-15)
+    np.testing.assert_allclose(g["FSIM"], synth.gate_fsim(), atol=1e-15)
+
+
+def test_gate_identities():
+    x = np.array([[0, 1], [1, 0]], dtype=complex)
+    y = np.array([[0, -1j], [1j, 0]])
+    w = (x + y) / np.sqrt(2)
+    np.testing.assert_allclose(synth.gate_sqrt_x() @ synth.gate_sqrt_x(), -1j * x, atol=1e-15)
+    np.testing.assert_allclose(synth.gate_sqrt_y() @ synth.gate_sqrt_y(), -1j * y, atol=1e-15)
+    np.testing.assert_allclose(synth.gate_sqrt_w() @ synth.gate_sqrt_w(), -1j * w, atol=1e-15)
+    th, ph = np.pi / 2, np.pi / 6
+    fs = np.array([[1, 0, 0, 0], [0, np.cos(th), -1j * np.sin(th), 0],
+                   [0, -1j * np.sin(th), np.cos(th), 0], [0, 0, 0, np.exp(-1j * ph)]])
+    np.testing.assert_allclose(synth.gate_fsim(), fs, atol=1e-15)
+    for g in (synth.gate_fsim(), synth.gate_sqrt_w(), synth.gate_h()):
+        np.testing.assert_allclose(g @ g.conj().T, np.eye(len(g)), atol=1e-15)
