@@ -1,0 +1,186 @@
+/*
+ * mps_abi.h -- C interface of libmpsgpu.so: the two-site gate update of
+ * matrix-product-state circuit emulation with truncation by column-pivoted
+ * Householder QR, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: arXiv 2505.06119 (Adamski & Brown, "Tensor-Parallel Emulation of
+ * Quantum Circuits with Block-Cyclic Distributed Matrix Product States").
+ *   - MPS form of a state: Sec. II-B, Eq. (2).
+ *   - tensor application of a gate on neighbouring sites: Sec. III-C.2 (the
+ *     sites are contracted, the gate applied, and the result decomposed back
+ *     by a truncating decomposition).
+ *   - QR with pivoting, M = Q R P^T: Table III (Sec. III-B.2).
+ *   - canonicalisation by QR / LQ: Sec. III-C.1.
+ *   - norm fidelity <Psi_T|Psi_T>: Sec. III-E.
+ *
+ * Conventions shared by every call
+ *   complex numbers   interleaved (re, im); complex64 storage for MPS_MIXED,
+ *                     complex128 for MPS_FP64.  Scalars reported to the host
+ *                     are always double.
+ *   matrices          column-major with an explicit leading dimension.
+ *   site tensors      A[l, s, r] (left bond l, physical s in {0,1}, right bond
+ *                     r) stored at offset l + chi_l*(s + 2*r).
+ *   gates             host array of 32 doubles: a 4x4 complex matrix, row-major,
+ *                     row index 2a'+b', column index 2a+b, a = qubit on the
+ *                     lower site.  Site 0 is the most significant bit.
+ *   device pointers   "device" buffers are HIP device memory owned by the
+ *                     caller; the library never allocates device memory.  All
+ *                     work runs on the caller's HIP stream (hipStream_t passed
+ *                     as void*; NULL = the null stream).  Host outputs are
+ *                     written after the stream has been synchronised.
+ *   errors            every call returns an mps_status; on failure
+ *                     mps_last_error() gives a thread-local message.  Argument
+ *                     errors (MPS_EINVAL) are detected on the host before any
+ *                     device work and leave every output untouched.
+ */
+#ifndef MPS_ABI_H
+#define MPS_ABI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MPS_OK = 0,
+    MPS_EINVAL = 1,   /* bad argument: nothing was done */
+    MPS_ENOMEM = 2,   /* workspace / arena too small: nothing was done */
+    MPS_EDEVICE = 3,  /* a HIP call failed */
+    MPS_ENUMERIC = 4, /* non-finite input or result */
+    MPS_ESTATE = 5    /* context unusable after an earlier device failure */
+} mps_status;
+
+typedef enum { MPS_FP64 = 0, MPS_MIXED = 1 } mps_precision;
+typedef enum { MPS_PIVOT_QRCP = 0, MPS_PIVOT_LEARNED = 1 } mps_pivot;
+
+/* Result of one truncating update (host struct). */
+typedef struct {
+    int64_t k;            /* new bond dimension = min(chi_cap, 2 chi_l, 2 chi_r) */
+    double trunc_err_sq;  /* ||R22||_F^2, the discarded weight (Sec. III-E)       */
+    double norm_sq;       /* ||theta||_F^2 before truncation                       */
+    double retained;      /* 1 - trunc_err_sq / norm_sq: this update's factor of
+                             the norm fidelity                                      */
+    int32_t fallback;     /* learned pivots rejected, plain QRCP used (0/1)          */
+    int32_t panels;       /* QR panels processed                                     */
+    int32_t refreshes;    /* exact recomputations of the residual column norms       */
+    int32_t pad;
+} mps_update_info;
+
+const char* mps_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * qrcp_truncate -- column-pivoted Householder QR of A (m x n), stopped after
+ * k = min(k_max, m, n) steps (Table III, "QR with pivoting", M = Q R P^T,
+ * truncated as in Sec. II-B).  Stateless.
+ *
+ *   A     device, read-only, m x n (lda >= m), precision prec.
+ *   Q     device, m x k (ldq >= m): orthonormal columns Q_k.
+ *   RPt   device, k x n (ldr >= k): R_k P^T, i.e. column piv[j] of RPt holds
+ *         column j of the upper-trapezoidal R_k.  Q RPt is the rank-k
+ *         approximation of A.
+ *   piv   device, n int32: piv[j] = original column placed at position j
+ *         (0-based; all n entries).
+ *   diagR device, k doubles: R_jj (real; sign as produced by the reflector
+ *         beta = -sign(Re alpha) ||x||).
+ *   k_out, err_fro (= ||R22||_F), a_fro (= ||A||_F): host, may be NULL.
+ *   work  device scratch of at least qrcp_work_bytes(...) bytes.
+ * Pivot rule: largest residual column norm; exact ties go to the smaller
+ * original column index.
+ * ------------------------------------------------------------------------ */
+int64_t qrcp_work_bytes(int64_t m, int64_t n, int64_t k_max, mps_precision prec);
+mps_status qrcp_truncate(int64_t m, int64_t n, int64_t k_max, mps_precision prec,
+                         const void* A, int64_t lda, void* Q, int64_t ldq, void* RPt, int64_t ldr,
+                         int32_t* piv, double* diagR, int64_t* k_out, double* err_fro, double* a_fro,
+                         void* work, int64_t work_bytes, void* hip_stream);
+
+/* ------------------------------------------------------------------------
+ * mps_update_bond -- one two-site update on explicit site tensors
+ * (Sec. III-C.2): theta = G (A B) contracted over the shared bond chi_m,
+ * truncated pivoted QR of theta as a (2 chi_l) x (2 chi_r) matrix, split into
+ *   A_out = Q_k            (chi_l x 2 x k site, left-orthonormal)
+ *   B_out = R_k P^T        (k x 2 x chi_r site)
+ * with k = min(chi_cap, 2 chi_l, 2 chi_r).  When renormalize != 0, B_out is
+ * scaled by 1/||Q_k R_k P^T||_F so that a state that was normalised stays
+ * normalised; info->retained then carries the norm-fidelity factor.
+ *
+ *   A, B        device, read-only sites (chi_l x 2 x chi_m, chi_m x 2 x chi_r).
+ *   g           host, 32 doubles (4x4 complex, see conventions).
+ *   A_out       device, room for chi_l*2*k elements; may not alias A or B.
+ *   B_out       device, room for k*2*chi_r elements; may not alias A or B.
+ *   info        host, may be NULL.
+ *   work        device scratch of at least mps_update_work_bytes(...) bytes.
+ * pivot = MPS_PIVOT_LEARNED is accepted only through a context with a
+ * trained proposal network; here it returns MPS_EINVAL.
+ * ------------------------------------------------------------------------ */
+int64_t mps_update_work_bytes(int64_t chi_l, int64_t chi_m, int64_t chi_r, int64_t chi_cap,
+                              mps_precision prec, mps_pivot pivot);
+mps_status mps_update_bond(int64_t chi_l, int64_t chi_m, int64_t chi_r, int64_t chi_cap,
+                           mps_precision prec, mps_pivot pivot, const void* A, const void* B,
+                           const double* g, void* A_out, void* B_out, int renormalize,
+                           mps_update_info* info, void* work, int64_t work_bytes, void* hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Stateful MPS of n_sites qubits in the product state |0...0> (all bond
+ * dimensions 1), stored in a caller-provided device arena.  Bond b (between
+ * sites b-1 and b) never exceeds min(2^b, 2^(n-b), chi_max).  The stored state
+ * is kept normalised with the orthogonality centre on one site; the norm
+ * fidelity (Sec. III-E) is accumulated as log F in FP64.
+ * ------------------------------------------------------------------------ */
+typedef struct mps_ctx mps_ctx;
+
+typedef struct {
+    int32_t n_sites;       /* >= 2 */
+    int32_t chi_max;       /* truncation cap chi, >= 1 */
+    mps_precision prec;
+    mps_pivot pivot;
+    double fallback_ratio; /* learned pivots: accept if eps_S <= ratio * eps_QRCP (1.01) */
+    int32_t sketch_rows;   /* learned pivots: rows of the Gaussian sketch */
+    int32_t pad;
+    uint64_t seed;
+} mps_config;
+
+/* Device bytes the arena of mps_create must provide for this configuration. */
+int64_t mps_arena_bytes(const mps_config* cfg);
+
+/* The arena (device, >= mps_arena_bytes) stays owned by the caller and must
+ * outlive the context; the stream is used by every later call on it. */
+mps_status mps_create(const mps_config* cfg, void* dev_arena, int64_t arena_bytes, void* hip_stream,
+                      mps_ctx** out);
+mps_status mps_destroy(mps_ctx* ctx);
+
+/* Apply the 4x4 gate g (host, 32 doubles) to sites (i, i+1), 0 <= i < n-1:
+ * the orthogonality centre is first moved to site i (or to i+1 when it lies
+ * right of i) by unpivoted QR / LQ (Sec. III-C.1), then the two-site update
+ * runs and the centre ends on site i+1.  info (host) may be NULL. */
+mps_status mps_apply_gate(mps_ctx* ctx, int32_t i, const double* g, mps_update_info* info);
+
+/* Apply n gates on pairwise disjoint bonds (i[t] + 1 < i[t+1]), in array
+ * order, with the semantics of n calls of mps_apply_gate.  g: n x 32 doubles;
+ * info: n entries or NULL.  Overlapping or unsorted bonds: MPS_EINVAL, no
+ * state change. */
+mps_status mps_apply_layer(mps_ctx* ctx, int64_t n, const int32_t* i, const double* g,
+                           mps_update_info* info);
+
+/* <x|Psi_T> for the bit string x (host, n_sites bytes of 0/1; site 0 first),
+ * where Psi_T is the stored normalised state times sqrt(norm fidelity), i.e.
+ * the paper's unnormalised truncated state.  out: host, 2 doubles. */
+mps_status mps_amplitude(mps_ctx* ctx, const uint8_t* bits, double* out);
+
+/* log of the norm fidelity accumulated so far (host double). */
+mps_status mps_log_norm_fidelity(const mps_ctx* ctx, double* out);
+
+/* Bond dimensions: dims[b] for b = 0..n_sites (dims[0] = dims[n] = 1). */
+mps_status mps_bond_dims(const mps_ctx* ctx, int64_t* dims);
+
+/* Orthogonality centre site index (host int32). */
+mps_status mps_centre(const mps_ctx* ctx, int32_t* out);
+
+/* Copy site j (chi_l x 2 x chi_r elements, site layout above, complex64 or
+ * complex128 per the context) to the device buffer dst of dst_bytes. */
+mps_status mps_get_site(mps_ctx* ctx, int32_t j, void* dst, int64_t dst_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPS_ABI_H */

@@ -1,0 +1,253 @@
+// C-ABI of libmpsgpu.so (declared in include/mps_abi.h): argument checking on
+// the host, workspace carving, and the host-side sequencing of the gfx950
+// kernels for the two-site update, pivoted QR and the stateful MPS.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mps_abi.h"
+#include "update.hpp"
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static mps_status fail(mps_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static mps_status fail(mps_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+static mps_status hip_fail(hipError_t e, const char* where)
+{
+    return fail(MPS_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+extern "C" const char* mps_last_error(void) { return g_err.c_str(); }
+
+#define HIPCHK(expr, where)                                   \
+    do {                                                      \
+        hipError_t _e = (expr);                               \
+        if (_e != hipSuccess) return hip_fail(_e, where);     \
+    } while (0)
+
+static inline int64_t elem_bytes(mps_precision p) { return p == MPS_FP64 ? 16 : 8; }
+static inline bool valid_prec(int p) { return p == MPS_FP64 || p == MPS_MIXED; }
+
+// Default panel width of the delayed-update QRCP.
+static int panel_width(int64_t m, int64_t n)
+{
+    (void)m;
+    if (n <= 64) return 16;
+    return 32;
+}
+
+static double recompute_tol(mps_precision p)
+{
+    // squared-norm ratio below which a downdated residual norm is recomputed:
+    // sqrt of the storage precision's unit roundoff
+    return p == MPS_FP64 ? 1.4901161193847656e-08 : 3.4526698300124393e-04;
+}
+
+template <typename T>
+static int64_t update_ws_bytes(int64_t m, int64_t n, int64_t k)
+{
+    Carver cv{nullptr, (int64_t)1 << 62, 0};
+    UpdateWs<T> w;
+    carve_update_ws<T>(cv, w, m, n, k, true);
+    return cv.used + 256;
+}
+
+// ---------------------------------------------------------------------------
+// qrcp_truncate
+// ---------------------------------------------------------------------------
+extern "C" int64_t qrcp_work_bytes(int64_t m, int64_t n, int64_t k_max, mps_precision prec)
+{
+    if (m < 0 || n < 0 || k_max < 0 || !valid_prec(prec)) return -1;
+    int64_t k = k_max < m ? k_max : m;
+    k = k < n ? k : n;
+    return prec == MPS_FP64 ? update_ws_bytes<double2>(m, n, k) : update_ws_bytes<float2>(m, n, k);
+}
+
+template <typename T>
+static mps_status qrcp_impl(int64_t m, int64_t n, int64_t k, mps_precision prec, const void* A, int64_t lda,
+                            void* Q, int64_t ldq, void* RPt, int64_t ldr, int32_t* piv, double* diagR,
+                            int64_t* k_out, double* err_fro, double* a_fro, void* work, int64_t work_bytes,
+                            hipStream_t st)
+{
+    Carver cv{(char*)work, work_bytes, 0};
+    UpdateWs<T> w;
+    if (!carve_update_ws<T>(cv, w, m, n, k, true))
+        return fail(MPS_ENOMEM, "qrcp_truncate: work_bytes %lld too small", (long long)work_bytes);
+    w.nb = panel_width(m, n);
+    w.d.tol = recompute_tol(prec);
+    w.d.pivoting = 1;
+    if (n > 0 && m > 0) {
+        dim3 grid((unsigned)(rup(m, 256) < 64 ? rup(m, 256) : 64), (unsigned)n);
+        hipLaunchKernelGGL((k_copy_cols<T>), grid, dim3(256), 0, st, (const T*)A, lda, w.d.A, w.d.lda, m);
+    }
+    init_norms<T>(w, st);
+    HIPCHK(hipGetLastError(), "qrcp_truncate launch");
+    QrcpStats stats;
+    if (k > 0) HIPCHK(run_qrcp<T>(w, st, &stats), "qrcp_truncate factorisation");
+    if (k > 0) {
+        HIPCHK(form_q<T>(w, (T*)Q, ldq, st), "qrcp_truncate Q");
+        hipLaunchKernelGGL((k_rpt<T>), dim3((unsigned)n), dim3(256), 0, st, (const T*)w.d.A, w.d.lda,
+                           (const int32_t*)w.d.perm, k, n, (T*)RPt, ldr, (const double*)w.d.dsc, 0);
+        HIPCHK(hipMemcpyAsync(diagR, w.d.diagR, sizeof(double) * k, hipMemcpyDeviceToDevice, st), "diagR");
+    }
+    if (n > 0) HIPCHK(hipMemcpyAsync(piv, w.d.perm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st), "piv");
+    double dsc[DSC_COUNT];
+    HIPCHK(hipMemcpyAsync(dsc, w.d.dsc, sizeof(dsc), hipMemcpyDeviceToHost, st), "qrcp_truncate readback");
+    HIPCHK(hipStreamSynchronize(st), "qrcp_truncate sync");
+    if (k_out) *k_out = k;
+    if (err_fro) *err_fro = sqrt(dsc[DSC_EPS2] > 0 ? dsc[DSC_EPS2] : 0.0);
+    if (a_fro) *a_fro = sqrt(dsc[DSC_NORM2]);
+    if (!isfinite(dsc[DSC_NORM2])) return fail(MPS_ENUMERIC, "qrcp_truncate: non-finite input");
+    return MPS_OK;
+}
+
+extern "C" mps_status qrcp_truncate(int64_t m, int64_t n, int64_t k_max, mps_precision prec, const void* A,
+                                    int64_t lda, void* Q, int64_t ldq, void* RPt, int64_t ldr, int32_t* piv,
+                                    double* diagR, int64_t* k_out, double* err_fro, double* a_fro, void* work,
+                                    int64_t work_bytes, void* hip_stream)
+{
+    if (m < 1 || n < 1 || k_max < 1) return fail(MPS_EINVAL, "qrcp_truncate: m, n, k_max must be >= 1");
+    if (!valid_prec(prec)) return fail(MPS_EINVAL, "qrcp_truncate: bad precision %d", (int)prec);
+    if (m > (1 << 20) || n > (1 << 20)) return fail(MPS_EINVAL, "qrcp_truncate: dimension too large");
+    int64_t k = k_max < m ? k_max : m;
+    k = k < n ? k : n;
+    if (!A || !Q || !RPt || !piv || !diagR || !work)
+        return fail(MPS_EINVAL, "qrcp_truncate: null device pointer");
+    if (lda < m || ldq < m || ldr < k) return fail(MPS_EINVAL, "qrcp_truncate: leading dimension too small");
+    if (work_bytes < qrcp_work_bytes(m, n, k_max, prec))
+        return fail(MPS_ENOMEM, "qrcp_truncate: need %lld work bytes, got %lld",
+                    (long long)qrcp_work_bytes(m, n, k_max, prec), (long long)work_bytes);
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (prec == MPS_FP64)
+        return qrcp_impl<double2>(m, n, k, prec, A, lda, Q, ldq, RPt, ldr, piv, diagR, k_out, err_fro, a_fro,
+                                  work, work_bytes, st);
+    return qrcp_impl<float2>(m, n, k, prec, A, lda, Q, ldq, RPt, ldr, piv, diagR, k_out, err_fro, a_fro, work,
+                             work_bytes, st);
+}
+
+// ---------------------------------------------------------------------------
+// two-site update core (shared by mps_update_bond and the context)
+// ---------------------------------------------------------------------------
+static bool gate_finite(const double* g)
+{
+    for (int q = 0; q < 32; ++q)
+        if (!isfinite(g[q])) return false;
+    return true;
+}
+
+static Gate4 make_gate(const double* g)
+{
+    Gate4 G;
+    for (int q = 0; q < 16; ++q) G.g[q] = make_double2(g[2 * q], g[2 * q + 1]);
+    return G;
+}
+
+// theta is formed in the workspace before any output is written, so the
+// outputs may alias the input sites.
+template <typename T>
+static mps_status update_core(int64_t chi_l, int64_t chi_m, int64_t chi_r, int64_t chi_cap, mps_precision prec,
+                              const T* A, const T* B, const double* g, T* A_out, T* B_out, int renorm,
+                              mps_update_info* info, void* work, int64_t work_bytes, hipStream_t st)
+{
+    const int64_t m = 2 * chi_l, n = 2 * chi_r;
+    int64_t k = chi_cap < m ? chi_cap : m;
+    k = k < n ? k : n;
+    Carver cv{(char*)work, work_bytes, 0};
+    UpdateWs<T> w;
+    if (!carve_update_ws<T>(cv, w, m, n, k, true)) return fail(MPS_ENOMEM, "update: workspace too small");
+    w.nb = panel_width(m, n);
+    w.d.tol = recompute_tol(prec);
+    w.d.pivoting = 1;
+    QrcpDev<T>& d = w.d;
+
+    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, st, d.ctl, d.dsc);
+    // a1: theta0 = A_mat (m x chi_m) * B_mat (chi_m x n)
+    if (!zgemm<T>(st, OP_N, false, OP_N, false, m, n, chi_m, C_ONE, A, m, B, chi_m, C_ZERO, d.A, d.lda, w.gsplit,
+                  w.gsplit_bytes))
+        return fail(MPS_EINVAL, "update: gemm form unavailable");
+    // a2 + a3
+    hipLaunchKernelGGL((k_gate_norms<T>), dim3((unsigned)chi_r), dim3(256), 0, st, d, chi_l, make_gate(g));
+    hipLaunchKernelGGL((k_partials_final<T>), dim3(1), dim3(256), 0, st, d, (int)chi_r, 1, (int)DSC_NORM2,
+                       (int64_t)0);
+    HIPCHK(hipGetLastError(), "update launch");
+    QrcpStats stats;
+    HIPCHK(run_qrcp<T>(w, st, &stats), "update factorisation");
+    HIPCHK(form_q<T>(w, A_out, m, st), "update Q");
+    hipLaunchKernelGGL((k_rpt<T>), dim3((unsigned)n), dim3(256), 0, st, (const T*)d.A, d.lda,
+                       (const int32_t*)d.perm, k, n, B_out, k, (const double*)d.dsc, renorm);
+    double dsc[DSC_COUNT];
+    HIPCHK(hipMemcpyAsync(dsc, d.dsc, sizeof(dsc), hipMemcpyDeviceToHost, st), "update readback");
+    HIPCHK(hipStreamSynchronize(st), "update sync");
+    if (!isfinite(dsc[DSC_NORM2]) || !isfinite(dsc[DSC_EPS2]))
+        return fail(MPS_ENUMERIC, "update: non-finite theta");
+    if (info) {
+        info->k = k;
+        info->trunc_err_sq = dsc[DSC_EPS2];
+        info->norm_sq = dsc[DSC_NORM2];
+        info->retained = dsc[DSC_NORM2] > 0 ? 1.0 - dsc[DSC_EPS2] / dsc[DSC_NORM2] : 1.0;
+        info->fallback = 0;
+        info->panels = stats.panels;
+        info->refreshes = stats.refreshes;
+        info->pad = 0;
+    }
+    return MPS_OK;
+}
+
+extern "C" int64_t mps_update_work_bytes(int64_t chi_l, int64_t chi_m, int64_t chi_r, int64_t chi_cap,
+                                         mps_precision prec, mps_pivot pivot)
+{
+    (void)chi_m;
+    if (chi_l < 1 || chi_r < 1 || chi_cap < 1 || !valid_prec(prec) || pivot != MPS_PIVOT_QRCP) return -1;
+    const int64_t m = 2 * chi_l, n = 2 * chi_r;
+    int64_t k = chi_cap < m ? chi_cap : m;
+    k = k < n ? k : n;
+    int64_t b = prec == MPS_FP64 ? update_ws_bytes<double2>(m, n, k) : update_ws_bytes<float2>(m, n, k);
+    // split-K scratch for the contraction when chi_m is long and theta small
+    return b + 16 * elem_bytes(prec) * (m * n + 64);
+}
+
+extern "C" mps_status mps_update_bond(int64_t chi_l, int64_t chi_m, int64_t chi_r, int64_t chi_cap,
+                                      mps_precision prec, mps_pivot pivot, const void* A, const void* B,
+                                      const double* g, void* A_out, void* B_out, int renormalize,
+                                      mps_update_info* info, void* work, int64_t work_bytes, void* hip_stream)
+{
+    if (chi_l < 1 || chi_m < 1 || chi_r < 1 || chi_cap < 1)
+        return fail(MPS_EINVAL, "mps_update_bond: dimensions must be >= 1");
+    if (chi_l > (1 << 19) || chi_r > (1 << 19) || chi_m > (1 << 20))
+        return fail(MPS_EINVAL, "mps_update_bond: dimension too large");
+    if (!valid_prec(prec)) return fail(MPS_EINVAL, "mps_update_bond: bad precision %d", (int)prec);
+    if (pivot != MPS_PIVOT_QRCP)
+        return fail(MPS_EINVAL, "mps_update_bond: learned pivots need a context with a trained network");
+    if (!A || !B || !g || !A_out || !B_out || !work) return fail(MPS_EINVAL, "mps_update_bond: null pointer");
+    if (!gate_finite(g)) return fail(MPS_ENUMERIC, "mps_update_bond: non-finite gate entry");
+    const int64_t need = mps_update_work_bytes(chi_l, chi_m, chi_r, chi_cap, prec, pivot);
+    if (work_bytes < need)
+        return fail(MPS_ENOMEM, "mps_update_bond: need %lld work bytes, got %lld", (long long)need,
+                    (long long)work_bytes);
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (prec == MPS_FP64)
+        return update_core<double2>(chi_l, chi_m, chi_r, chi_cap, prec, (const double2*)A, (const double2*)B, g,
+                                    (double2*)A_out, (double2*)B_out, renormalize, info, work, work_bytes, st);
+    return update_core<float2>(chi_l, chi_m, chi_r, chi_cap, prec, (const float2*)A, (const float2*)B, g,
+                               (float2*)A_out, (float2*)B_out, renormalize, info, work, work_bytes, st);
+}
+
+// stateful MPS context
+#include "context.hpp"

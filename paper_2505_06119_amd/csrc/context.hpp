@@ -1,0 +1,417 @@
+// Stateful MPS context (included at the end of abi.hip, after the error
+// helpers and update_core).  The state is a chain of site tensors in a
+// caller-provided device arena, kept normalised with one orthogonality centre;
+// moves of the centre are unpivoted Householder QR (to the right) or LQ, done
+// as the QR of the conjugate transpose (to the left) -- paper Sec. III-C.1.
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_iota(int32_t* perm, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        perm[i] = (int32_t)i;
+}
+
+// dst (cols x rows, ldd) = src (rows x cols, lds)^H, through 32x32 LDS tiles.
+template <typename T>
+__global__ __launch_bounds__(256) void k_conj_transpose(const T* src, int64_t lds, int64_t rows, int64_t cols,
+                                                        T* dst, int64_t ldd)
+{
+    __shared__ T tile[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    const int64_t r0 = (int64_t)blockIdx.x * 32, c0 = (int64_t)blockIdx.y * 32;
+    for (int q = ty; q < 32; q += 8) {
+        const int64_t r = r0 + tx, c = c0 + q;
+        if (r < rows && c < cols) tile[q][tx] = src[r + lds * c];
+    }
+    __syncthreads();
+    for (int q = ty; q < 32; q += 8) {
+        const int64_t c = c0 + tx, r = r0 + q;   // dst row = c, dst col = r
+        if (r < rows && c < cols) {
+            T v = tile[tx][q];
+            v.y = -v.y;
+            dst[c + ldd * r] = v;
+        }
+    }
+}
+
+// out[r] = sum_l v[l] * S[l + ld*r]  (row vector times matrix, FP64 accumulate)
+template <typename T>
+__global__ __launch_bounds__(256) void k_vecmat(const double2* v, const T* S, int64_t ld, int64_t rows,
+                                                int64_t cols, double2* out)
+{
+    __shared__ double red_lds[8];
+    __shared__ double red_out[2];
+    const int64_t r = blockIdx.x;
+    if (r >= cols) return;
+    double2 acc = czero();
+    for (int64_t l = threadIdx.x; l < rows; l += 256) acc = cadd(acc, cmul(v[l], to_d(S[l + ld * r])));
+    double a[2] = {acc.x, acc.y};
+    block_sum_vec<2>(a, red_lds, red_out);
+    if (threadIdx.x == 0) out[r] = make_double2(red_out[0], red_out[1]);
+}
+
+struct mps_ctx {
+    mps_config cfg;
+    int n;
+    int64_t chi_max;
+    mps_precision prec;
+    hipStream_t st;
+    std::vector<int64_t> dims;   // n + 1 bond dimensions
+    std::vector<int64_t> cap;    // per-site capacity in elements
+    std::vector<char*> site;
+    char* ws;
+    int64_t ws_bytes;
+    char* tmp;                   // max site capacity
+    char* rbuf;                  // dmax * dmax elements
+    double2* vec0;
+    double2* vec1;
+    int32_t centre;
+    double log_fid;
+    bool poisoned;
+};
+
+static int64_t max_bond(int n, int b, int64_t chi)
+{
+    int64_t d = chi;
+    const int e1 = b, e2 = n - b;
+    if (e1 < 62 && ((int64_t)1 << e1) < d) d = (int64_t)1 << e1;
+    if (e2 < 62 && ((int64_t)1 << e2) < d) d = (int64_t)1 << e2;
+    return d;
+}
+
+struct CtxLayout {
+    std::vector<int64_t> off;   // site offsets
+    std::vector<int64_t> cap;
+    int64_t dmax, ws_off, ws_bytes, tmp_off, rbuf_off, vec_off, total;
+};
+
+static bool ctx_layout(const mps_config* cfg, CtxLayout& L)
+{
+    const int n = cfg->n_sites;
+    const int64_t eb = elem_bytes(cfg->prec);
+    L.off.assign(n, 0);
+    L.cap.assign(n, 0);
+    int64_t pos = 0, maxcap = 0;
+    L.dmax = 1;
+    for (int j = 0; j < n; ++j) {
+        const int64_t dl = max_bond(n, j, cfg->chi_max), dr = max_bond(n, j + 1, cfg->chi_max);
+        if (dl > L.dmax) L.dmax = dl;
+        L.cap[j] = dl * 2 * dr;
+        maxcap = L.cap[j] > maxcap ? L.cap[j] : maxcap;
+        L.off[j] = pos;
+        pos += (L.cap[j] * eb + 255) / 256 * 256;
+    }
+    const int64_t m = 2 * L.dmax;
+    L.ws_off = pos;
+    L.ws_bytes = (cfg->prec == MPS_FP64 ? update_ws_bytes<double2>(m, m, L.dmax)
+                                        : update_ws_bytes<float2>(m, m, L.dmax)) +
+                 16 * eb * (m * m + 64);
+    pos += (L.ws_bytes + 255) / 256 * 256;
+    L.tmp_off = pos;
+    pos += (maxcap * eb + 255) / 256 * 256;
+    L.rbuf_off = pos;
+    pos += (L.dmax * L.dmax * eb + 255) / 256 * 256;
+    L.vec_off = pos;
+    pos += 2 * ((L.dmax * 16 + 255) / 256 * 256);
+    L.total = pos + 256;
+    return true;
+}
+
+static bool cfg_valid(const mps_config* cfg)
+{
+    return cfg && cfg->n_sites >= 2 && cfg->n_sites <= 4096 && cfg->chi_max >= 1 && cfg->chi_max <= (1 << 16) &&
+           valid_prec(cfg->prec) && (cfg->pivot == MPS_PIVOT_QRCP);
+}
+
+extern "C" int64_t mps_arena_bytes(const mps_config* cfg)
+{
+    if (!cfg_valid(cfg)) return -1;
+    CtxLayout L;
+    ctx_layout(cfg, L);
+    return L.total;
+}
+
+template <typename T>
+static mps_status ctx_init_sites(mps_ctx* c)
+{
+    std::vector<T> one(2);
+    one[0].x = 1; one[0].y = 0;
+    one[1].x = 0; one[1].y = 0;
+    for (int j = 0; j < c->n; ++j)
+        HIPCHK(hipMemcpyAsync(c->site[j], one.data(), 2 * sizeof(T), hipMemcpyHostToDevice, c->st), "init site");
+    HIPCHK(hipStreamSynchronize(c->st), "init sync");
+    return MPS_OK;
+}
+
+extern "C" mps_status mps_create(const mps_config* cfg, void* dev_arena, int64_t arena_bytes, void* hip_stream,
+                                 mps_ctx** out)
+{
+    if (!out) return fail(MPS_EINVAL, "mps_create: out is NULL");
+    *out = nullptr;
+    if (cfg && cfg->pivot == MPS_PIVOT_LEARNED)
+        return fail(MPS_EINVAL, "mps_create: learned pivots are not available in this build");
+    if (!cfg_valid(cfg)) return fail(MPS_EINVAL, "mps_create: invalid configuration");
+    if (!dev_arena) return fail(MPS_EINVAL, "mps_create: arena is NULL");
+    CtxLayout L;
+    ctx_layout(cfg, L);
+    if (arena_bytes < L.total)
+        return fail(MPS_ENOMEM, "mps_create: arena needs %lld bytes, got %lld", (long long)L.total,
+                    (long long)arena_bytes);
+    char* base = (char*)(((uintptr_t)dev_arena + 255) & ~(uintptr_t)255);
+    mps_ctx* c = new mps_ctx();
+    c->cfg = *cfg;
+    c->n = cfg->n_sites;
+    c->chi_max = cfg->chi_max;
+    c->prec = cfg->prec;
+    c->st = (hipStream_t)hip_stream;
+    c->dims.assign(c->n + 1, 1);
+    c->cap = L.cap;
+    c->site.resize(c->n);
+    for (int j = 0; j < c->n; ++j) c->site[j] = base + L.off[j];
+    c->ws = base + L.ws_off;
+    c->ws_bytes = L.ws_bytes;
+    c->tmp = base + L.tmp_off;
+    c->rbuf = base + L.rbuf_off;
+    c->vec0 = (double2*)(base + L.vec_off);
+    c->vec1 = (double2*)(base + L.vec_off + (L.dmax * 16 + 255) / 256 * 256);
+    c->centre = 0;
+    c->log_fid = 0.0;
+    c->poisoned = false;
+    mps_status s = c->prec == MPS_FP64 ? ctx_init_sites<double2>(c) : ctx_init_sites<float2>(c);
+    if (s != MPS_OK) {
+        delete c;
+        return s;
+    }
+    *out = c;
+    return MPS_OK;
+}
+
+extern "C" mps_status mps_destroy(mps_ctx* ctx)
+{
+    if (!ctx) return fail(MPS_EINVAL, "mps_destroy: NULL context");
+    delete ctx;
+    return MPS_OK;
+}
+
+// Unpivoted QR of M (m x n, ld m) in the context workspace: Q (m x k', ldq)
+// and R (k' x n, ld k') into rbuf.  k' = min(m, n).
+template <typename T>
+static mps_status ctx_qr(mps_ctx* c, const T* M, int64_t m, int64_t n, bool transpose_in, int64_t ld_in, T* Q,
+                         int64_t ldq, int64_t* kout)
+{
+    const int64_t k = m < n ? m : n;
+    Carver cv{c->ws, c->ws_bytes, 0};
+    UpdateWs<T> w;
+    if (!carve_update_ws<T>(cv, w, m, n, k, true)) return fail(MPS_ENOMEM, "centre move: workspace too small");
+    w.nb = panel_width(m, n);
+    w.d.tol = 0.0;
+    w.d.pivoting = 0;
+    hipStream_t st = c->st;
+    if (transpose_in) {
+        // M is given as its conjugate transpose: an n x m matrix with ld ld_in
+        dim3 grid((unsigned)rup(n, 32), (unsigned)rup(m, 32));
+        hipLaunchKernelGGL((k_conj_transpose<T>), grid, dim3(256), 0, st, M, ld_in, n, m, w.d.A, w.d.lda);
+    } else {
+        dim3 grid((unsigned)(rup(m, 256) < 64 ? rup(m, 256) : 64), (unsigned)n);
+        hipLaunchKernelGGL((k_copy_cols<T>), grid, dim3(256), 0, st, M, ld_in, w.d.A, w.d.lda, m);
+    }
+    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, st, w.d.ctl, w.d.dsc);
+    hipLaunchKernelGGL((k_iota<T>), dim3((unsigned)rup(n, 256)), dim3(256), 0, st, w.d.perm, n);
+    HIPCHK(hipGetLastError(), "centre move launch");
+    HIPCHK(run_qrcp<T>(w, st, nullptr), "centre move QR");
+    HIPCHK(form_q<T>(w, Q, ldq, st), "centre move Q");
+    hipLaunchKernelGGL((k_rpt<T>), dim3((unsigned)n), dim3(256), 0, st, (const T*)w.d.A, w.d.lda,
+                       (const int32_t*)w.d.perm, k, n, (T*)c->rbuf, k, (const double*)w.d.dsc, 0);
+    HIPCHK(hipGetLastError(), "centre move R");
+    *kout = k;
+    return MPS_OK;
+}
+
+template <typename T>
+static mps_status ctx_move_right(mps_ctx* c)
+{
+    const int s = c->centre;
+    const int64_t chl = c->dims[s], chr = c->dims[s + 1], chr2 = c->dims[s + 2];
+    T* A = (T*)c->site[s];
+    int64_t k = 0;
+    mps_status r = ctx_qr<T>(c, A, 2 * chl, chr, false, 2 * chl, A, 2 * chl, &k);
+    if (r != MPS_OK) return r;
+    // site s+1 <- R (k x chr) * B (chr x 2 chr2)
+    T* B = (T*)c->site[s + 1];
+    if (!zgemm<T>(c->st, OP_N, false, OP_N, false, k, 2 * chr2, chr, C_ONE, (const T*)c->rbuf, k, B, chr, C_ZERO,
+                  (T*)c->tmp, k, nullptr, 0))
+        return fail(MPS_EINVAL, "centre move: gemm form unavailable");
+    HIPCHK(hipMemcpyAsync(B, c->tmp, sizeof(T) * k * 2 * chr2, hipMemcpyDeviceToDevice, c->st), "centre move copy");
+    c->dims[s + 1] = k;
+    c->centre = s + 1;
+    return MPS_OK;
+}
+
+template <typename T>
+static mps_status ctx_move_left(mps_ctx* c)
+{
+    const int s = c->centre;
+    const int64_t chl = c->dims[s], chr = c->dims[s + 1], chl2 = c->dims[s - 1];
+    T* A = (T*)c->site[s];
+    // LQ of A (chl x 2chr): A^H = Q' R', A = R'^H Q'^H
+    int64_t k = 0;
+    mps_status r = ctx_qr<T>(c, A, 2 * chr, chl, true, chl, (T*)c->tmp, 2 * chr, &k);
+    if (r != MPS_OK) return r;
+    {
+        dim3 grid((unsigned)rup(2 * chr, 32), (unsigned)rup(k, 32));
+        hipLaunchKernelGGL((k_conj_transpose<T>), grid, dim3(256), 0, c->st, (const T*)c->tmp, 2 * chr, 2 * chr,
+                           k, A, k);
+    }
+    // site s-1 (2chl2 x chl) <- site s-1 * R'^H
+    T* P = (T*)c->site[s - 1];
+    if (!zgemm<T>(c->st, OP_N, false, OP_C, false, 2 * chl2, k, chl, C_ONE, P, 2 * chl2, (const T*)c->rbuf, k,
+                  C_ZERO, (T*)c->tmp, 2 * chl2, nullptr, 0))
+        return fail(MPS_EINVAL, "centre move: gemm form unavailable");
+    HIPCHK(hipMemcpyAsync(P, c->tmp, sizeof(T) * 2 * chl2 * k, hipMemcpyDeviceToDevice, c->st), "centre move copy");
+    c->dims[s] = k;
+    c->centre = s - 1;
+    return MPS_OK;
+}
+
+template <typename T>
+static mps_status ctx_apply_gate(mps_ctx* c, int i, const double* g, mps_update_info* info)
+{
+    const int target = c->centre <= i ? i : i + 1;
+    while (c->centre < target) {
+        mps_status r = ctx_move_right<T>(c);
+        if (r != MPS_OK) return r;
+    }
+    while (c->centre > target) {
+        mps_status r = ctx_move_left<T>(c);
+        if (r != MPS_OK) return r;
+    }
+    mps_update_info loc;
+    mps_status r = update_core<T>(c->dims[i], c->dims[i + 1], c->dims[i + 2], c->chi_max, c->prec,
+                                  (const T*)c->site[i], (const T*)c->site[i + 1], g, (T*)c->site[i],
+                                  (T*)c->site[i + 1], 1, &loc, c->ws, c->ws_bytes, c->st);
+    if (r != MPS_OK) return r;
+    c->dims[i + 1] = loc.k;
+    c->centre = i + 1;
+    if (loc.retained > 0) c->log_fid += log(loc.retained);
+    if (info) *info = loc;
+    return MPS_OK;
+}
+
+static mps_status ctx_check(const mps_ctx* c)
+{
+    if (!c) return fail(MPS_EINVAL, "NULL context");
+    if (c->poisoned) return fail(MPS_ESTATE, "context unusable after an earlier device failure");
+    return MPS_OK;
+}
+
+extern "C" mps_status mps_apply_gate(mps_ctx* ctx, int32_t i, const double* g, mps_update_info* info)
+{
+    mps_status s = ctx_check(ctx);
+    if (s != MPS_OK) return s;
+    if (i < 0 || i >= ctx->n - 1) return fail(MPS_EINVAL, "mps_apply_gate: bond %d out of range", (int)i);
+    if (!g) return fail(MPS_EINVAL, "mps_apply_gate: NULL gate");
+    if (!gate_finite(g)) return fail(MPS_ENUMERIC, "mps_apply_gate: non-finite gate entry");
+    s = ctx->prec == MPS_FP64 ? ctx_apply_gate<double2>(ctx, i, g, info) : ctx_apply_gate<float2>(ctx, i, g, info);
+    if (s == MPS_EDEVICE) ctx->poisoned = true;
+    return s;
+}
+
+extern "C" mps_status mps_apply_layer(mps_ctx* ctx, int64_t n, const int32_t* idx, const double* g,
+                                      mps_update_info* info)
+{
+    mps_status s = ctx_check(ctx);
+    if (s != MPS_OK) return s;
+    if (n < 0 || (n > 0 && (!idx || !g))) return fail(MPS_EINVAL, "mps_apply_layer: bad arrays");
+    for (int64_t t = 0; t < n; ++t) {
+        if (idx[t] < 0 || idx[t] >= ctx->n - 1)
+            return fail(MPS_EINVAL, "mps_apply_layer: bond %d out of range", (int)idx[t]);
+        if (t > 0 && idx[t] < idx[t - 1] + 2)
+            return fail(MPS_EINVAL, "mps_apply_layer: bonds must be disjoint and increasing");
+        if (!gate_finite(g + 32 * t)) return fail(MPS_ENUMERIC, "mps_apply_layer: non-finite gate entry");
+    }
+    for (int64_t t = 0; t < n; ++t) {
+        s = ctx->prec == MPS_FP64 ? ctx_apply_gate<double2>(ctx, idx[t], g + 32 * t, info ? info + t : nullptr)
+                                  : ctx_apply_gate<float2>(ctx, idx[t], g + 32 * t, info ? info + t : nullptr);
+        if (s != MPS_OK) {
+            if (s == MPS_EDEVICE) ctx->poisoned = true;
+            return s;
+        }
+    }
+    return MPS_OK;
+}
+
+template <typename T>
+static mps_status ctx_amplitude(mps_ctx* c, const uint8_t* bits, double* out)
+{
+    double2 one = make_double2(1.0, 0.0);
+    HIPCHK(hipMemcpyAsync(c->vec0, &one, sizeof(one), hipMemcpyHostToDevice, c->st), "amplitude init");
+    double2* v = c->vec0;
+    double2* wv = c->vec1;
+    for (int j = 0; j < c->n; ++j) {
+        const int64_t chl = c->dims[j], chr = c->dims[j + 1];
+        const T* S = (const T*)c->site[j] + chl * bits[j];
+        hipLaunchKernelGGL((k_vecmat<T>), dim3((unsigned)chr), dim3(256), 0, c->st, (const double2*)v, S, 2 * chl,
+                           chl, chr, wv);
+        double2* t = v;
+        v = wv;
+        wv = t;
+    }
+    double2 res;
+    HIPCHK(hipMemcpyAsync(&res, v, sizeof(res), hipMemcpyDeviceToHost, c->st), "amplitude readback");
+    HIPCHK(hipStreamSynchronize(c->st), "amplitude sync");
+    const double s = exp(0.5 * c->log_fid);
+    out[0] = res.x * s;
+    out[1] = res.y * s;
+    return MPS_OK;
+}
+
+extern "C" mps_status mps_amplitude(mps_ctx* ctx, const uint8_t* bits, double* out)
+{
+    mps_status s = ctx_check(ctx);
+    if (s != MPS_OK) return s;
+    if (!bits || !out) return fail(MPS_EINVAL, "mps_amplitude: NULL argument");
+    for (int j = 0; j < ctx->n; ++j)
+        if (bits[j] > 1) return fail(MPS_EINVAL, "mps_amplitude: bit %d is not 0/1", j);
+    s = ctx->prec == MPS_FP64 ? ctx_amplitude<double2>(ctx, bits, out) : ctx_amplitude<float2>(ctx, bits, out);
+    if (s == MPS_EDEVICE) ctx->poisoned = true;
+    return s;
+}
+
+extern "C" mps_status mps_log_norm_fidelity(const mps_ctx* ctx, double* out)
+{
+    mps_status s = ctx_check(ctx);
+    if (s != MPS_OK) return s;
+    if (!out) return fail(MPS_EINVAL, "mps_log_norm_fidelity: NULL out");
+    *out = ctx->log_fid;
+    return MPS_OK;
+}
+
+extern "C" mps_status mps_bond_dims(const mps_ctx* ctx, int64_t* dims)
+{
+    mps_status s = ctx_check(ctx);
+    if (s != MPS_OK) return s;
+    if (!dims) return fail(MPS_EINVAL, "mps_bond_dims: NULL out");
+    for (int b = 0; b <= ctx->n; ++b) dims[b] = ctx->dims[b];
+    return MPS_OK;
+}
+
+extern "C" mps_status mps_centre(const mps_ctx* ctx, int32_t* out)
+{
+    mps_status s = ctx_check(ctx);
+    if (s != MPS_OK) return s;
+    if (!out) return fail(MPS_EINVAL, "mps_centre: NULL out");
+    *out = ctx->centre;
+    return MPS_OK;
+}
+
+extern "C" mps_status mps_get_site(mps_ctx* ctx, int32_t j, void* dst, int64_t dst_bytes)
+{
+    mps_status s = ctx_check(ctx);
+    if (s != MPS_OK) return s;
+    if (j < 0 || j >= ctx->n) return fail(MPS_EINVAL, "mps_get_site: site %d out of range", (int)j);
+    const int64_t bytes = ctx->dims[j] * 2 * ctx->dims[j + 1] * elem_bytes(ctx->prec);
+    if (!dst || dst_bytes < bytes) return fail(MPS_EINVAL, "mps_get_site: need %lld bytes", (long long)bytes);
+    HIPCHK(hipMemcpyAsync(dst, ctx->site[j], bytes, hipMemcpyDeviceToDevice, ctx->st), "mps_get_site copy");
+    HIPCHK(hipStreamSynchronize(ctx->st), "mps_get_site sync");
+    return MPS_OK;
+}

@@ -1,0 +1,290 @@
+// Complex GEMM on the gfx950 matrix cores:  C = alpha * op(A) op(B) + beta * C
+//
+// Column-major operands.  op(X) is X or its conjugate transpose X^H.  A complex
+// product is four real MFMAs (v_mfma_f32_16x16x4f32 for complex64 storage,
+// v_mfma_f64_16x16x4f64 for complex128) into separate real / imaginary
+// accumulators.  Each 256-thread workgroup computes a (32*WM) x (32*WN) tile of
+// C with a 2 x 2 arrangement of waves; each wave owns (16*WM) x (16*WN).  The
+// MFMA is fed with the B fragment as its first operand so that the 16 lanes
+// of a lane group hold 16 consecutive *rows* of one C column: the epilogue's
+// stores are then contiguous in column-major memory.  Output register e of
+// lane l holds MFMA row 4*(l/16)+e for the f32 instruction and row l/16+4e for
+// the f64 one (checked on gfx950).
+//
+// An operand can be read as a unit lower-trapezoidal matrix (the stored
+// Householder vectors below a diagonal: entries above the diagonal read as 0,
+// the diagonal as 1) -- the "V" of a block reflector I - V T V^H.
+//
+// Tall-skinny products (small M*N, long K) are split along K into partial
+// products that a second kernel sums in FP64, in a fixed order.
+#pragma once
+#include "common.hpp"
+
+struct GemmArgs {
+    int64_t M, N, K;
+    const void* A;
+    int64_t lda;
+    const void* B;
+    int64_t ldb;
+    void* C;
+    int64_t ldc;
+    double2 alpha, beta;
+    int64_t kchunk;   // split-K: number of K per z-slice (multiple of BK)
+    void* part;       // split-K partial products (z x M x N, ld M), or null
+};
+
+template <typename T> struct MfmaOps;
+template <> struct MfmaOps<float2> {
+    typedef float S;
+    typedef floatx4 Acc;
+    static __device__ __forceinline__ Acc mma(S a, S b, Acc c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // output row of accumulator register e held by this lane
+    static __device__ __forceinline__ int drow(int lane, int e) { return 4 * (lane >> 4) + e; }
+};
+template <> struct MfmaOps<double2> {
+    typedef double S;
+    typedef doublex4 Acc;
+    static __device__ __forceinline__ Acc mma(S a, S b, Acc c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // the f64 variant interleaves its output rows across the 4 registers
+    static __device__ __forceinline__ int drow(int lane, int e) { return (lane >> 4) + 4 * e; }
+};
+
+template <typename T>
+__device__ __forceinline__ T load_masked(const T* base, int64_t ld, int64_t sr, int64_t sc, bool mask)
+{
+    if (mask) {
+        if (sr < sc) { T z; z.x = 0; z.y = 0; return z; }
+        if (sr == sc) { T o; o.x = 1; o.y = 0; return o; }
+    }
+    return base[sr + ld * sc];
+}
+
+#define GEMM_BK 16
+#define GEMM_PAD 1
+
+template <typename T, int WM, int WN, bool CA, bool CB, bool MA, bool MB>
+__global__ __launch_bounds__(256) void k_zgemm(GemmArgs g)
+{
+    typedef typename MfmaOps<T>::S S;
+    typedef typename MfmaOps<T>::Acc Acc;
+    constexpr int BM = 32 * WM, BN = 32 * WN, BK = GEMM_BK;
+    __shared__ S As_re[BK][BM + GEMM_PAD], As_im[BK][BM + GEMM_PAD];
+    __shared__ S Bs_re[BK][BN + GEMM_PAD], Bs_im[BK][BN + GEMM_PAD];
+
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t row0 = (int64_t)blockIdx.x * BM, col0 = (int64_t)blockIdx.y * BN;
+    const int wr = (wid >> 1) * (16 * WM), wc = (wid & 1) * (16 * WN);
+    const T* A = (const T*)g.A;
+    const T* B = (const T*)g.B;
+
+    int64_t kbeg = 0, kend = g.K;
+    if (g.part) {
+        kbeg = (int64_t)blockIdx.z * g.kchunk;
+        kend = kbeg + g.kchunk < g.K ? kbeg + g.kchunk : g.K;
+    }
+
+    Acc acc_re[WM][WN], acc_im[WM][WN];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) { acc_re[i][j][e] = 0; acc_im[i][j][e] = 0; }
+
+    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+        // ---- stage op(A)[row0:row0+BM, k0:k0+BK] ----
+        constexpr int AEL = BM * BK / 256;
+#pragma unroll
+        for (int q = 0; q < AEL; ++q) {
+            int r, kk;
+            if (!CA) { r = (tid + 256 * q) % BM; kk = (tid + 256 * q) / BM; }
+            else     { kk = (tid + 256 * q) % BK; r = (tid + 256 * q) / BK; }
+            const int64_t gr = row0 + r, gk = k0 + kk;
+            S vr = 0, vi = 0;
+            if (gr < g.M && gk < kend) {
+                T v = CA ? load_masked(A, g.lda, gk, gr, MA) : load_masked(A, g.lda, gr, gk, MA);
+                vr = v.x;
+                vi = CA ? -v.y : v.y;
+            }
+            As_re[kk][r] = vr;
+            As_im[kk][r] = vi;
+        }
+        // ---- stage op(B)[k0:k0+BK, col0:col0+BN] ----
+        constexpr int BEL = BN * BK / 256;
+#pragma unroll
+        for (int q = 0; q < BEL; ++q) {
+            int c, kk;
+            if (!CB) { kk = (tid + 256 * q) % BK; c = (tid + 256 * q) / BK; }
+            else     { c = (tid + 256 * q) % BN; kk = (tid + 256 * q) / BN; }
+            const int64_t gc = col0 + c, gk = k0 + kk;
+            S vr = 0, vi = 0;
+            if (gc < g.N && gk < kend) {
+                T v = CB ? load_masked(B, g.ldb, gc, gk, MB) : load_masked(B, g.ldb, gk, gc, MB);
+                vr = v.x;
+                vi = CB ? -v.y : v.y;
+            }
+            Bs_re[kk][c] = vr;
+            Bs_im[kk][c] = vi;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 4) {
+            const int kk = ks + (lane >> 4);
+            S ar[WM], ai[WM], br[WN], bi[WN], nbi[WN];
+#pragma unroll
+            for (int i = 0; i < WM; ++i) {
+                ar[i] = As_re[kk][wr + 16 * i + (lane & 15)];
+                ai[i] = As_im[kk][wr + 16 * i + (lane & 15)];
+            }
+#pragma unroll
+            for (int j = 0; j < WN; ++j) {
+                br[j] = Bs_re[kk][wc + 16 * j + (lane & 15)];
+                bi[j] = Bs_im[kk][wc + 16 * j + (lane & 15)];
+                nbi[j] = -bi[j];
+            }
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WN; ++j) {
+                    acc_re[i][j] = MfmaOps<T>::mma(br[j], ar[i], acc_re[i][j]);
+                    acc_re[i][j] = MfmaOps<T>::mma(nbi[j], ai[i], acc_re[i][j]);
+                    acc_im[i][j] = MfmaOps<T>::mma(bi[j], ar[i], acc_im[i][j]);
+                    acc_im[i][j] = MfmaOps<T>::mma(br[j], ai[i], acc_im[i][j]);
+                }
+        }
+        __syncthreads();
+    }
+
+    // ---- epilogue: lane holds C[row = .. + lane%16][col = .. + drow(lane, e)] ----
+    T* C = (T*)g.C;
+    T* P = (T*)g.part;
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t r = row0 + wr + 16 * i + (lane & 15);
+                const int64_t c = col0 + wc + 16 * j + MfmaOps<T>::drow(lane, e);
+                if (r >= g.M || c >= g.N) continue;
+                double2 v = make_double2((double)acc_re[i][j][e], (double)acc_im[i][j][e]);
+                if (P) {
+                    P[(int64_t)blockIdx.z * g.M * g.N + r + g.M * c] = from_d<T>(v);
+                } else {
+                    v = cmul(g.alpha, v);
+                    if (g.beta.x != 0.0 || g.beta.y != 0.0)
+                        v = cadd(v, cmul(g.beta, to_d(C[r + g.ldc * c])));
+                    C[r + g.ldc * c] = from_d<T>(v);
+                }
+            }
+}
+
+// Sum split-K partial products in a fixed order (FP64) and apply alpha/beta.
+template <typename T>
+__global__ __launch_bounds__(256) void k_splitk_reduce(GemmArgs g, int nz)
+{
+    const int64_t total = g.M * g.N;
+    const T* P = (const T*)g.part;
+    T* C = (T*)g.C;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * 256) {
+        double2 s = czero();
+        for (int z = 0; z < nz; ++z) s = cadd(s, to_d(P[(int64_t)z * total + idx]));
+        const int64_t r = idx % g.M, c = idx / g.M;
+        double2 v = cmul(g.alpha, s);
+        if (g.beta.x != 0.0 || g.beta.y != 0.0) v = cadd(v, cmul(g.beta, to_d(C[r + g.ldc * c])));
+        C[r + g.ldc * c] = from_d<T>(v);
+    }
+}
+
+enum GemmOp { OP_N = 0, OP_C = 1 };
+
+// Bytes of split-K scratch the launcher may need for an M x N product.
+static inline int64_t gemm_splitk_bytes(int64_t M, int64_t N, int64_t K, int64_t elem)
+{
+    (void)K;
+    return 16 * M * N * elem;   // at most 16 slices
+}
+
+template <typename T, int WM, int WN, bool CA, bool CB, bool MA, bool MB>
+static void launch_gemm_cfg(GemmArgs g, hipStream_t st, int nz)
+{
+    constexpr int BM = 32 * WM, BN = 32 * WN;
+    dim3 grid((unsigned)((g.M + BM - 1) / BM), (unsigned)((g.N + BN - 1) / BN), (unsigned)nz);
+    hipLaunchKernelGGL((k_zgemm<T, WM, WN, CA, CB, MA, MB>), grid, dim3(256), 0, st, g);
+}
+
+// Tile shapes per storage type: complex64 uses 128 x 128 tiles for large
+// products; complex128 uses 128 x 64 (its LDS staging is twice as large).
+template <typename T> struct GemmTile;
+template <> struct GemmTile<float2> { static constexpr int WM = 4, WN = 4; };
+template <> struct GemmTile<double2> { static constexpr int WM = 4, WN = 2; };
+
+template <typename T, bool CA, bool CB, bool MA, bool MB>
+static void launch_gemm_t(GemmArgs g, hipStream_t st, void* scratch, int64_t scratch_bytes)
+{
+    if (g.M <= 0 || g.N <= 0) return;
+    constexpr int BWM = GemmTile<T>::WM, BWN = GemmTile<T>::WN;
+    const bool big = g.M >= 512 && g.N >= 512;
+    const int64_t BM = big ? 32 * BWM : 64, BN = big ? 32 * BWN : 64;
+    const int64_t tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
+    int nz = 1;
+    if (g.K > 0 && tiles < 256 && g.K >= 512 && scratch) {
+        int64_t want = 512 / tiles;
+        int64_t maxz = g.K / 256;
+        nz = (int)(want < maxz ? want : maxz);
+        if (nz > 16) nz = 16;
+        if (nz < 1) nz = 1;
+        if ((int64_t)nz * g.M * g.N * (int64_t)sizeof(T) > scratch_bytes) nz = 1;
+    }
+    if (nz > 1) {
+        int64_t chunk = (g.K + nz - 1) / nz;
+        chunk = (chunk + GEMM_BK - 1) / GEMM_BK * GEMM_BK;
+        nz = (int)((g.K + chunk - 1) / chunk);
+        g.kchunk = chunk;
+        g.part = scratch;
+    } else {
+        g.part = nullptr;
+        g.kchunk = g.K;
+    }
+    if (big) launch_gemm_cfg<T, BWM, BWN, CA, CB, MA, MB>(g, st, nz);
+    else     launch_gemm_cfg<T, 2, 2, CA, CB, MA, MB>(g, st, nz);
+    if (g.part) {
+        int64_t total = g.M * g.N;
+        int64_t blocks = (total + 255) / 256;
+        if (blocks > 4096) blocks = 4096;
+        hipLaunchKernelGGL((k_splitk_reduce<T>), dim3((unsigned)blocks), dim3(256), 0, st, g, nz);
+    }
+}
+
+// Runtime dispatch over the operand forms used by the library.  Returns false
+// for a combination that has no instantiation.
+template <typename T>
+static bool zgemm(hipStream_t st, GemmOp opa, bool maska, GemmOp opb, bool maskb,
+                  int64_t M, int64_t N, int64_t K, double2 alpha,
+                  const T* A, int64_t lda, const T* B, int64_t ldb, double2 beta, T* C, int64_t ldc,
+                  void* scratch, int64_t scratch_bytes)
+{
+    GemmArgs g;
+    g.M = M; g.N = N; g.K = K;
+    g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+    g.alpha = alpha; g.beta = beta;
+    g.kchunk = K; g.part = nullptr;
+    const int key = (opa == OP_C ? 8 : 0) | (opb == OP_C ? 4 : 0) | (maska ? 2 : 0) | (maskb ? 1 : 0);
+    switch (key) {
+    case 0:  launch_gemm_t<T, false, false, false, false>(g, st, scratch, scratch_bytes); return true;
+    case 4:  launch_gemm_t<T, false, true, false, false>(g, st, scratch, scratch_bytes); return true;
+    case 8:  launch_gemm_t<T, true, false, false, false>(g, st, scratch, scratch_bytes); return true;
+    case 2:  launch_gemm_t<T, false, false, true, false>(g, st, scratch, scratch_bytes); return true;
+    case 10: launch_gemm_t<T, true, false, true, false>(g, st, scratch, scratch_bytes); return true;
+    case 11: launch_gemm_t<T, true, false, true, true>(g, st, scratch, scratch_bytes); return true;
+    case 12: launch_gemm_t<T, true, true, false, false>(g, st, scratch, scratch_bytes); return true;
+    default: return false;
+    }
+}

@@ -1,0 +1,333 @@
+// The two-site update (paper Sec. III-C.2 "tensor application" for a gate on
+// neighbouring sites, with the truncated pivoted-QR decomposition of Table III):
+//
+//   a1  theta0 = A_i A_{i+1}                       (MFMA GEMM)
+//   a2  theta  = G applied to the physical indices  (fused with a3)
+//   a3  FP64 column norms of theta, ||theta||_F^2
+//   a4-a9  pivoted QR with delayed panel updates   (qrcp.hpp + MFMA GEMM)
+//   a10 eps^2 = ||R22||_F^2 from the final trailing block
+//   a11 Q_k = H_0 ... H_{k-1} [I; 0] by blocked backward accumulation
+//   a12 split: A_i' = Q_k, A_{i+1}' = R_k P^T (scaled)
+//
+// Site storage: A[l, s, r] at l + chi_l*(s + 2r) (column-major in (l, s, r)).
+// Site i is then a column-major (2 chi_l) x chi_m matrix with row l + chi_l*s,
+// site i+1 a column-major chi_m x (2 chi_r) matrix with column s + 2r, and
+// theta is column-major (2 chi_l) x (2 chi_r); Q_k is the new site i and
+// R_k P^T the new site i+1 without any transposition.
+#pragma once
+#include <vector>
+#include "gemm.hpp"
+#include "qrcp.hpp"
+
+struct Gate4 {
+    double2 g[16];   // row-major: g[4*(2a'+b') + (2a+b)]
+};
+
+// a2 + a3: apply the gate in place to column pair (b=0,b=1) of bond index r
+// and row pair (a=0,a=1) of each l; FP64 norms of the two columns.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gate_norms(QrcpDev<T> d, int64_t chi_l, Gate4 G)
+{
+    __shared__ double red_lds[4 * 2];
+    __shared__ double red_out[2];
+    __shared__ ArgBest arg_lds[4];
+    const int64_t r = blockIdx.x;
+    const int64_t c0 = 2 * r, c1 = 2 * r + 1;
+    double n0 = 0.0, n1 = 0.0;
+    for (int64_t l = threadIdx.x; l < chi_l; l += 256) {
+        double2 t[4];
+        t[0] = to_d(d.A[l + d.lda * c0]);            // a=0, b=0
+        t[1] = to_d(d.A[l + d.lda * c1]);            // a=0, b=1
+        t[2] = to_d(d.A[l + chi_l + d.lda * c0]);    // a=1, b=0
+        t[3] = to_d(d.A[l + chi_l + d.lda * c1]);    // a=1, b=1
+        double2 o[4];
+#pragma unroll
+        for (int row = 0; row < 4; ++row) {
+            double2 s = czero();
+#pragma unroll
+            for (int col = 0; col < 4; ++col) s = cadd(s, cmul(G.g[4 * row + col], t[col]));
+            o[row] = s;
+        }
+        T o0 = from_d<T>(o[0]), o1 = from_d<T>(o[1]), o2 = from_d<T>(o[2]), o3 = from_d<T>(o[3]);
+        d.A[l + d.lda * c0] = o0;
+        d.A[l + d.lda * c1] = o1;
+        d.A[l + chi_l + d.lda * c0] = o2;
+        d.A[l + chi_l + d.lda * c1] = o3;
+        n0 += cabs2(to_d(o0)) + cabs2(to_d(o2));
+        n1 += cabs2(to_d(o1)) + cabs2(to_d(o3));
+    }
+    double v[2] = {n0, n1};
+    block_sum_vec<2>(v, red_lds, red_out);
+    ArgBest best;
+    best.val = -1.0;
+    best.key = 0x7fffffff;
+    best.slot = -1;
+    if (threadIdx.x < 2) {
+        const int64_t c = c0 + threadIdx.x;
+        d.nu[c] = red_out[threadIdx.x];
+        d.nuref[c] = red_out[threadIdx.x];
+        d.perm[c] = (int32_t)c;
+        best.val = red_out[threadIdx.x];
+        best.key = (int32_t)c;
+        best.slot = (int32_t)c;
+    }
+    best = block_argmax256(best, arg_lds);
+    if (threadIdx.x == 0) {
+        d.cpart[r] = best;
+        d.npart[r] = red_out[0] + red_out[1];
+    }
+}
+
+// a12: RPt[:, perm[c]] = column c of R (rows < k; R[t,c] = 0 for t > c),
+// times the scale 1/sqrt(||theta||^2 - eps^2) when renormalising.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rpt(const T* A, int64_t lda, const int32_t* perm, int64_t k, int64_t n,
+                                             T* out, int64_t ldo, const double* dsc, int renorm)
+{
+    const int64_t c = blockIdx.x;
+    if (c >= n) return;
+    double s = 1.0;
+    if (renorm) {
+        const double kept = dsc[DSC_NORM2] - dsc[DSC_EPS2];
+        s = kept > 0.0 ? 1.0 / sqrt(kept) : 1.0;
+    }
+    const int64_t oc = perm[c];
+    for (int64_t t = threadIdx.x; t < k; t += 256) {
+        double2 v = t <= c ? to_d(A[t + lda * c]) : czero();
+        out[t + ldo * oc] = from_d<T>(cscale(v, s));
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_eye(T* Q, int64_t ldq, int64_t m, int64_t k)
+{
+    const int64_t c = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256) {
+        T v;
+        v.x = (i == c) ? 1 : 0;
+        v.y = 0;
+        Q[i + ldq * c] = v;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy_cols(const T* src, int64_t lds, T* dst, int64_t ldd, int64_t m)
+{
+    const int64_t c = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256)
+        dst[i + ldd * c] = src[i + lds * c];
+}
+
+#define UNGQR_NB 32
+
+// T factor of a block reflector (forward, columnwise): H_0..H_{nb-1} = I - V T V^H
+// with T[t,t] = tau_t and T[0:t, t] = -tau_t T[0:t, 0:t] (V^H V)[0:t, t].
+// One block of 64 threads; G = V^H V (nb x nb, ld UNGQR_NB) from a GEMM.
+template <typename T>
+__global__ __launch_bounds__(64) void k_larft(const T* G, const double2* tau, int nb, T* Tout)
+{
+    __shared__ double2 Ts[UNGQR_NB][UNGQR_NB + 1];
+    __shared__ double2 Gs[UNGQR_NB][UNGQR_NB + 1];
+    const int s = threadIdx.x;
+    for (int q = s; q < UNGQR_NB * UNGQR_NB; q += 64) {
+        const int r = q % UNGQR_NB, c = q / UNGQR_NB;
+        Gs[r][c] = (r < nb && c < nb) ? to_d(G[r + UNGQR_NB * c]) : czero();
+        Ts[r][c] = czero();
+    }
+    __syncthreads();
+    for (int t = 0; t < nb; ++t) {
+        const double2 tt = tau[t];
+        double2 v = czero();
+        if (s < t) {
+            for (int u = s; u < t; ++u) v = cadd(v, cmul(Ts[s][u], Gs[u][t]));
+            v = cscale(cmul(tt, v), -1.0);
+        }
+        __syncthreads();
+        if (s < t) Ts[s][t] = v;
+        if (s == t) Ts[s][t] = tt;
+        __syncthreads();
+    }
+    for (int q = s; q < UNGQR_NB * UNGQR_NB; q += 64) {
+        const int r = q % UNGQR_NB, c = q / UNGQR_NB;
+        Tout[r + UNGQR_NB * c] = from_d<T>(Ts[r][c]);
+    }
+}
+
+// Scratch carved from a caller-provided workspace.
+struct Carver {
+    char* base;
+    int64_t cap, used;
+    void* take(int64_t bytes)
+    {
+        int64_t off = (used + 255) & ~(int64_t)255;
+        if (bytes < 0 || off + bytes > cap) return nullptr;
+        used = off + bytes;
+        return base ? (void*)(base + off) : (void*)(intptr_t)(off + 256);
+    }
+};
+
+template <typename T>
+struct UpdateWs {
+    QrcpDev<T> d;
+    T* Gbuf;       // UNGQR_NB^2
+    T* Tbuf;       // UNGQR_NB^2
+    T* Wbuf;       // UNGQR_NB x k
+    T* W2buf;      // UNGQR_NB x k
+    void* gsplit;  // split-K scratch
+    int64_t gsplit_bytes;
+    int nb;        // QRCP panel width
+};
+
+static inline int64_t rup(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Lay out the workspace of one factorisation of an m x n matrix with k steps.
+// theta_in_ws: whether theta itself lives in the workspace.  With base == null
+// only sizes are computed; returns false when cap is too small.
+template <typename T>
+static bool carve_update_ws(Carver& cv, UpdateWs<T>& w, int64_t m, int64_t n, int64_t k, bool theta_in_ws)
+{
+    QrcpDev<T>& d = w.d;
+    d.m = m; d.n = n; d.k = k; d.lda = m > 1 ? m : 1;
+    d.A = theta_in_ws ? (T*)cv.take((int64_t)sizeof(T) * m * n) : nullptr;
+    d.nu = (double*)cv.take(8 * (n + 1));
+    d.nuref = (double*)cv.take(8 * (n + 1));
+    d.perm = (int32_t*)cv.take(4 * (n + 1));
+    d.ldf = n > 1 ? n : 1;
+    d.F = (T*)cv.take((int64_t)sizeof(T) * d.ldf * QR_NBMAX);
+    d.tau = (double2*)cv.take(16 * (k + 1));
+    d.diagR = (double*)cv.take(8 * (k + 1));
+    d.xbuf = (double2*)cv.take(16 * (m + 1));
+    d.apart = (double*)cv.take(8 * APART_STRIDE * (rup(m, 256) + 1));
+    d.hh = (double2*)cv.take(16 * (4 + QR_NBMAX));
+    d.fsave = (double2*)cv.take(16 * QR_NBMAX);
+    const int64_t np = rup(n, QR_CW) + rup(n, 2) + 8;
+    d.cpart = (ArgBest*)cv.take((int64_t)sizeof(ArgBest) * np);
+    d.npart = (double*)cv.take(8 * np);
+    d.ctl = (int32_t*)cv.take(4 * CTL_COUNT);
+    d.dsc = (double*)cv.take(8 * DSC_COUNT);
+    w.Gbuf = (T*)cv.take((int64_t)sizeof(T) * UNGQR_NB * UNGQR_NB);
+    w.Tbuf = (T*)cv.take((int64_t)sizeof(T) * UNGQR_NB * UNGQR_NB);
+    w.Wbuf = (T*)cv.take((int64_t)sizeof(T) * UNGQR_NB * (k + 1));
+    w.W2buf = (T*)cv.take((int64_t)sizeof(T) * UNGQR_NB * (k + 1));
+    const int64_t sk = (int64_t)sizeof(T) * 16 * UNGQR_NB * (k > UNGQR_NB ? k : UNGQR_NB);
+    w.gsplit = cv.take(sk);
+    w.gsplit_bytes = sk;
+    return d.nu && d.nuref && d.perm && d.F && d.tau && d.diagR && d.xbuf && d.apart && d.hh && d.fsave &&
+           d.cpart && d.npart && d.ctl && d.dsc && w.Gbuf && w.Tbuf && w.Wbuf && w.W2buf && w.gsplit &&
+           (!theta_in_ws || d.A);
+}
+
+static const double2 C_ONE = {1.0, 0.0};
+static const double2 C_MONE = {-1.0, 0.0};
+static const double2 C_ZERO = {0.0, 0.0};
+
+struct QrcpStats {
+    int panels = 0;
+    int refreshes = 0;
+};
+
+// a4-a10 on d.A; expects nu/nuref/perm/ctl[PIV] set up (pivoting) and the
+// control block reset.  Synchronises the stream once per panel.
+template <typename T>
+static hipError_t run_qrcp(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats)
+{
+    QrcpDev<T>& d = w.d;
+    const int64_t m = d.m, n = d.n, k = d.k;
+    const int nb = w.nb;
+    const unsigned na = (unsigned)rup(m, 256);
+    int64_t j = 0;
+    while (j < k) {
+        const int64_t p0 = j;
+        const int64_t pend = (p0 + nb < k) ? p0 + nb : k;
+        hipLaunchKernelGGL(k_ctl_panel, dim3(1), dim3(64), 0, st, d.ctl, (int32_t)p0);
+        for (int64_t jc = p0; jc < pend; ++jc) {
+            const int jj = (int)(jc - p0);
+            hipLaunchKernelGGL((k_step_a<T>), dim3(na), dim3(256), 0, st, d, jc, p0, jj);
+            int64_t ncol = n - jc - 1;
+            unsigned nc = (unsigned)(ncol > 0 ? rup(ncol, QR_CW) : 1);
+            hipLaunchKernelGGL((k_step_c<T>), dim3(nc), dim3(256), 0, st, d, jc, p0, jj, n);
+        }
+        int32_t hctl[CTL_COUNT];
+        hipError_t e = hipMemcpyAsync(hctl, d.ctl, sizeof(hctl), hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) return e;
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return e;
+        const int64_t jend = hctl[CTL_JDONE];
+        if (jend <= p0 || jend > pend) return hipErrorUnknown;   // no progress: corrupt state
+        const int64_t nbe = jend - p0;
+        // trailing update A[jend:, jend:] -= V[jend:, p0:jend] F[jend:, 0:nbe]^H
+        if (m > jend && n > jend) {
+            if (!zgemm<T>(st, OP_N, false, OP_C, false, m - jend, n - jend, nbe, C_MONE,
+                          d.A + jend + d.lda * p0, d.lda, d.F + jend, d.ldf, C_ONE,
+                          d.A + jend + d.lda * jend, d.lda, nullptr, 0))
+                return hipErrorInvalidValue;
+        }
+        if (stats) stats->panels++;
+        if (hctl[CTL_STOP] && jend < k && d.pivoting) {
+            const unsigned nblk = (unsigned)rup(n - jend, QR_CW);
+            hipLaunchKernelGGL((k_colnorms<T>), dim3(nblk), dim3(256), 0, st, d, jend, jend, 1, 0);
+            hipLaunchKernelGGL((k_partials_final<T>), dim3(1), dim3(256), 0, st, d, (int)nblk, 1, -1, jend);
+            if (stats) stats->refreshes++;
+        }
+        j = jend;
+    }
+    // a10: ||R22||_F^2 over the final trailing block
+    if (m > k && n > k) {
+        const unsigned nblk = (unsigned)rup(n - k, QR_CW);
+        hipLaunchKernelGGL((k_colnorms<T>), dim3(nblk), dim3(256), 0, st, d, k, k, 0, 0);
+        hipLaunchKernelGGL((k_partials_final<T>), dim3(1), dim3(256), 0, st, d, (int)nblk, 0, (int)DSC_EPS2,
+                           (int64_t)0);
+    }
+    return hipGetLastError();
+}
+
+// a11: Q (m x k, ldq) = H_0 ... H_{k-1} [I_k; 0] from the reflectors stored in
+// d.A below the diagonal, by blocks of UNGQR_NB from the last block backwards.
+template <typename T>
+static hipError_t form_q(UpdateWs<T>& w, T* Q, int64_t ldq, hipStream_t st)
+{
+    QrcpDev<T>& d = w.d;
+    const int64_t m = d.m, k = d.k;
+    if (k <= 0) return hipSuccess;
+    {
+        dim3 grid((unsigned)(rup(m, 256) < 64 ? rup(m, 256) : 64), (unsigned)k);
+        hipLaunchKernelGGL((k_eye<T>), grid, dim3(256), 0, st, Q, ldq, m, k);
+    }
+    const int64_t last = ((k - 1) / UNGQR_NB) * UNGQR_NB;
+    for (int64_t b0 = last; b0 >= 0; b0 -= UNGQR_NB) {
+        const int nbe = (int)((k - b0) < UNGQR_NB ? (k - b0) : UNGQR_NB);
+        const T* V = d.A + b0 + d.lda * b0;
+        const int64_t rows = m - b0, cols = k - b0;
+        // G = V^H V
+        if (!zgemm<T>(st, OP_C, true, OP_N, true, nbe, nbe, rows, C_ONE, V, d.lda, V, d.lda, C_ZERO, w.Gbuf,
+                      UNGQR_NB, w.gsplit, w.gsplit_bytes))
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_larft<T>), dim3(1), dim3(64), 0, st, w.Gbuf, d.tau + b0, nbe, w.Tbuf);
+        // W = V^H Q[b0:, b0:k]
+        if (!zgemm<T>(st, OP_C, true, OP_N, false, nbe, cols, rows, C_ONE, V, d.lda, Q + b0 + ldq * b0, ldq,
+                      C_ZERO, w.Wbuf, UNGQR_NB, w.gsplit, w.gsplit_bytes))
+            return hipErrorInvalidValue;
+        // W2 = T W
+        if (!zgemm<T>(st, OP_N, false, OP_N, false, nbe, cols, nbe, C_ONE, w.Tbuf, UNGQR_NB, w.Wbuf, UNGQR_NB,
+                      C_ZERO, w.W2buf, UNGQR_NB, nullptr, 0))
+            return hipErrorInvalidValue;
+        // Q[b0:, b0:k] -= V W2
+        if (!zgemm<T>(st, OP_N, true, OP_N, false, rows, cols, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, C_ONE,
+                      Q + b0 + ldq * b0, ldq, nullptr, 0))
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Norms, perm and first pivot of a matrix already in d.A (no gate).
+template <typename T>
+static void init_norms(UpdateWs<T>& w, hipStream_t st)
+{
+    QrcpDev<T>& d = w.d;
+    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, st, d.ctl, d.dsc);
+    if (d.n <= 0) return;
+    const unsigned nblk = (unsigned)rup(d.n, QR_CW);
+    hipLaunchKernelGGL((k_colnorms<T>), dim3(nblk), dim3(256), 0, st, d, (int64_t)0, (int64_t)0, 1, 1);
+    hipLaunchKernelGGL((k_partials_final<T>), dim3(1), dim3(256), 0, st, d, (int)nblk, 1, (int)DSC_NORM2,
+                       (int64_t)0);
+}

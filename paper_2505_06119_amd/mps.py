@@ -1,0 +1,304 @@
+"""ctypes binding of libmpsgpu.so (declared in include/mps_abi.h).
+
+Argument marshalling only: every step of the update runs in the library's HIP
+kernels.  PyTorch supplies device memory (tensors, the context arena, the
+workspace) and the stream (``torch.cuda.current_stream()``).
+
+Layouts on the device
+* a matrix is column-major: a torch tensor ``M`` of shape (rows, cols) with
+  strides (1, rows) -- see :func:`colmajor`;
+* a site tensor A[l, s, r] lives at l + chi_l*(s + 2r): a contiguous torch
+  tensor of shape (chi_r, 2, chi_l) -- see :func:`site_to_device`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpsgpu.so")
+
+MPS_FP64, MPS_MIXED = 0, 1
+MPS_PIVOT_QRCP, MPS_PIVOT_LEARNED = 0, 1
+STATUS = {0: "MPS_OK", 1: "MPS_EINVAL", 2: "MPS_ENOMEM", 3: "MPS_EDEVICE", 4: "MPS_ENUMERIC", 5: "MPS_ESTATE"}
+
+
+class MpsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class UpdateInfo(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int64), ("trunc_err_sq", ctypes.c_double), ("norm_sq", ctypes.c_double),
+                ("retained", ctypes.c_double), ("fallback", ctypes.c_int32), ("panels", ctypes.c_int32),
+                ("refreshes", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("n_sites", ctypes.c_int32), ("chi_max", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("pivot", ctypes.c_int32), ("fallback_ratio", ctypes.c_double), ("sketch_rows", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libmpsgpu.so; raises when it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2505_06119_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    p, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    pd, pi64 = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)
+    L.mps_last_error.restype = ctypes.c_char_p
+    L.mps_last_error.argtypes = []
+    L.qrcp_work_bytes.restype = i64
+    L.qrcp_work_bytes.argtypes = [i64, i64, i64, i32]
+    L.qrcp_truncate.restype = i32
+    L.qrcp_truncate.argtypes = [i64, i64, i64, i32, p, i64, p, i64, p, i64, p, p, pi64, pd, pd, p, i64, p]
+    L.mps_update_work_bytes.restype = i64
+    L.mps_update_work_bytes.argtypes = [i64, i64, i64, i64, i32, i32]
+    L.mps_update_bond.restype = i32
+    L.mps_update_bond.argtypes = [i64, i64, i64, i64, i32, i32, p, p, pd, p, p, ctypes.c_int,
+                                  ctypes.POINTER(UpdateInfo), p, i64, p]
+    L.mps_arena_bytes.restype = i64
+    L.mps_arena_bytes.argtypes = [ctypes.POINTER(Config)]
+    L.mps_create.restype = i32
+    L.mps_create.argtypes = [ctypes.POINTER(Config), p, i64, p, ctypes.POINTER(p)]
+    L.mps_destroy.restype = i32
+    L.mps_destroy.argtypes = [p]
+    L.mps_apply_gate.restype = i32
+    L.mps_apply_gate.argtypes = [p, i32, pd, ctypes.POINTER(UpdateInfo)]
+    L.mps_apply_layer.restype = i32
+    L.mps_apply_layer.argtypes = [p, i64, ctypes.POINTER(ctypes.c_int32), pd, ctypes.POINTER(UpdateInfo)]
+    L.mps_amplitude.restype = i32
+    L.mps_amplitude.argtypes = [p, ctypes.POINTER(ctypes.c_uint8), pd]
+    L.mps_log_norm_fidelity.restype = i32
+    L.mps_log_norm_fidelity.argtypes = [p, pd]
+    L.mps_bond_dims.restype = i32
+    L.mps_bond_dims.argtypes = [p, pi64]
+    L.mps_centre.restype = i32
+    L.mps_centre.argtypes = [p, ctypes.POINTER(ctypes.c_int32)]
+    L.mps_get_site.restype = i32
+    L.mps_get_site.argtypes = [p, i32, p, i64]
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != 0:
+        raise MpsError(status, lib().mps_last_error().decode())
+
+
+def last_error() -> str:
+    return lib().mps_last_error().decode()
+
+
+# --- device helpers ----------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def cdtype(prec: int):
+    torch = _torch()
+    return torch.complex128 if prec == MPS_FP64 else torch.complex64
+
+
+def np_cdtype(prec: int):
+    return np.complex128 if prec == MPS_FP64 else np.complex64
+
+
+def stream_ptr():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def colmajor(a: np.ndarray, prec: int, device="cuda"):
+    """Upload a (rows, cols) matrix as a column-major device tensor."""
+    torch = _torch()
+    t = torch.from_numpy(np.ascontiguousarray(np.asarray(a).T.astype(np_cdtype(prec))))
+    return t.to(device).t()
+
+
+def empty_colmajor(rows: int, cols: int, prec: int, device="cuda"):
+    torch = _torch()
+    return torch.empty((cols, rows), dtype=cdtype(prec), device=device).t()
+
+
+def site_to_device(a: np.ndarray, prec: int, device="cuda"):
+    """Site [l, s, r] (numpy) -> contiguous device tensor of shape (chi_r, 2, chi_l)."""
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a).transpose(2, 1, 0).astype(np_cdtype(prec)))).to(device)
+
+
+def site_from_device(t, chi_l: int, chi_r: int) -> np.ndarray:
+    """Inverse of site_to_device; returns complex128 [l, s, r]."""
+    arr = t.reshape(-1)[: chi_l * 2 * chi_r].reshape(chi_r, 2, chi_l).cpu().numpy()
+    return np.ascontiguousarray(arr.transpose(2, 1, 0)).astype(np.complex128)
+
+
+def gate_buffer(g: np.ndarray):
+    g = np.ascontiguousarray(np.asarray(g, dtype=np.complex128).reshape(4, 4))
+    buf = np.ascontiguousarray(g.view(np.float64).reshape(-1))
+    return buf, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# --- stateless calls -------------------------------------------------------------------
+
+def qrcp_work_bytes(m: int, n: int, k_max: int, prec: int) -> int:
+    return int(lib().qrcp_work_bytes(m, n, k_max, prec))
+
+
+def qrcp_truncate(A, k_max: int, prec: int, work=None, stream=None) -> dict:
+    """Pivoted QR of the column-major device matrix A (m x n), k = min(k_max, m, n)."""
+    torch = _torch()
+    m, n = A.shape
+    k = max(0, min(k_max, m, n))
+    lda = A.stride(1) if n > 1 else max(m, 1)
+    if A.stride(0) != 1:
+        raise ValueError("A must be column-major (stride (1, lda))")
+    Q = empty_colmajor(m, k, prec)
+    R = empty_colmajor(k, n, prec)
+    piv = torch.empty(n, dtype=torch.int32, device=A.device)
+    diag = torch.empty(max(k, 1), dtype=torch.float64, device=A.device)
+    wb = qrcp_work_bytes(m, n, k_max, prec)
+    if work is None:
+        work = torch.empty(max(wb, 1), dtype=torch.uint8, device=A.device)
+    kout = ctypes.c_int64(0)
+    err = ctypes.c_double(0)
+    afro = ctypes.c_double(0)
+    _check(lib().qrcp_truncate(m, n, k_max, prec, _ptr(A), lda, _ptr(Q), m, _ptr(R), max(k, 1), _ptr(piv),
+                               _ptr(diag), ctypes.byref(kout), ctypes.byref(err), ctypes.byref(afro), _ptr(work),
+                               work.numel(), stream if stream is not None else stream_ptr()))
+    return {"Q": Q, "RPt": R, "piv": piv, "diagR": diag[:k], "k": int(kout.value), "err": float(err.value),
+            "a_fro": float(afro.value)}
+
+
+def mps_update_work_bytes(chi_l, chi_m, chi_r, chi_cap, prec, pivot=MPS_PIVOT_QRCP) -> int:
+    return int(lib().mps_update_work_bytes(chi_l, chi_m, chi_r, chi_cap, prec, pivot))
+
+
+def mps_update_bond(A, B, g, chi_l, chi_m, chi_r, chi_cap, prec, renormalize=True, A_out=None, B_out=None,
+                    work=None, pivot=MPS_PIVOT_QRCP, stream=None, info=None) -> dict:
+    """Two-site update on device sites A (chi_l x 2 x chi_m) and B (chi_m x 2 x chi_r)."""
+    torch = _torch()
+    k = min(chi_cap, 2 * chi_l, 2 * chi_r)
+    if A_out is None:
+        A_out = torch.empty((k, 2, chi_l), dtype=cdtype(prec), device=A.device)
+    if B_out is None:
+        B_out = torch.empty((chi_r, 2, k), dtype=cdtype(prec), device=A.device)
+    if work is None:
+        wb = mps_update_work_bytes(chi_l, chi_m, chi_r, chi_cap, prec, pivot)
+        work = torch.empty(max(wb, 1), dtype=torch.uint8, device=A.device)
+    gbuf, gp = gate_buffer(g)
+    if info is None:
+        info = UpdateInfo()
+    _check(lib().mps_update_bond(chi_l, chi_m, chi_r, chi_cap, prec, pivot, _ptr(A), _ptr(B), gp, _ptr(A_out),
+                                 _ptr(B_out), 1 if renormalize else 0, ctypes.byref(info), _ptr(work), work.numel(),
+                                 stream if stream is not None else stream_ptr()))
+    del gbuf
+    return {"A": A_out, "B": B_out, "info": info.as_dict(), "k": int(info.k)}
+
+
+# --- stateful MPS ------------------------------------------------------------------------
+
+class MPS:
+    """An MPS held by the library (mps_create ... mps_destroy)."""
+
+    def __init__(self, n_sites: int, chi_max: int, prec: int = MPS_FP64, pivot: int = MPS_PIVOT_QRCP,
+                 device="cuda"):
+        torch = _torch()
+        self.cfg = Config(n_sites, chi_max, prec, pivot, 1.01, 64, 0, 0)
+        nbytes = int(lib().mps_arena_bytes(ctypes.byref(self.cfg)))
+        if nbytes < 0:
+            raise MpsError(1, "invalid configuration")
+        self.arena = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = torch.cuda.current_stream()
+        self._h = ctypes.c_void_p()
+        _check(lib().mps_create(ctypes.byref(self.cfg), _ptr(self.arena), nbytes,
+                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._h)))
+        self.n = n_sites
+        self.prec = prec
+
+    def close(self):
+        if self._h:
+            lib().mps_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply_gate(self, i: int, g) -> dict:
+        info = UpdateInfo()
+        gbuf, gp = gate_buffer(g)
+        _check(lib().mps_apply_gate(self._h, i, gp, ctypes.byref(info)))
+        del gbuf
+        return info.as_dict()
+
+    def apply_layer(self, layer) -> list:
+        n = len(layer)
+        idx = (ctypes.c_int32 * max(n, 1))(*[int(i) for i, _ in layer])
+        gs = np.ascontiguousarray(np.stack([np.asarray(g, dtype=np.complex128).reshape(4, 4) for _, g in layer])
+                                  if n else np.zeros((1, 4, 4), np.complex128))
+        gflat = np.ascontiguousarray(gs.view(np.float64).reshape(-1))
+        infos = (UpdateInfo * max(n, 1))()
+        _check(lib().mps_apply_layer(self._h, n, idx, gflat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     infos))
+        return [infos[t].as_dict() for t in range(n)]
+
+    def apply_layers(self, layers):
+        out = []
+        for layer in layers:
+            out += self.apply_layer(sorted(layer, key=lambda ig: ig[0]))
+        return out
+
+    def amplitude(self, bits) -> complex:
+        b = (ctypes.c_uint8 * self.n)(*[int(x) for x in bits])
+        out = (ctypes.c_double * 2)()
+        _check(lib().mps_amplitude(self._h, b, out))
+        return complex(out[0], out[1])
+
+    def log_norm_fidelity(self) -> float:
+        v = ctypes.c_double(0)
+        _check(lib().mps_log_norm_fidelity(self._h, ctypes.byref(v)))
+        return float(v.value)
+
+    def bond_dims(self) -> list:
+        dims = (ctypes.c_int64 * (self.n + 1))()
+        _check(lib().mps_bond_dims(self._h, dims))
+        return [int(x) for x in dims]
+
+    def centre(self) -> int:
+        v = ctypes.c_int32(0)
+        _check(lib().mps_centre(self._h, ctypes.byref(v)))
+        return int(v.value)
+
+    def site(self, j: int) -> np.ndarray:
+        """Site j as a complex128 numpy array [l, s, r] (normalised state)."""
+        torch = _torch()
+        dims = self.bond_dims()
+        chl, chr_ = dims[j], dims[j + 1]
+        t = torch.empty((chr_, 2, chl), dtype=cdtype(self.prec), device=self.arena.device)
+        _check(lib().mps_get_site(self._h, j, _ptr(t), t.numel() * t.element_size()))
+        return site_from_device(t, chl, chr_)
+
+    def sites(self) -> list:
+        return [self.site(j) for j in range(self.n)]

@@ -1,0 +1,131 @@
+"""GPU parity of the stateful MPS (mps_apply_gate / mps_apply_layer /
+mps_amplitude) against brute-force statevectors and the FP64 oracle MPS."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2505_06119_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-10, 1: 1e-4}
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2505_06119_amd import mps
+    return mps
+
+
+def _bits(x, n):
+    return [(x >> (n - 1 - j)) & 1 for j in range(n)]
+
+
+def _gpu_statevector(st):
+    return oracle.statevector(st.sites()) * np.sqrt(np.exp(st.log_norm_fidelity()))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_brickwork_exact_vs_statevector(M, prec):
+    """12 qubits, brickwork depth 10, 55 Haar gates, chi cap 64: exact."""
+    print(f"case brickwork exact prec={prec}", flush=True)
+    n = 12
+    layers = synth.brickwork(synth.rng(100), n, 10)
+    st = M.MPS(n, 64, prec)
+    st.apply_layers(layers)
+    ref = oracle.brute_force(n, layers)
+    tol = TOL[prec]
+    sv = _gpu_statevector(st)
+    assert np.max(np.abs(sv - ref)) <= tol * np.max(np.abs(ref)) * 10
+    assert abs(st.log_norm_fidelity()) <= tol * 10
+    for x in synth.rng(101).integers(0, 2 ** n, size=12):
+        amp = st.amplitude(_bits(int(x), n))
+        assert abs(amp - ref[int(x)]) <= tol * np.max(np.abs(ref)) * 10
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_brickwork_truncated_vs_oracle(M, prec):
+    """Same circuit at chi cap 32: truncating; compare with the oracle MPS."""
+    print(f"case brickwork truncated prec={prec}", flush=True)
+    n = 12
+    layers = synth.brickwork(synth.rng(100), n, 10)
+    st = M.MPS(n, 32, prec)
+    infos = st.apply_layers(layers)
+    om = oracle.MPS(synth.product_state_sites(n), chi_cap=32)
+    om.apply_layers(layers)
+    fbar_o = oracle.norm_fidelity(om.sites)
+    fbar_g = np.exp(st.log_norm_fidelity())
+    tol = TOL[prec]
+    assert fbar_o < 0.999
+    assert abs(fbar_g - fbar_o) <= tol * 10 * fbar_o
+    assert st.bond_dims() == [1] + om.bond_dims() + [1]
+    sv_o = oracle.statevector(om.sites)
+    sv_g = _gpu_statevector(st)
+    fid = abs(np.vdot(sv_o, sv_g)) ** 2 / (np.vdot(sv_o, sv_o).real * np.vdot(sv_g, sv_g).real)
+    assert 1 - fid <= tol * 10
+    assert np.max(np.abs(sv_g - sv_o)) <= tol * 10 * np.max(np.abs(sv_o))
+    assert len(infos) == 55
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_ghz_and_qft(M, prec):
+    print(f"case ghz/qft prec={prec}", flush=True)
+    tol = TOL[prec]
+    n = 7
+    st = M.MPS(n, 2, prec)
+    st.apply_layers(synth.ghz_circuit(n))
+    assert max(st.bond_dims()) <= 2
+    assert abs(st.amplitude([0] * n) - 1 / np.sqrt(2)) <= tol
+    assert abs(st.amplitude([1] * n) - 1 / np.sqrt(2)) <= tol
+    n = 5
+    x = 19
+    st = M.MPS(n, 32, prec)
+    xg = np.array([[0, 1], [1, 0]])
+    st.apply_layers([[(0, synth.kron1(xg, True))], [(3, synth.kron1(xg, True))],
+                     [(3, synth.kron1(xg, False))]])                           # |10011> = 19
+    st.apply_layers(synth.qft_circuit(n))
+    N = 2 ** n
+    ref = np.exp(2j * np.pi * x * np.arange(N) / N) / np.sqrt(N)
+    sv = _gpu_statevector(st)
+    assert np.max(np.abs(sv - ref)) <= tol * 10
+
+
+def test_swap_routing_roundtrip(M):
+    print("case swap roundtrip", flush=True)
+    n = 8
+    layers = synth.brickwork(synth.rng(105), n, 4)
+    st = M.MPS(n, 16, 0)
+    st.apply_layers(layers)
+    before = _gpu_statevector(st)
+    order = list(range(n))
+    target = [3, 0, 5, 1, 7, 4, 2, 6]
+    for i in synth.bubble_swaps(order, target) + synth.bubble_swaps(target, order):
+        st.apply_gate(i, synth.gate_swap())
+    after = _gpu_statevector(st)
+    assert np.max(np.abs(after - before)) <= 1e-10
+
+
+def test_layer_rejects_overlap(M):
+    st = M.MPS(6, 8, 0)
+    g = synth.haar_unitary(synth.rng(1), 4)
+    with pytest.raises(M.MpsError) as e:
+        st.apply_layer([(1, g), (2, g)])
+    assert e.value.status == 1
+    assert st.bond_dims() == [1] * 7
+
+
+def test_centre_moves_both_directions(M):
+    """Gates far to the right then far to the left exercise QR and LQ moves."""
+    print("case centre moves", flush=True)
+    n = 10
+    r = synth.rng(17)
+    gates = [(0, synth.haar_unitary(r, 4)), (7, synth.haar_unitary(r, 4)), (2, synth.haar_unitary(r, 4)),
+             (8, synth.haar_unitary(r, 4)), (0, synth.haar_unitary(r, 4)), (4, synth.haar_unitary(r, 4))]
+    layers = [[gi] for gi in gates] * 3
+    st = M.MPS(n, 32, 0)
+    st.apply_layers(layers)
+    ref = oracle.brute_force(n, layers)
+    sv = _gpu_statevector(st)
+    assert np.max(np.abs(sv - ref)) <= 1e-10

@@ -1,0 +1,160 @@
+"""GPU parity of qrcp_truncate and mps_update_bond against the FP64 oracle.
+
+Tolerances: FP64 mode 1e-10 relative; mixed mode (complex64 storage, FP64
+norms and reflectors) 1e-4 relative.  Pivot sequences must agree exactly on
+inputs with well-separated pivots (synth.well_separated)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2505_06119_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-10, 1: 1e-4}
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2505_06119_amd import mps
+    return mps
+
+
+def _host(t):
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def _run_qrcp(M, a, k, prec):
+    A = M.colmajor(a, prec)
+    out = M.qrcp_truncate(A, k, prec)
+    return {"Q": _host(out["Q"]), "RPt": _host(out["RPt"]), "piv": out["piv"].cpu().numpy().astype(np.int64),
+            "diagR": out["diagR"].cpu().numpy(), "k": out["k"], "err": out["err"], "a_fro": out["a_fro"]}
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("m,n,seed", [(64, 64, 1), (300, 200, 2), (1000, 700, 3), (257, 129, 4)])
+def test_well_separated_pivots_exact(M, prec, m, n, seed):
+    print(f"case well_separated m={m} n={n} prec={prec} seed={seed}", flush=True)
+    a, p = synth.well_separated(synth.rng(seed), m, n)
+    if prec == 1:
+        a = a.astype(np.complex64).astype(np.complex128)
+    g = _run_qrcp(M, a, n, prec)
+    o = oracle.qrcp(a, n)
+    assert list(o["piv"]) == list(p)
+    assert list(g["piv"]) == list(p)
+    tol = TOL[prec]
+    scale = np.linalg.norm(a)
+    np.testing.assert_allclose(g["diagR"], o["diagR"], rtol=tol, atol=tol * scale)
+    rp_o = oracle.r_unpivot(o["R"], o["piv"])
+    assert np.linalg.norm(g["RPt"] - rp_o) <= tol * 10 * scale
+    assert np.linalg.norm(g["Q"] - o["Q"]) <= tol * 10 * np.sqrt(n)
+    assert np.linalg.norm(a - g["Q"] @ g["RPt"]) <= tol * 10 * scale
+    assert abs(g["a_fro"] - scale) <= tol * scale
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("m,n,k,seed", [(96, 96, 48, 5), (200, 130, 70, 6), (130, 200, 64, 7), (513, 260, 100, 8)])
+def test_truncated_gaussian(M, prec, m, n, k, seed):
+    print(f"case truncated_gaussian m={m} n={n} k={k} prec={prec}", flush=True)
+    a = synth.cgauss(synth.rng(seed), (m, n))
+    if prec == 1:
+        a = a.astype(np.complex64).astype(np.complex128)
+    g = _run_qrcp(M, a, k, prec)
+    o = oracle.qrcp(a, k)
+    assert g["k"] == o["k"] == min(k, m, n)
+    tol = TOL[prec]
+    scale = np.linalg.norm(a)
+    if prec == 0:
+        assert list(g["piv"][:k]) == list(o["piv"][:k])
+    # the truncated approximation and its error agree (gauge invariant)
+    approx_g = g["Q"] @ g["RPt"]
+    approx_o = o["Q"] @ oracle.r_unpivot(o["R"], o["piv"])
+    assert np.linalg.norm(approx_g - approx_o) <= tol * 10 * scale
+    assert abs(g["err"] - o["err"]) <= tol * 10 * scale
+    # invariants of the GPU result itself
+    q = g["Q"]
+    np.testing.assert_allclose(q.conj().T @ q, np.eye(g["k"]), atol=tol * 10)
+    assert abs(np.linalg.norm(a - approx_g) - g["err"]) <= tol * 10 * scale
+    d = np.abs(g["diagR"])
+    assert np.all(d[1:] <= d[:-1] * (1 + tol * 10))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_edge_shapes(M, prec):
+    r = synth.rng(9)
+    tol = TOL[prec]
+    cases = [(1, 1, 1), (1, 7, 3), (7, 1, 3), (5, 9, 20), (33, 2, 2), (2, 33, 2), (64, 65, 65)]
+    for m, n, k in cases:
+        print(f"case edge m={m} n={n} k={k} prec={prec}", flush=True)
+        a = synth.cgauss(r, (m, n))
+        if prec == 1:
+            a = a.astype(np.complex64).astype(np.complex128)
+        g = _run_qrcp(M, a, k, prec)
+        o = oracle.qrcp(a, k)
+        assert g["k"] == o["k"]
+        approx_g = g["Q"] @ g["RPt"]
+        approx_o = o["Q"] @ oracle.r_unpivot(o["R"], o["piv"])
+        scale = np.linalg.norm(a)
+        assert np.linalg.norm(approx_g - approx_o) <= tol * 10 * scale
+        assert abs(g["err"] - o["err"]) <= tol * 10 * scale
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_rank_deficient(M, prec):
+    print(f"case rank_deficient prec={prec}", flush=True)
+    r = synth.rng(10)
+    a = synth.cgauss(r, (80, 3)) @ synth.cgauss(r, (3, 60))
+    a[:, 7] = 0.0
+    if prec == 1:
+        a = a.astype(np.complex64).astype(np.complex128)
+    g = _run_qrcp(M, a, 10, prec)
+    tol = TOL[prec]
+    q = g["Q"]
+    np.testing.assert_allclose(q.conj().T @ q, np.eye(10), atol=tol * 10)
+    assert np.linalg.norm(a - q @ g["RPt"]) <= tol * 100 * np.linalg.norm(a)
+    assert g["err"] <= tol * 100 * np.linalg.norm(a)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("chl,chm,chr_,cap,seed", [(8, 16, 8, 8, 11), (24, 40, 20, 32, 12), (64, 96, 64, 64, 13),
+                                                   (33, 50, 30, 100, 14), (1, 2, 1, 4, 15)])
+def test_update_bond_matches_oracle(M, prec, chl, chm, chr_, cap, seed):
+    print(f"case update chi=({chl},{chm},{chr_}) cap={cap} prec={prec}", flush=True)
+    r = synth.rng(seed)
+    a, b = synth.canonical_pair(r, chl, chm, chr_, synth.exp_spectrum(chm, chm / 4.0))
+    g = synth.haar_unitary(r, 4)
+    if prec == 1:
+        a = a.astype(np.complex64).astype(np.complex128)
+        b = b.astype(np.complex64).astype(np.complex128)
+    u_o = oracle.two_site_update(a, b, g, cap)
+    out = M.mps_update_bond(M.site_to_device(a, prec), M.site_to_device(b, prec), g, chl, chm, chr_, cap, prec,
+                            renormalize=False)
+    k = out["k"]
+    assert k == u_o["k"]
+    a2 = M.site_from_device(out["A"], chl, k)
+    b2 = M.site_from_device(out["B"], k, chr_)
+    tt_g = np.tensordot(a2, b2, axes=(2, 0))
+    tt_o = np.tensordot(u_o["A"], u_o["B"], axes=(2, 0))
+    tol = TOL[prec]
+    assert np.linalg.norm(tt_g - tt_o) <= tol * 10
+    info = out["info"]
+    assert abs(info["norm_sq"] - u_o["norm2"]) <= tol * 10
+    assert abs(info["trunc_err_sq"] - u_o["err"] ** 2) <= tol * 10
+    # left site is an isometry
+    q = a2.transpose(1, 0, 2).reshape(2 * chl, k)
+    np.testing.assert_allclose(q.conj().T @ q, np.eye(k), atol=tol * 10)
+
+
+def test_update_bond_renormalises(M):
+    r = synth.rng(16)
+    a, b = synth.canonical_pair(r, 16, 32, 16, synth.exp_spectrum(32, 6.0))
+    g = synth.haar_unitary(r, 4)
+    out = M.mps_update_bond(M.site_to_device(a, 0), M.site_to_device(b, 0), g, 16, 32, 16, 12, 0,
+                            renormalize=True)
+    b2 = M.site_from_device(out["B"], out["k"], 16)
+    assert abs(np.linalg.norm(b2) - 1.0) < 1e-12
+    info = out["info"]
+    assert abs(info["retained"] - (1 - info["trunc_err_sq"] / info["norm_sq"])) < 1e-15
+    assert 0.5 < info["retained"] < 1.0
