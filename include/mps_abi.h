@@ -180,6 +180,35 @@ mps_status mps_centre(const mps_ctx* ctx, int32_t* out);
  * complex128 per the context) to the device buffer dst of dst_bytes. */
 mps_status mps_get_site(mps_ctx* ctx, int32_t j, void* dst, int64_t dst_bytes);
 
+/* ------------------------------------------------------------------------
+ * Per-kernel timing.  mps_profile(1) resets and enables process-wide timing
+ * of the library's launches with HIP events recorded on the caller's stream
+ * (mps_profile(0) disables it).  mps_profile_read fills up to n entries,
+ * indexed by mps_kernel_class, with the launch count, the summed event time
+ * and the algorithmic bytes and flops of those launches.  Not thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef enum {
+    MPS_K_CONTRACT = 0, /* theta0 = A_i A_{i+1} (MFMA GEMM)                   */
+    MPS_K_GATE = 1,     /* gate + FP64 column norms                           */
+    MPS_K_STEP_A = 2,   /* pivot swap, pivot-column bring-up, reflector       */
+    MPS_K_STEP_C = 3,   /* trailing GEMV, F column, pivot row, norm downdate  */
+    MPS_K_TRAIL = 4,    /* panel-end trailing update A -= V F^H (MFMA)        */
+    MPS_K_NORMS = 5,    /* exact norm recomputation and ||R22||_F             */
+    MPS_K_UNGQR = 6,    /* Q_k formation (MFMA)                               */
+    MPS_K_SPLIT = 7,    /* R_k P^T scatter into the right site                */
+    MPS_K_COUNT = 8
+} mps_kernel_class;
+
+typedef struct {
+    int64_t launches;
+    double total_ms;
+    double alg_bytes;
+    double alg_flops;
+} mps_kernel_stats;
+
+mps_status mps_profile(int enable);
+mps_status mps_profile_read(mps_kernel_stats* out, int32_t n);
+
 #ifdef __cplusplus
 }
 #endif

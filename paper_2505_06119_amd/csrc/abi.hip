@@ -97,10 +97,10 @@ static mps_status qrcp_impl(int64_t m, int64_t n, int64_t k, mps_precision prec,
         dim3 grid((unsigned)(rup(m, 256) < 64 ? rup(m, 256) : 64), (unsigned)n);
         hipLaunchKernelGGL((k_copy_cols<T>), grid, dim3(256), 0, st, (const T*)A, lda, w.d.A, w.d.lda, m);
     }
-    init_norms<T>(w, st);
+    const int nparts = init_norms<T>(w, st);
     HIPCHK(hipGetLastError(), "qrcp_truncate launch");
     QrcpStats stats;
-    if (k > 0) HIPCHK(run_qrcp<T>(w, st, &stats), "qrcp_truncate factorisation");
+    if (k > 0) HIPCHK(run_qrcp<T>(w, st, &stats, nparts), "qrcp_truncate factorisation");
     if (k > 0) {
         HIPCHK(form_q<T>(w, (T*)Q, ldq, st), "qrcp_truncate Q");
         hipLaunchKernelGGL((k_rpt<T>), dim3((unsigned)n), dim3(256), 0, st, (const T*)w.d.A, w.d.lda,
@@ -179,22 +179,30 @@ static mps_status update_core(int64_t chi_l, int64_t chi_m, int64_t chi_r, int64
 
     hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, st, d.ctl, d.dsc);
     // a1: theta0 = A_mat (m x chi_m) * B_mat (chi_m x n)
+    hipEvent_t e1 = prof_begin(st);
     if (!zgemm<T>(st, OP_N, false, OP_N, false, m, n, chi_m, C_ONE, A, m, B, chi_m, C_ZERO, d.A, d.lda, w.gsplit,
                   w.gsplit_bytes))
         return fail(MPS_EINVAL, "update: gemm form unavailable");
+    prof_end(e1, st, PK_CONTRACT, (double)sizeof(T) * ((double)m * chi_m + (double)chi_m * n + (double)m * n),
+             8.0 * (double)m * (double)n * (double)chi_m);
     // a2 + a3
+    hipEvent_t e2 = prof_begin(st);
     hipLaunchKernelGGL((k_gate_norms<T>), dim3((unsigned)chi_r), dim3(256), 0, st, d, chi_l, make_gate(g));
-    hipLaunchKernelGGL((k_partials_final<T>), dim3(1), dim3(256), 0, st, d, (int)chi_r, 1, (int)DSC_NORM2,
-                       (int64_t)0);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, (const double*)d.npart, (int)chi_r, d.dsc,
+                       (int)DSC_NORM2);
+    prof_end(e2, st, PK_GATE, 2.0 * sizeof(T) * (double)m * (double)n, 64.0 * (double)m * (double)n / 4.0);
     HIPCHK(hipGetLastError(), "update launch");
     QrcpStats stats;
-    HIPCHK(run_qrcp<T>(w, st, &stats), "update factorisation");
+    HIPCHK(run_qrcp<T>(w, st, &stats, (int)chi_r), "update factorisation");
     HIPCHK(form_q<T>(w, A_out, m, st), "update Q");
+    hipEvent_t e3 = prof_begin(st);
     hipLaunchKernelGGL((k_rpt<T>), dim3((unsigned)n), dim3(256), 0, st, (const T*)d.A, d.lda,
                        (const int32_t*)d.perm, k, n, B_out, k, (const double*)d.dsc, renorm);
+    prof_end(e3, st, PK_SPLIT, 2.0 * sizeof(T) * (double)k * (double)n, 0.0);
     double dsc[DSC_COUNT];
     HIPCHK(hipMemcpyAsync(dsc, d.dsc, sizeof(dsc), hipMemcpyDeviceToHost, st), "update readback");
     HIPCHK(hipStreamSynchronize(st), "update sync");
+    prof_flush();
     if (!isfinite(dsc[DSC_NORM2]) || !isfinite(dsc[DSC_EPS2]))
         return fail(MPS_ENUMERIC, "update: non-finite theta");
     if (info) {
@@ -251,3 +259,26 @@ extern "C" mps_status mps_update_bond(int64_t chi_l, int64_t chi_m, int64_t chi_
 
 // stateful MPS context
 #include "context.hpp"
+
+// ---------------------------------------------------------------------------
+// per-kernel timing
+// ---------------------------------------------------------------------------
+extern "C" mps_status mps_profile(int enable)
+{
+    g_prof.on = enable != 0;
+    g_prof.pending.clear();
+    for (int c = 0; c < PK_COUNT; ++c) g_prof.acc[c] = ProfAcc{0, 0.0, 0.0, 0.0};
+    return MPS_OK;
+}
+
+extern "C" mps_status mps_profile_read(mps_kernel_stats* out, int32_t n)
+{
+    if (!out || n < 1) return fail(MPS_EINVAL, "mps_profile_read: bad arguments");
+    for (int c = 0; c < n && c < PK_COUNT; ++c) {
+        out[c].launches = g_prof.acc[c].launches;
+        out[c].total_ms = g_prof.acc[c].total_ms;
+        out[c].alg_bytes = g_prof.acc[c].alg_bytes;
+        out[c].alg_flops = g_prof.acc[c].alg_flops;
+    }
+    return MPS_OK;
+}

@@ -218,7 +218,7 @@ static mps_status ctx_qr(mps_ctx* c, const T* M, int64_t m, int64_t n, bool tran
     hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, st, w.d.ctl, w.d.dsc);
     hipLaunchKernelGGL((k_iota<T>), dim3((unsigned)rup(n, 256)), dim3(256), 0, st, w.d.perm, n);
     HIPCHK(hipGetLastError(), "centre move launch");
-    HIPCHK(run_qrcp<T>(w, st, nullptr), "centre move QR");
+    HIPCHK(run_qrcp<T>(w, st, nullptr, 0), "centre move QR");
     HIPCHK(form_q<T>(w, Q, ldq, st), "centre move Q");
     hipLaunchKernelGGL((k_rpt<T>), dim3((unsigned)n), dim3(256), 0, st, (const T*)w.d.A, w.d.lda,
                        (const int32_t*)w.d.perm, k, n, (T*)c->rbuf, k, (const double*)w.d.dsc, 0);

@@ -1,0 +1,89 @@
+// Optional per-kernel timing with HIP events on the launch stream.  When
+// enabled (mps_profile), every timed launch is bracketed by an event pair; the
+// pairs are resolved at the next host synchronisation point of the library
+// and accumulated per kernel class together with the algorithmic bytes and
+// flops of each launch.  Process-global; meant for single-threaded use.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <vector>
+
+enum {
+    PK_CONTRACT = 0,  // theta0 = A B (MFMA GEMM)
+    PK_GATE = 1,      // gate + FP64 column norms
+    PK_STEP_A = 2,    // pivot swap, bring-up, reflector
+    PK_STEP_C = 3,    // trailing GEMV, F column, pivot row, downdate
+    PK_TRAIL = 4,     // panel-end MFMA update A -= V F^H
+    PK_NORMS = 5,     // exact norm recomputation / ||R22||
+    PK_UNGQR = 6,     // Q formation
+    PK_SPLIT = 7,     // R P^T scatter
+    PK_COUNT = 8
+};
+
+struct ProfAcc {
+    int64_t launches;
+    double total_ms;
+    double alg_bytes;
+    double alg_flops;
+};
+
+struct ProfState {
+    bool on = false;
+    struct Rec {
+        hipEvent_t a, b;
+        int cls;
+        double bytes, flops;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    ProfAcc acc[PK_COUNT] = {};
+};
+
+static ProfState g_prof;
+
+static hipEvent_t prof_event()
+{
+    if (!g_prof.pool.empty()) {
+        hipEvent_t e = g_prof.pool.back();
+        g_prof.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Returns an opaque begin event (or null when profiling is off).
+static inline hipEvent_t prof_begin(hipStream_t st)
+{
+    if (!g_prof.on) return nullptr;
+    hipEvent_t e = prof_event();
+    if (e) (void)hipEventRecord(e, st);
+    return e;
+}
+
+static inline void prof_end(hipEvent_t begin, hipStream_t st, int cls, double bytes, double flops)
+{
+    if (!g_prof.on || !begin) return;
+    hipEvent_t e = prof_event();
+    if (!e) return;
+    (void)hipEventRecord(e, st);
+    g_prof.pending.push_back({begin, e, cls, bytes, flops});
+}
+
+// Call after the stream has been synchronised.
+static inline void prof_flush()
+{
+    for (auto& r : g_prof.pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            ProfAcc& a = g_prof.acc[r.cls];
+            a.launches++;
+            a.total_ms += ms;
+            a.alg_bytes += r.bytes;
+            a.alg_flops += r.flops;
+        }
+        g_prof.pool.push_back(r.a);
+        g_prof.pool.push_back(r.b);
+    }
+    g_prof.pending.clear();
+}

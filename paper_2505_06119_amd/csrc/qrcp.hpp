@@ -9,15 +9,20 @@
 // with V the stored Householder vectors (unit lower trapezoidal, columns
 // p0..j-1 of theta) and F (n x nb).  One pivot step j costs two launches:
 //
-//   step A  (rows split over blocks)  pivot swap, bring the pivot column up to
-//           date (x = A_ps[:, j] - V F[j, :]^H), partial sums of ||x||^2 and
-//           V^H x; the last block to finish forms the reflector
-//           (beta, tau, scale) in FP64 and aux = V^H v.
-//   step C  (columns split over blocks)  the GEMV w = A_ps^H v over the whole
-//           trailing block (the HBM-bound part), the new F column
+//   step A  (rows split over blocks)  every block first reduces the argmax
+//           partials of the previous launch to the pivot p; then the pivot
+//           swap, the bring-up of the pivot column (x = A_ps[:, j] - V F[j, :]^H)
+//           and per-block partial sums of ||x||^2 and V^H x.
+//   step C  (columns split over blocks)  every block first reduces step A's
+//           partials to the reflector (beta, tau, scale in FP64) and
+//           aux = V^H v; then the GEMV w = A_ps^H v over the whole trailing
+//           block (the HBM-bound part), the new F column
 //           F[:, jj] = tau (w - F aux), the pivot row of R, the FP64 downdate
-//           of the residual column norms and a partial argmax; the last block
-//           to finish picks the next pivot.
+//           of the residual column norms and a per-block argmax partial.
+//
+// The redundant per-block reductions replace in-kernel cross-block
+// synchronisation: partial results only cross a kernel boundary, so no block
+// ever waits for or fences against another.
 //
 // At the end of a panel the host launches the MFMA update
 // A[j:, j:] -= V F^H.  A residual norm whose downdated value has fallen below
@@ -32,20 +37,15 @@
 #include "common.hpp"
 
 #define QR_NBMAX 64
-#define QR_CW 4            // columns per block in step C
+#define QR_CW 8            // columns per block in step C and the norm kernel
 
 enum {
-    CTL_PIV = 0,      // pivot position for the next step
+    CTL_PIV = 0,      // pivot position of the current step (written by step A)
     CTL_STOP = 1,     // panel must end: a norm needs recomputing
     CTL_JDONE = 2,    // number of completed steps
-    CTL_TICKET_A = 3,
-    CTL_TICKET_C = 4,
-    CTL_TICKET_M = 5,
-    CTL_PEND = 6,     // a column was flagged during the current step C
-    CTL_NREFRESH = 7, // number of norm refreshes (statistics)
     CTL_COUNT = 16
 };
-enum { DSC_NORM2 = 0, DSC_EPS2 = 1, DSC_RET2 = 2, DSC_COUNT = 8 };
+enum { DSC_NORM2 = 0, DSC_EPS2 = 1, DSC_COUNT = 8 };
 
 template <typename T>
 struct QrcpDev {
@@ -58,11 +58,13 @@ struct QrcpDev {
     int64_t ldf;
     double2* tau;
     double* diagR;
-    double2* xbuf;
+    double2* xbuf;     // pivot column after bring-up, FP64
+    T* xlo;            // the same in storage precision (vector GEMV operand)
     double* apart;     // step-A partials, (2 + 2*QR_NBMAX) doubles per block
-    double2* hh;       // [0] alpha [1] beta [2] tau [3] scale [4..] aux
+    double2* hh;       // [0] alpha (written by the block holding row j)
     double2* fsave;    // QR_NBMAX
-    ArgBest* cpart;    // step-C / norm-kernel argmax partials
+    ArgBest* cpart;    // argmax partials of the last producer (gate, norms, step C)
+    int32_t* cflag;    // per-partial "a norm needs recomputing" flags
     double* npart;     // per-block partial sums of squares
     int32_t* ctl;      // CTL_COUNT ints
     double* dsc;       // DSC_COUNT doubles
@@ -93,20 +95,42 @@ __device__ __forceinline__ void block_sum_vec(double (&v)[NV], double* lds /* 4*
 }
 
 // ---------------------------------------------------------------------------
-// step A: pivot swap + bring-up of the pivot column + reflector (last block)
-// grid: ceil(m / 256) blocks, one row per thread.
+// step A: pivot choice + swap + bring-up of the pivot column + partial sums.
+// grid: ceil(m / 256) blocks, one row per thread.  nparts: number of argmax
+// partials left by the previous launch.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_step_a(QrcpDev<T> d, int64_t j, int64_t p0, int jj)
+__global__ __launch_bounds__(256) void k_step_a(QrcpDev<T> d, int64_t j, int64_t p0, int jj, int nparts)
 {
     __shared__ double2 fp[QR_NBMAX];
     __shared__ double red_lds[4 * 16];
     __shared__ double red_out[16];
-    __shared__ int last_flag;
-    if (ld_coherent(&d.ctl[CTL_STOP])) return;
+    __shared__ ArgBest arg_lds[4];
+    if (d.ctl[CTL_STOP]) return;
 
     const int tid = threadIdx.x;
-    const int64_t p = d.pivoting ? (int64_t)d.ctl[CTL_PIV] : j;
+    int64_t p = j;
+    if (d.pivoting) {
+        ArgBest b;
+        b.val = -1.0;
+        b.key = 0x7fffffff;
+        b.slot = -1;
+        double fl = 0.0;
+        for (int q = tid; q < nparts; q += 256) {
+            const ArgBest e = d.cpart[q];
+            if (e.slot >= 0 && arg_better(e.val, e.key, b.val, b.key)) b = e;
+            fl += d.cflag[q] ? 1.0 : 0.0;
+        }
+        b = block_argmax256(b, arg_lds);
+        fl = block_sum256(fl, red_lds);
+        if (fl > 0.0) {
+            // a residual norm of the previous step became unreliable: end the panel
+            if (blockIdx.x == 0 && tid == 0) d.ctl[CTL_STOP] = 1;
+            return;
+        }
+        if (b.slot >= j) p = b.slot;
+        if (blockIdx.x == 0 && tid == 0) d.ctl[CTL_PIV] = (int32_t)p;
+    }
     if (tid < jj) fp[tid] = to_d(d.F[p + d.ldf * tid]);
     if (blockIdx.x == 0 && p != j) {
         if (tid < jj) {
@@ -137,6 +161,7 @@ __global__ __launch_bounds__(256) void k_step_a(QrcpDev<T> d, int64_t j, int64_t
             for (int t = 0; t < jj; ++t)
                 x = csub(x, cmul(to_d(d.A[i + d.lda * (p0 + t)]), cconj(fp[t])));
             d.xbuf[i] = x;
+            d.xlo[i] = from_d<T>(x);
             has = true;
             if (i == j) d.hh[0] = x;
         }
@@ -160,27 +185,121 @@ __global__ __launch_bounds__(256) void k_step_a(QrcpDev<T> d, int64_t j, int64_t
         block_sum_vec<16>(v, red_lds, red_out);
         if (tid < 16 && t0 + tid / 2 < jj) part[2 + 2 * t0 + tid] = red_out[tid];
     }
+}
 
-    if (!last_block_ticket((unsigned int*)&d.ctl[CTL_TICKET_A], gridDim.x, &last_flag)) return;
+// Partial GEMV of one thread: acc[2u], acc[2u+1] += sum over this thread's
+// rows i > j of conj(A[i, cbase+u]) x_i, for the CW columns cbase.. (< cend).
+// x is read in storage precision (xlo); accumulation is FP64.  Storage is
+// read in 16-byte vectors: two complex64 rows or one complex128 row per load,
+// two loads per column in flight per thread.  The leading dimension is even,
+// so every column starts 16-byte aligned.
+template <typename T, int CW>
+__device__ __forceinline__ void gemv_cols(const QrcpDev<T>& d, int64_t j, int64_t cbase, int64_t cend,
+                                          double (&acc)[2 * CW])
+{
+#pragma unroll
+    for (int u = 0; u < 2 * CW; ++u) acc[u] = 0.0;
+    const int tid = threadIdx.x;
+    const int64_t ncols = cend - cbase;
+    if constexpr (sizeof(T) == 8) {
+        // complex64: pairs of rows (r, r+1), r even, starting at the pair holding row j+1
+        const int64_t r0 = (j + 1) & ~(int64_t)1;
+        const int64_t m = d.m;
+        for (int64_t r = r0 + 2 * tid; r < m; r += 1024) {
+            const int64_t r2 = r + 512;
+            const bool has2 = r2 < m;
+            const float4 xa = *(const float4*)(d.xlo + r);
+            float4 xb = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (has2) xb = *(const float4*)(d.xlo + r2);
+            float4 av[CW], bv[CW];
+#pragma unroll
+            for (int u = 0; u < CW; ++u) {
+                if (u < ncols) {
+                    const T* col = d.A + d.lda * (cbase + u);
+                    av[u] = *(const float4*)(col + r);
+                    bv[u] = has2 ? *(const float4*)(col + r2) : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+            }
+            // rows outside (j, m) contribute nothing (select, so no NaN leaks in)
+            const bool a0 = r > j, a1 = r + 1 < m, b1 = r2 + 1 < m;
+#pragma unroll
+            for (int u = 0; u < CW; ++u) {
+                if (u < ncols) {
+                    double2 p = czero();
+                    if (a0) p = cadd(p, cmulc(make_double2(av[u].x, av[u].y), make_double2(xa.x, xa.y)));
+                    if (a1) p = cadd(p, cmulc(make_double2(av[u].z, av[u].w), make_double2(xa.z, xa.w)));
+                    if (has2) {
+                        p = cadd(p, cmulc(make_double2(bv[u].x, bv[u].y), make_double2(xb.x, xb.y)));
+                        if (b1) p = cadd(p, cmulc(make_double2(bv[u].z, bv[u].w), make_double2(xb.z, xb.w)));
+                    }
+                    acc[2 * u] += p.x;
+                    acc[2 * u + 1] += p.y;
+                }
+            }
+        }
+    } else {
+        // complex128: one row per 16-byte load
+        const int64_t m = d.m;
+        for (int64_t r = j + 1 + tid; r < m; r += 512) {
+            const int64_t r2 = r + 256;
+            const bool has2 = r2 < m;
+            const double2 xa = to_d(d.xlo[r]);
+            const double2 xb = has2 ? to_d(d.xlo[r2]) : czero();
+            double2 av[CW], bv[CW];
+#pragma unroll
+            for (int u = 0; u < CW; ++u) {
+                if (u < ncols) {
+                    const T* col = d.A + d.lda * (cbase + u);
+                    av[u] = to_d(col[r]);
+                    bv[u] = has2 ? to_d(col[r2]) : czero();
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < CW; ++u) {
+                if (u < ncols) {
+                    double2 p = cmulc(av[u], xa);
+                    if (has2) p = cadd(p, cmulc(bv[u], xb));
+                    acc[2 * u] += p.x;
+                    acc[2 * u + 1] += p.y;
+                }
+            }
+        }
+    }
+}
 
-    // ---- last block: reduce partials, form the reflector ----
-    __shared__ double2 wsum[QR_NBMAX];
-    __shared__ double2 s_alpha, s_scale;
-    const int nb = gridDim.x;
+
+// ---------------------------------------------------------------------------
+// step C: reflector from step A's partials, GEMV over the trailing block,
+// new F column, pivot row of R, downdate + per-block argmax partial.
+// grid: ceil((cend - j - 1) / QR_CW) blocks (at least one); na = step A blocks.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_step_c(QrcpDev<T> d, int64_t j, int64_t p0, int jj, int64_t cend,
+                                                int na)
+{
+    __shared__ double2 s_aux[QR_NBMAX], s_vj[QR_NBMAX], s_w[QR_NBMAX];
+    __shared__ double2 s_par[4];   // beta, tau, scale, alpha
+    __shared__ double red_lds[4 * 2 * QR_CW];
+    __shared__ double red_out[2 * QR_CW];
+    __shared__ ArgBest arg_lds[4];
+    __shared__ double flag_lds[4];
+    if (d.ctl[CTL_STOP]) return;
+
+    const int tid = threadIdx.x;
+    // ---- reflector from step A's partials (identical in every block) ----
     if (tid < jj) {
         double2 w = czero();
-        for (int b = 0; b < nb; ++b) {
-            w.x += ld_coherent(d.apart + (int64_t)b * APART_STRIDE + 2 + 2 * tid);
-            w.y += ld_coherent(d.apart + (int64_t)b * APART_STRIDE + 3 + 2 * tid);
+        for (int b = 0; b < na; ++b) {
+            w.x += d.apart[(int64_t)b * APART_STRIDE + 2 + 2 * tid];
+            w.y += d.apart[(int64_t)b * APART_STRIDE + 3 + 2 * tid];
         }
-        wsum[tid] = w;
+        s_w[tid] = w;
+        s_vj[tid] = to_d(d.A[j + d.lda * (p0 + tid)]);
     }
-    if (tid == 0) {
+    if (tid == 64) {
         double rest = 0.0;
-        for (int b = 0; b < nb; ++b) rest += ld_coherent(d.apart + (int64_t)b * APART_STRIDE);
-        double2 alpha;
-        alpha.x = ld_coherent(&d.hh[0].x);
-        alpha.y = ld_coherent(&d.hh[0].y);
+        for (int b = 0; b < na; ++b) rest += d.apart[(int64_t)b * APART_STRIDE];
+        const double2 alpha = d.hh[0];
         double2 tau, scale;
         double beta;
         if (rest == 0.0 && alpha.y == 0.0) {
@@ -193,43 +312,18 @@ __global__ __launch_bounds__(256) void k_step_a(QrcpDev<T> d, int64_t j, int64_t
             tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
             scale = cdiv(make_double2(1.0, 0.0), make_double2(alpha.x - beta, alpha.y));
         }
-        d.hh[1] = make_double2(beta, 0.0);
-        d.hh[2] = tau;
-        d.hh[3] = scale;
-        s_alpha = alpha;
-        s_scale = scale;
+        s_par[0] = make_double2(beta, 0.0);
+        s_par[1] = tau;
+        s_par[2] = scale;
+        s_par[3] = alpha;
     }
     __syncthreads();
     if (tid < jj) {
-        // aux_t = V[:, t]^H v with v = (1, scale * x_rest)
-        const double2 vjt = cconj(to_d(d.A[j + d.lda * (p0 + tid)]));
-        const double2 rest = csub(wsum[tid], cmul(vjt, s_alpha));
-        d.hh[4 + tid] = cadd(vjt, cmul(s_scale, rest));
+        // aux_t = V[:, t]^H v with v = (1, scale * x_rest), V[j, t] = s_vj[t]
+        const double2 vjt = cconj(s_vj[tid]);
+        const double2 rest = csub(s_w[tid], cmul(vjt, s_par[3]));
+        s_aux[tid] = cadd(vjt, cmul(s_par[2], rest));
     }
-}
-
-// ---------------------------------------------------------------------------
-// step C: GEMV over the trailing block, new F column, pivot row of R,
-// downdate + partial argmax; last block picks the next pivot.
-// grid: ceil((cend - j - 1) / QR_CW) blocks (at least one).
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_step_c(QrcpDev<T> d, int64_t j, int64_t p0, int jj, int64_t cend)
-{
-    __shared__ double2 s_aux[QR_NBMAX], s_vj[QR_NBMAX];
-    __shared__ double2 s_par[4];   // beta, tau, scale
-    __shared__ double red_lds[4 * 2 * QR_CW];
-    __shared__ double red_out[2 * QR_CW];
-    __shared__ ArgBest arg_lds[4];
-    __shared__ int last_flag;
-    if (ld_coherent(&d.ctl[CTL_STOP])) return;
-
-    const int tid = threadIdx.x;
-    if (tid < jj) {
-        s_aux[tid] = d.hh[4 + tid];
-        s_vj[tid] = to_d(d.A[j + d.lda * (p0 + tid)]);
-    }
-    if (tid < 3) s_par[tid] = d.hh[1 + tid];
     __syncthreads();
     const double beta = s_par[0].x;
     const double2 tau = s_par[1], scale = s_par[2];
@@ -238,20 +332,7 @@ __global__ __launch_bounds__(256) void k_step_c(QrcpDev<T> d, int64_t j, int64_t
     // ---- GEMV: g_u = sum_{i>j} conj(A[i, c_u]) x_i ----
     const int64_t cbase = j + 1 + (int64_t)blockIdx.x * QR_CW;
     double acc[2 * QR_CW];
-#pragma unroll
-    for (int u = 0; u < 2 * QR_CW; ++u) acc[u] = 0.0;
-    for (int64_t i = j + 1 + tid; i < d.m; i += 256) {
-        const double2 xi = d.xbuf[i];
-#pragma unroll
-        for (int u = 0; u < QR_CW; ++u) {
-            const int64_t c = cbase + u;
-            if (c < cend) {
-                const double2 w = cmulc(to_d(d.A[i + d.lda * c]), xi);
-                acc[2 * u] += w.x;
-                acc[2 * u + 1] += w.y;
-            }
-        }
-    }
+    gemv_cols<T, QR_CW>(d, j, cbase, cend, acc);
     block_sum_vec<2 * QR_CW>(acc, red_lds, red_out);
 
     // ---- per-column scalar work (one thread per column) ----
@@ -259,6 +340,7 @@ __global__ __launch_bounds__(256) void k_step_c(QrcpDev<T> d, int64_t j, int64_t
     best.val = -1.0;
     best.key = 0x7fffffff;
     best.slot = -1;
+    double flagged = 0.0;
     if (tid < QR_CW) {
         const int64_t c = cbase + tid;
         if (c < cend) {
@@ -283,8 +365,9 @@ __global__ __launch_bounds__(256) void k_step_c(QrcpDev<T> d, int64_t j, int64_t
                 if (nn < 0.0) nn = 0.0;
                 const bool flag = nn <= d.tol * d.nuref[c];
                 d.nu[c] = nn;
-                if (flag) atomicOr(&d.ctl[CTL_PEND], 1);
-                else {
+                if (flag) {
+                    flagged = 1.0;
+                } else {
                     best.val = nn;
                     best.key = d.perm[c];
                     best.slot = (int32_t)c;
@@ -305,30 +388,11 @@ __global__ __launch_bounds__(256) void k_step_c(QrcpDev<T> d, int64_t j, int64_t
         }
     }
     if (!d.pivoting) return;
-
     best = block_argmax256(best, arg_lds);
-    if (tid == 0) d.cpart[blockIdx.x] = best;
-    if (!last_block_ticket((unsigned int*)&d.ctl[CTL_TICKET_C], gridDim.x, &last_flag)) return;
-
-    // ---- last block: next pivot ----
-    ArgBest b;
-    b.val = -1.0;
-    b.key = 0x7fffffff;
-    b.slot = -1;
-    for (int q = tid; q < (int)gridDim.x; q += 256) {
-        ArgBest e;
-        e.val = ld_coherent(&d.cpart[q].val);
-        e.key = ld_coherent(&d.cpart[q].key);
-        e.slot = ld_coherent(&d.cpart[q].slot);
-        if (e.slot >= 0 && arg_better(e.val, e.key, b.val, b.key)) b = e;
-    }
-    b = block_argmax256(b, arg_lds);
+    flagged = block_sum256(flagged, flag_lds);
     if (tid == 0) {
-        d.ctl[CTL_PIV] = b.slot >= 0 ? b.slot : (int32_t)(j + 1 < d.n ? j + 1 : j);
-        if (ld_coherent(&d.ctl[CTL_PEND])) {
-            d.ctl[CTL_PEND] = 0;
-            d.ctl[CTL_STOP] = 1;
-        }
+        d.cpart[blockIdx.x] = best;
+        d.cflag[blockIdx.x] = flagged > 0.0 ? 1 : 0;
     }
 }
 
@@ -373,40 +437,21 @@ __global__ __launch_bounds__(256) void k_colnorms(QrcpDev<T> d, int64_t r0, int6
     best = block_argmax256(best, arg_lds);
     if (tid == 0) {
         d.cpart[blockIdx.x] = best;
+        d.cflag[blockIdx.x] = 0;
         double s = 0.0;
         for (int u = 0; u < QR_CW; ++u) s += red_out[u];
         d.npart[blockIdx.x] = s;
     }
 }
 
-// One block: reduce the partials of k_colnorms (or of the gate kernel) into
-// the next pivot and/or a scalar sum stored in dsc[dslot] (dslot < 0: none).
-template <typename T>
-__global__ __launch_bounds__(256) void k_partials_final(QrcpDev<T> d, int nparts, int do_piv, int dslot,
-                                                        int64_t fallback_piv)
+// One block: fixed-order FP64 sum of the per-block partial sums into dsc[dslot].
+__global__ __launch_bounds__(256) void k_sum_partials(const double* npart, int nparts, double* dsc, int dslot)
 {
-    __shared__ ArgBest arg_lds[4];
     __shared__ double red[4];
-    const int tid = threadIdx.x;
-    ArgBest b;
-    b.val = -1.0;
-    b.key = 0x7fffffff;
-    b.slot = -1;
     double s = 0.0;
-    for (int q = tid; q < nparts; q += 256) {
-        if (do_piv) {
-            ArgBest e = d.cpart[q];
-            if (e.slot >= 0 && arg_better(e.val, e.key, b.val, b.key)) b = e;
-        }
-        if (dslot >= 0) s += d.npart[q];
-    }
-    // fixed-order FP64 sum: per-thread strided partials, then a block sum
+    for (int q = threadIdx.x; q < nparts; q += 256) s += npart[q];
     s = block_sum256(s, red);
-    b = block_argmax256(b, arg_lds);
-    if (tid == 0) {
-        if (do_piv) d.ctl[CTL_PIV] = b.slot >= 0 ? b.slot : (int32_t)fallback_piv;
-        if (dslot >= 0) d.dsc[dslot] = s;
-    }
+    if (threadIdx.x == 0) dsc[dslot] = s;
 }
 
 // Reset the per-factorisation control block.
@@ -420,7 +465,6 @@ __global__ void k_ctl_panel(int32_t* ctl, int32_t jdone)
 {
     if (threadIdx.x == 0) {
         ctl[CTL_STOP] = 0;
-        ctl[CTL_PEND] = 0;
         ctl[CTL_JDONE] = jdone;
     }
 }

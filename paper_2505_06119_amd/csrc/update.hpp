@@ -17,6 +17,7 @@
 #pragma once
 #include <vector>
 #include "gemm.hpp"
+#include "prof.hpp"
 #include "qrcp.hpp"
 
 struct Gate4 {
@@ -74,6 +75,7 @@ __global__ __launch_bounds__(256) void k_gate_norms(QrcpDev<T> d, int64_t chi_l,
     best = block_argmax256(best, arg_lds);
     if (threadIdx.x == 0) {
         d.cpart[r] = best;
+        d.cflag[r] = 0;
         d.npart[r] = red_out[0] + red_out[1];
     }
 }
@@ -187,8 +189,8 @@ template <typename T>
 static bool carve_update_ws(Carver& cv, UpdateWs<T>& w, int64_t m, int64_t n, int64_t k, bool theta_in_ws)
 {
     QrcpDev<T>& d = w.d;
-    d.m = m; d.n = n; d.k = k; d.lda = m > 1 ? m : 1;
-    d.A = theta_in_ws ? (T*)cv.take((int64_t)sizeof(T) * m * n) : nullptr;
+    d.m = m; d.n = n; d.k = k; d.lda = m > 1 ? m + (m & 1) : 2;   // even: 16-byte aligned columns
+    d.A = theta_in_ws ? (T*)cv.take((int64_t)sizeof(T) * d.lda * n) : nullptr;
     d.nu = (double*)cv.take(8 * (n + 1));
     d.nuref = (double*)cv.take(8 * (n + 1));
     d.perm = (int32_t*)cv.take(4 * (n + 1));
@@ -197,12 +199,14 @@ static bool carve_update_ws(Carver& cv, UpdateWs<T>& w, int64_t m, int64_t n, in
     d.tau = (double2*)cv.take(16 * (k + 1));
     d.diagR = (double*)cv.take(8 * (k + 1));
     d.xbuf = (double2*)cv.take(16 * (m + 1));
+    d.xlo = (T*)cv.take((int64_t)sizeof(T) * (d.lda + 2));
     d.apart = (double*)cv.take(8 * APART_STRIDE * (rup(m, 256) + 1));
     d.hh = (double2*)cv.take(16 * (4 + QR_NBMAX));
     d.fsave = (double2*)cv.take(16 * QR_NBMAX);
     const int64_t np = rup(n, QR_CW) + rup(n, 2) + 8;
     d.cpart = (ArgBest*)cv.take((int64_t)sizeof(ArgBest) * np);
     d.npart = (double*)cv.take(8 * np);
+    d.cflag = (int32_t*)cv.take(4 * np);
     d.ctl = (int32_t*)cv.take(4 * CTL_COUNT);
     d.dsc = (double*)cv.take(8 * DSC_COUNT);
     w.Gbuf = (T*)cv.take((int64_t)sizeof(T) * UNGQR_NB * UNGQR_NB);
@@ -212,8 +216,8 @@ static bool carve_update_ws(Carver& cv, UpdateWs<T>& w, int64_t m, int64_t n, in
     const int64_t sk = (int64_t)sizeof(T) * 16 * UNGQR_NB * (k > UNGQR_NB ? k : UNGQR_NB);
     w.gsplit = cv.take(sk);
     w.gsplit_bytes = sk;
-    return d.nu && d.nuref && d.perm && d.F && d.tau && d.diagR && d.xbuf && d.apart && d.hh && d.fsave &&
-           d.cpart && d.npart && d.ctl && d.dsc && w.Gbuf && w.Tbuf && w.Wbuf && w.W2buf && w.gsplit &&
+    return d.nu && d.nuref && d.perm && d.F && d.tau && d.diagR && d.xbuf && d.xlo && d.apart && d.hh && d.fsave &&
+           d.cpart && d.npart && d.cflag && d.ctl && d.dsc && w.Gbuf && w.Tbuf && w.Wbuf && w.W2buf && w.gsplit &&
            (!theta_in_ws || d.A);
 }
 
@@ -228,8 +232,10 @@ struct QrcpStats {
 
 // a4-a10 on d.A; expects nu/nuref/perm/ctl[PIV] set up (pivoting) and the
 // control block reset.  Synchronises the stream once per panel.
+// nparts: argmax partials left by the kernel that set up the norms (ignored
+// without pivoting).
 template <typename T>
-static hipError_t run_qrcp(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats)
+static hipError_t run_qrcp(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats, int nparts)
 {
     QrcpDev<T>& d = w.d;
     const int64_t m = d.m, n = d.n, k = d.k;
@@ -242,31 +248,44 @@ static hipError_t run_qrcp(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats)
         hipLaunchKernelGGL(k_ctl_panel, dim3(1), dim3(64), 0, st, d.ctl, (int32_t)p0);
         for (int64_t jc = p0; jc < pend; ++jc) {
             const int jj = (int)(jc - p0);
-            hipLaunchKernelGGL((k_step_a<T>), dim3(na), dim3(256), 0, st, d, jc, p0, jj);
+            hipEvent_t ea = prof_begin(st);
+            hipLaunchKernelGGL((k_step_a<T>), dim3(na), dim3(256), 0, st, d, jc, p0, jj, nparts);
+            prof_end(ea, st, PK_STEP_A, (double)sizeof(T) * (double)(m - jc) * (jj + 1), 8.0 * (m - jc) * jj);
             int64_t ncol = n - jc - 1;
             unsigned nc = (unsigned)(ncol > 0 ? rup(ncol, QR_CW) : 1);
-            hipLaunchKernelGGL((k_step_c<T>), dim3(nc), dim3(256), 0, st, d, jc, p0, jj, n);
+            hipEvent_t ec = prof_begin(st);
+            hipLaunchKernelGGL((k_step_c<T>), dim3(nc), dim3(256), 0, st, d, jc, p0, jj, n, (int)na);
+            nparts = (int)nc;
+            // algorithmic traffic of one step: one read of the trailing block
+            prof_end(ec, st, PK_STEP_C, (double)sizeof(T) * (double)(m - jc) * (double)(ncol > 0 ? ncol : 0),
+                     8.0 * (double)(m - jc) * (double)(ncol > 0 ? ncol : 0));
         }
         int32_t hctl[CTL_COUNT];
         hipError_t e = hipMemcpyAsync(hctl, d.ctl, sizeof(hctl), hipMemcpyDeviceToHost, st);
         if (e != hipSuccess) return e;
         e = hipStreamSynchronize(st);
         if (e != hipSuccess) return e;
+        prof_flush();
         const int64_t jend = hctl[CTL_JDONE];
         if (jend <= p0 || jend > pend) return hipErrorUnknown;   // no progress: corrupt state
         const int64_t nbe = jend - p0;
         // trailing update A[jend:, jend:] -= V[jend:, p0:jend] F[jend:, 0:nbe]^H
         if (m > jend && n > jend) {
+            hipEvent_t et = prof_begin(st);
             if (!zgemm<T>(st, OP_N, false, OP_C, false, m - jend, n - jend, nbe, C_MONE,
                           d.A + jend + d.lda * p0, d.lda, d.F + jend, d.ldf, C_ONE,
                           d.A + jend + d.lda * jend, d.lda, nullptr, 0))
                 return hipErrorInvalidValue;
+            const double mn = (double)(m - jend) * (double)(n - jend);
+            prof_end(et, st, PK_TRAIL, 2.0 * sizeof(T) * mn, 8.0 * mn * nbe);
         }
         if (stats) stats->panels++;
         if (hctl[CTL_STOP] && jend < k && d.pivoting) {
             const unsigned nblk = (unsigned)rup(n - jend, QR_CW);
+            hipEvent_t en = prof_begin(st);
             hipLaunchKernelGGL((k_colnorms<T>), dim3(nblk), dim3(256), 0, st, d, jend, jend, 1, 0);
-            hipLaunchKernelGGL((k_partials_final<T>), dim3(1), dim3(256), 0, st, d, (int)nblk, 1, -1, jend);
+            nparts = (int)nblk;
+            prof_end(en, st, PK_NORMS, (double)sizeof(T) * (double)(m - jend) * (double)(n - jend), 0.0);
             if (stats) stats->refreshes++;
         }
         j = jend;
@@ -274,9 +293,11 @@ static hipError_t run_qrcp(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats)
     // a10: ||R22||_F^2 over the final trailing block
     if (m > k && n > k) {
         const unsigned nblk = (unsigned)rup(n - k, QR_CW);
+        hipEvent_t en = prof_begin(st);
         hipLaunchKernelGGL((k_colnorms<T>), dim3(nblk), dim3(256), 0, st, d, k, k, 0, 0);
-        hipLaunchKernelGGL((k_partials_final<T>), dim3(1), dim3(256), 0, st, d, (int)nblk, 0, (int)DSC_EPS2,
-                           (int64_t)0);
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, (const double*)d.npart, (int)nblk, d.dsc,
+                           (int)DSC_EPS2);
+        prof_end(en, st, PK_NORMS, (double)sizeof(T) * (double)(m - k) * (double)(n - k), 0.0);
     }
     return hipGetLastError();
 }
@@ -294,6 +315,8 @@ static hipError_t form_q(UpdateWs<T>& w, T* Q, int64_t ldq, hipStream_t st)
         hipLaunchKernelGGL((k_eye<T>), grid, dim3(256), 0, st, Q, ldq, m, k);
     }
     const int64_t last = ((k - 1) / UNGQR_NB) * UNGQR_NB;
+    hipEvent_t eq = prof_begin(st);
+    double flops = 0.0, bytes = 0.0;
     for (int64_t b0 = last; b0 >= 0; b0 -= UNGQR_NB) {
         const int nbe = (int)((k - b0) < UNGQR_NB ? (k - b0) : UNGQR_NB);
         const T* V = d.A + b0 + d.lda * b0;
@@ -315,19 +338,24 @@ static hipError_t form_q(UpdateWs<T>& w, T* Q, int64_t ldq, hipStream_t st)
         if (!zgemm<T>(st, OP_N, true, OP_N, false, rows, cols, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, C_ONE,
                       Q + b0 + ldq * b0, ldq, nullptr, 0))
             return hipErrorInvalidValue;
+        flops += 8.0 * nbe * ((double)rows * nbe + 2.0 * (double)rows * cols + (double)nbe * cols);
+        bytes += (double)sizeof(T) * (3.0 * (double)rows * cols + 2.0 * (double)rows * nbe);
     }
+    prof_end(eq, st, PK_UNGQR, bytes, flops);
     return hipGetLastError();
 }
 
-// Norms, perm and first pivot of a matrix already in d.A (no gate).
+// Norms, perm and first-pivot partials of a matrix already in d.A (no gate);
+// returns the number of argmax partials left for the first step.
 template <typename T>
-static void init_norms(UpdateWs<T>& w, hipStream_t st)
+static int init_norms(UpdateWs<T>& w, hipStream_t st)
 {
     QrcpDev<T>& d = w.d;
     hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, st, d.ctl, d.dsc);
-    if (d.n <= 0) return;
+    if (d.n <= 0) return 0;
     const unsigned nblk = (unsigned)rup(d.n, QR_CW);
     hipLaunchKernelGGL((k_colnorms<T>), dim3(nblk), dim3(256), 0, st, d, (int64_t)0, (int64_t)0, 1, 1);
-    hipLaunchKernelGGL((k_partials_final<T>), dim3(1), dim3(256), 0, st, d, (int)nblk, 1, (int)DSC_NORM2,
-                       (int64_t)0);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, (const double*)d.npart, (int)nblk, d.dsc,
+                       (int)DSC_NORM2);
+    return (int)nblk;
 }

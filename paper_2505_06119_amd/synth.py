@@ -135,6 +135,34 @@ def canonical_pair(r: np.random.Generator, chi_l: int, chi_m: int, chi_r: int,
     return np.ascontiguousarray(a), np.ascontiguousarray(b)
 
 
+def canonical_pair_device(r: np.random.Generator, chi_l: int, chi_m: int, chi_r: int, sigma: np.ndarray,
+                          device="cuda"):
+    """canonical_pair for large bonds, drawn on the GPU.
+
+    Same construction (and the same Gaussian draws from ``r``) as
+    canonical_pair, but the orthonormalisation of the Gaussian factors runs in
+    torch on ``device`` so that chi in the thousands takes seconds.  Returns
+    complex128 torch tensors in the library's site layout: shape
+    (chi_right, 2, chi_left), i.e. A[l, s, r] at l + chi_l*(s + 2r)."""
+    import torch
+
+    def iso(rows, cols):
+        z = torch.from_numpy(cgauss(r, (rows, cols))).to(device)
+        q, rr = torch.linalg.qr(z)
+        d = torch.diagonal(rr)
+        ph = d / torch.where(d.abs() == 0, torch.ones_like(d.abs()), d.abs())
+        return q * ph[None, :]
+
+    u = iso(2 * chi_l, chi_m)                        # rows l + chi_l*s, cols m
+    a_dev = u.transpose(0, 1).contiguous().reshape(chi_m, 2, chi_l)
+    w = iso(2 * chi_r, chi_m)
+    s = torch.from_numpy(np.asarray(sigma, dtype=np.float64) / np.linalg.norm(sigma)).to(device)
+    mm = s[:, None] * w.conj().transpose(0, 1)      # chi_m x (2 chi_r), cols s + 2r
+    b_dev = mm.transpose(0, 1).contiguous().reshape(chi_r, 2, chi_m)
+    del u, w, mm
+    return a_dev, b_dev
+
+
 def exp_spectrum(chi: int, scale: float) -> np.ndarray:
     """sigma_k = exp(-k/scale), k = 0..chi-1."""
     return np.exp(-np.arange(chi, dtype=np.float64) / scale)
