@@ -97,42 +97,63 @@ __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g)
 #pragma unroll
             for (int e = 0; e < 4; ++e) { acc_re[i][j][e] = 0; acc_im[i][j][e] = 0; }
 
-    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
-        // ---- stage op(A)[row0:row0+BM, k0:k0+BK] ----
-        constexpr int AEL = BM * BK / 256;
+    // The next K tile is loaded into registers while the current one is
+    // multiplied out of LDS.
+    constexpr int AEL = BM * BK / 256;
+    constexpr int BEL = BN * BK / 256;
+    T ra[AEL], rb[BEL];
+    auto load_tile = [&](int64_t k0) {
 #pragma unroll
         for (int q = 0; q < AEL; ++q) {
             int r, kk;
             if (!CA) { r = (tid + 256 * q) % BM; kk = (tid + 256 * q) / BM; }
             else     { kk = (tid + 256 * q) % BK; r = (tid + 256 * q) / BK; }
             const int64_t gr = row0 + r, gk = k0 + kk;
-            S vr = 0, vi = 0;
-            if (gr < g.M && gk < kend) {
-                T v = CA ? load_masked(A, g.lda, gk, gr, MA) : load_masked(A, g.lda, gr, gk, MA);
-                vr = v.x;
-                vi = CA ? -v.y : v.y;
-            }
-            As_re[kk][r] = vr;
-            As_im[kk][r] = vi;
+            T v;
+            v.x = 0;
+            v.y = 0;
+            if (gr < g.M && gk < kend)
+                v = CA ? load_masked(A, g.lda, gk, gr, MA) : load_masked(A, g.lda, gr, gk, MA);
+            ra[q] = v;
         }
-        // ---- stage op(B)[k0:k0+BK, col0:col0+BN] ----
-        constexpr int BEL = BN * BK / 256;
 #pragma unroll
         for (int q = 0; q < BEL; ++q) {
             int c, kk;
             if (!CB) { kk = (tid + 256 * q) % BK; c = (tid + 256 * q) / BK; }
             else     { c = (tid + 256 * q) % BN; kk = (tid + 256 * q) / BN; }
             const int64_t gc = col0 + c, gk = k0 + kk;
-            S vr = 0, vi = 0;
-            if (gc < g.N && gk < kend) {
-                T v = CB ? load_masked(B, g.ldb, gc, gk, MB) : load_masked(B, g.ldb, gk, gc, MB);
-                vr = v.x;
-                vi = CB ? -v.y : v.y;
-            }
-            Bs_re[kk][c] = vr;
-            Bs_im[kk][c] = vi;
+            T v;
+            v.x = 0;
+            v.y = 0;
+            if (gc < g.N && gk < kend)
+                v = CB ? load_masked(B, g.ldb, gc, gk, MB) : load_masked(B, g.ldb, gk, gc, MB);
+            rb[q] = v;
         }
+    };
+    auto store_tile = [&]() {
+#pragma unroll
+        for (int q = 0; q < AEL; ++q) {
+            int r, kk;
+            if (!CA) { r = (tid + 256 * q) % BM; kk = (tid + 256 * q) / BM; }
+            else     { kk = (tid + 256 * q) % BK; r = (tid + 256 * q) / BK; }
+            As_re[kk][r] = ra[q].x;
+            As_im[kk][r] = CA ? -ra[q].y : ra[q].y;
+        }
+#pragma unroll
+        for (int q = 0; q < BEL; ++q) {
+            int c, kk;
+            if (!CB) { kk = (tid + 256 * q) % BK; c = (tid + 256 * q) / BK; }
+            else     { c = (tid + 256 * q) % BN; kk = (tid + 256 * q) / BN; }
+            Bs_re[kk][c] = rb[q].x;
+            Bs_im[kk][c] = CB ? -rb[q].y : rb[q].y;
+        }
+    };
+
+    if (kbeg < kend) load_tile(kbeg);
+    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+        store_tile();
         __syncthreads();
+        if (k0 + BK < kend) load_tile(k0 + BK);
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 4) {
             const int kk = ks + (lane >> 4);
@@ -161,16 +182,28 @@ __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g)
         __syncthreads();
     }
 
-    // ---- epilogue: lane holds C[row = .. + lane%16][col = .. + drow(lane, e)] ----
+    // ---- epilogue: lane holds C[row = .. + lane%16][col = .. + drow(lane, e)];
+    //      the C loads of one row block are issued together ----
     T* C = (T*)g.C;
     T* P = (T*)g.part;
+    const bool use_beta = (g.beta.x != 0.0 || g.beta.y != 0.0) && !P;
 #pragma unroll
-    for (int i = 0; i < WM; ++i)
+    for (int i = 0; i < WM; ++i) {
+        const int64_t r = row0 + wr + 16 * i + (lane & 15);
+        T cv[WN][4];
+        if (use_beta) {
+#pragma unroll
+            for (int j = 0; j < WN; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int64_t c = col0 + wc + 16 * j + MfmaOps<T>::drow(lane, e);
+                    if (r < g.M && c < g.N) cv[j][e] = C[r + g.ldc * c];
+                }
+        }
 #pragma unroll
         for (int j = 0; j < WN; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int64_t r = row0 + wr + 16 * i + (lane & 15);
                 const int64_t c = col0 + wc + 16 * j + MfmaOps<T>::drow(lane, e);
                 if (r >= g.M || c >= g.N) continue;
                 double2 v = make_double2((double)acc_re[i][j][e], (double)acc_im[i][j][e]);
@@ -178,11 +211,11 @@ __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g)
                     P[(int64_t)blockIdx.z * g.M * g.N + r + g.M * c] = from_d<T>(v);
                 } else {
                     v = cmul(g.alpha, v);
-                    if (g.beta.x != 0.0 || g.beta.y != 0.0)
-                        v = cadd(v, cmul(g.beta, to_d(C[r + g.ldc * c])));
+                    if (use_beta) v = cadd(v, cmul(g.beta, to_d(cv[j][e])));
                     C[r + g.ldc * c] = from_d<T>(v);
                 }
             }
+    }
 }
 
 // Sum split-K partial products in a fixed order (FP64) and apply alpha/beta.
@@ -231,7 +264,9 @@ static void launch_gemm_t(GemmArgs g, hipStream_t st, void* scratch, int64_t scr
 {
     if (g.M <= 0 || g.N <= 0) return;
     constexpr int BWM = GemmTile<T>::WM, BWN = GemmTile<T>::WN;
-    const bool big = g.M >= 512 && g.N >= 512;
+    // Large tiles only pay off for long K; a rank-k update with k <= 64 is
+    // memory-bound and wants many resident blocks to overlap C traffic.
+    const bool big = g.M >= 512 && g.N >= 512 && g.K > 64;
     const int64_t BM = big ? 32 * BWM : 64, BN = big ? 32 * BWN : 64;
     const int64_t tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
     int nz = 1;

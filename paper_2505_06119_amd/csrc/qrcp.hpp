@@ -37,7 +37,7 @@
 #include "common.hpp"
 
 #define QR_NBMAX 64
-#define QR_CW 8            // columns per block in step C and the norm kernel
+#define QR_CW 4            // columns per block in step C and the norm kernel
 
 enum {
     CTL_PIV = 0,      // pivot position of the current step (written by step A)
@@ -116,10 +116,26 @@ __global__ __launch_bounds__(256) void k_step_a(QrcpDev<T> d, int64_t j, int64_t
         b.key = 0x7fffffff;
         b.slot = -1;
         double fl = 0.0;
-        for (int q = tid; q < nparts; q += 256) {
-            const ArgBest e = d.cpart[q];
-            if (e.slot >= 0 && arg_better(e.val, e.key, b.val, b.key)) b = e;
-            fl += d.cflag[q] ? 1.0 : 0.0;
+        for (int q0 = 0; q0 < nparts; q0 += 256 * 8) {
+            // issue up to 8 partial loads per thread before using any
+            ArgBest e[8];
+            int32_t f[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int q = q0 + tid + 256 * u;
+                if (q < nparts) {
+                    e[u] = d.cpart[q];
+                    f[u] = d.cflag[q];
+                } else {
+                    e[u].slot = -1;
+                    f[u] = 0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (e[u].slot >= 0 && arg_better(e[u].val, e[u].key, b.val, b.key)) b = e[u];
+                fl += f[u] ? 1.0 : 0.0;
+            }
         }
         b = block_argmax256(b, arg_lds);
         fl = block_sum256(fl, red_lds);
@@ -158,8 +174,16 @@ __global__ __launch_bounds__(256) void k_step_a(QrcpDev<T> d, int64_t j, int64_t
         }
         if (i >= j) {
             x = to_d(ap);
-            for (int t = 0; t < jj; ++t)
-                x = csub(x, cmul(to_d(d.A[i + d.lda * (p0 + t)]), cconj(fp[t])));
+            // V row loads issued 8 at a time so their latencies overlap
+            for (int t0 = 0; t0 < jj; t0 += 8) {
+                T vr[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (t0 + u < jj) vr[u] = d.A[i + d.lda * (p0 + t0 + u)];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (t0 + u < jj) x = csub(x, cmul(to_d(vr[u]), cconj(fp[t0 + u])));
+            }
             d.xbuf[i] = x;
             d.xlo[i] = from_d<T>(x);
             has = true;
@@ -328,12 +352,33 @@ __global__ __launch_bounds__(256) void k_step_c(QrcpDev<T> d, int64_t j, int64_t
     const double beta = s_par[0].x;
     const double2 tau = s_par[1], scale = s_par[2];
     const int64_t p = d.pivoting ? (int64_t)d.ctl[CTL_PIV] : j;
+    const int64_t cbase = j + 1 + (int64_t)blockIdx.x * QR_CW;
+
+    // ---- stage this block's F rows and column scalars in LDS; the loads
+    //      complete while the GEMV streams the trailing block ----
+    __shared__ double2 s_f[QR_CW][QR_NBMAX];
+    __shared__ double2 s_arow[QR_CW];
+    __shared__ double s_nu[QR_CW], s_nuref[QR_CW];
+    __shared__ int32_t s_perm[QR_CW];
+    for (int q = tid; q < QR_CW * jj; q += 256) {
+        const int u = q % QR_CW, t = q / QR_CW;
+        const int64_t c = cbase + u;
+        if (c < cend) s_f[u][t] = (d.pivoting && c == p && p != j) ? d.fsave[t] : to_d(d.F[c + d.ldf * t]);
+    }
+    if (tid < QR_CW && cbase + tid < cend) {
+        const int64_t c = cbase + tid;
+        s_arow[tid] = to_d(d.A[j + d.lda * c]);
+        if (d.pivoting) {
+            s_nu[tid] = d.nu[c];
+            s_nuref[tid] = d.nuref[c];
+            s_perm[tid] = d.perm[c];
+        }
+    }
 
     // ---- GEMV: g_u = sum_{i>j} conj(A[i, c_u]) x_i ----
-    const int64_t cbase = j + 1 + (int64_t)blockIdx.x * QR_CW;
     double acc[2 * QR_CW];
     gemv_cols<T, QR_CW>(d, j, cbase, cend, acc);
-    block_sum_vec<2 * QR_CW>(acc, red_lds, red_out);
+    block_sum_vec<2 * QR_CW>(acc, red_lds, red_out);   // ends with a barrier: LDS staging visible
 
     // ---- per-column scalar work (one thread per column) ----
     ArgBest best;
@@ -346,11 +391,11 @@ __global__ __launch_bounds__(256) void k_step_c(QrcpDev<T> d, int64_t j, int64_t
         if (c < cend) {
             const bool moved = d.pivoting && c == p && p != j;
             const double2 g = make_double2(red_out[2 * tid], red_out[2 * tid + 1]);
-            const double2 ajc = to_d(d.A[j + d.lda * c]);
+            const double2 ajc = s_arow[tid];
             double2 w = cadd(cconj(ajc), cmul(scale, g));
             double2 corr = czero(), rrow = ajc;
             for (int t = 0; t < jj; ++t) {
-                const double2 f = moved ? d.fsave[t] : to_d(d.F[c + d.ldf * t]);
+                const double2 f = s_f[tid][t];
                 corr = cadd(corr, cmul(f, s_aux[t]));
                 rrow = csub(rrow, cmul(s_vj[t], cconj(f)));
                 if (moved) d.F[c + d.ldf * t] = from_d<T>(f);
@@ -361,15 +406,15 @@ __global__ __launch_bounds__(256) void k_step_c(QrcpDev<T> d, int64_t j, int64_t
             rrow = csub(rrow, cconj(fnew));
             d.A[j + d.lda * c] = from_d<T>(rrow);
             if (d.pivoting) {
-                double nn = d.nu[c] - cabs2(rrow);
+                double nn = s_nu[tid] - cabs2(rrow);
                 if (nn < 0.0) nn = 0.0;
-                const bool flag = nn <= d.tol * d.nuref[c];
+                const bool flag = nn <= d.tol * s_nuref[tid];
                 d.nu[c] = nn;
                 if (flag) {
                     flagged = 1.0;
                 } else {
                     best.val = nn;
-                    best.key = d.perm[c];
+                    best.key = s_perm[tid];
                     best.slot = (int32_t)c;
                 }
             }
