@@ -65,7 +65,31 @@ typedef struct {
     int32_t panels;       /* QR panels processed                                     */
     int32_t refreshes;    /* exact recomputations of the residual column norms       */
     int32_t pad;
+    double learned_err_sq;/* learned pivots: ||R22||^2 of the proposed order (-1: n/a) */
+    double qrcp_err_sq;   /* ||R22||^2 of plain pivoted QR when it ran (-1: n/a)      */
 } mps_update_info;
+
+/* Learned pivot proposal (spec addition, not in the paper): a Gaussian
+ * sketch Y = Omega theta (sketch_rows x n, Omega from a SplitMix64 counter
+ * generator seeded with `seed`), per-column sketch features, and a small
+ * network (MPS_PIVNET_PARAMS float32 parameters: 4 features -> 16 tanh units
+ * -> 1 score) rank the columns; the pivoted QR then runs with that column order
+ * fixed.  Acceptance:
+ *   verify = 0  certificate: every unselected column's residual norm is at most
+ *               the smallest |R_jj| of the selected ones (what plain pivoted QR
+ *               guarantees by construction);
+ *   verify = 1  plain pivoted QR also runs and the proposal is kept only if
+ *               its truncation error is at most fallback_ratio times QRCP's.
+ * A rejected proposal falls back to plain pivoted QR of the same theta. */
+#define MPS_PIVNET_PARAMS 97
+#define MPS_PIVNET_FEATURES 4
+typedef struct {
+    const float* params;   /* device, MPS_PIVNET_PARAMS floats */
+    int32_t sketch_rows;   /* 1..256 */
+    int32_t verify;        /* 0 or 1, see above */
+    uint64_t seed;
+    double fallback_ratio; /* >= 1, e.g. 1.01 */
+} mps_learned_cfg;
 
 const char* mps_last_error(void);
 
@@ -106,19 +130,49 @@ mps_status qrcp_truncate(int64_t m, int64_t n, int64_t k_max, mps_precision prec
  *
  *   A, B        device, read-only sites (chi_l x 2 x chi_m, chi_m x 2 x chi_r).
  *   g           host, 32 doubles (4x4 complex, see conventions).
- *   A_out       device, room for chi_l*2*k elements; may not alias A or B.
- *   B_out       device, room for k*2*chi_r elements; may not alias A or B.
+ *   A_out       device, room for chi_l*2*k elements.
+ *   B_out       device, room for k*2*chi_r elements; must not overlap A_out.
+ *               theta is formed in the workspace first, so the outputs may
+ *               alias the input sites.
+ *   learned     host, required for pivot = MPS_PIVOT_LEARNED, else ignored.
  *   info        host, may be NULL.
  *   work        device scratch of at least mps_update_work_bytes(...) bytes.
- * pivot = MPS_PIVOT_LEARNED is accepted only through a context with a
- * trained proposal network; here it returns MPS_EINVAL.
  * ------------------------------------------------------------------------ */
 int64_t mps_update_work_bytes(int64_t chi_l, int64_t chi_m, int64_t chi_r, int64_t chi_cap,
                               mps_precision prec, mps_pivot pivot);
 mps_status mps_update_bond(int64_t chi_l, int64_t chi_m, int64_t chi_r, int64_t chi_cap,
                            mps_precision prec, mps_pivot pivot, const void* A, const void* B,
                            const double* g, void* A_out, void* B_out, int renormalize,
-                           mps_update_info* info, void* work, int64_t work_bytes, void* hip_stream);
+                           const mps_learned_cfg* learned, mps_update_info* info, void* work,
+                           int64_t work_bytes, void* hip_stream);
+
+/* theta = G (A B) of the two-site update (steps before the factorisation),
+ * written column-major (2 chi_l) x (2 chi_r) into the device buffer theta
+ * (ld >= 2 chi_l).  work: at least mps_update_work_bytes(chi_l, chi_m, chi_r,
+ * 1, prec, MPS_PIVOT_QRCP) bytes. */
+mps_status mps_theta(int64_t chi_l, int64_t chi_m, int64_t chi_r, mps_precision prec, const void* A,
+                     const void* B, const double* g, void* theta, int64_t ld, void* work, int64_t work_bytes,
+                     void* hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Pivot-proposal network: the pieces of the learned path, exposed for
+ * training and testing.  All arrays are device memory; phi is n x 4 float32
+ * (row c = features of column c), scores n float32, labels n bytes (1 = the
+ * column is among plain pivoted QR's first k pivots), grad MPS_PIVNET_PARAMS+1
+ * float32 (gradient of the mean logistic loss, then the loss itself).
+ * ------------------------------------------------------------------------ */
+int64_t pivnet_work_bytes(int64_t m, int64_t n, int32_t sketch_rows, mps_precision prec);
+mps_status pivnet_features(int64_t m, int64_t n, mps_precision prec, const void* theta, int64_t ld,
+                           int32_t sketch_rows, uint64_t seed, float* phi, void* work, int64_t work_bytes,
+                           void* hip_stream);
+mps_status pivnet_forward(const float* params, const float* phi, int64_t n, float* scores, void* hip_stream);
+mps_status pivnet_grad(const float* params, const float* phi, const uint8_t* labels, int64_t n, float* grad,
+                       void* work, int64_t work_bytes, void* hip_stream);
+/* Adam step on params with moment buffers m1, m2 (MPS_PIVNET_PARAMS each); t >= 1. */
+mps_status pivnet_adam(float* params, const float* grad, float* m1, float* m2, int32_t t, float lr,
+                       void* hip_stream);
+/* order[r] = column with the r-th largest score (ties: smaller column first). */
+mps_status pivnet_rank(const float* scores, int64_t n, int32_t* order, void* hip_stream);
 
 /* ------------------------------------------------------------------------
  * Stateful MPS of n_sites qubits in the product state |0...0> (all bond
@@ -148,6 +202,12 @@ int64_t mps_arena_bytes(const mps_config* cfg);
 mps_status mps_create(const mps_config* cfg, void* dev_arena, int64_t arena_bytes, void* hip_stream,
                       mps_ctx** out);
 mps_status mps_destroy(mps_ctx* ctx);
+
+/* For a context created with pivot = MPS_PIVOT_LEARNED: the proposal network
+ * and acceptance policy used by every later update (cfg is copied; the
+ * parameter buffer it points to must stay valid).  Updates fail with
+ * MPS_EINVAL until it has been set. */
+mps_status mps_set_pivot_network(mps_ctx* ctx, const mps_learned_cfg* cfg);
 
 /* Apply the 4x4 gate g (host, 32 doubles) to sites (i, i+1), 0 <= i < n-1:
  * the orthogonality centre is first moved to site i (or to i+1 when it lies
@@ -196,7 +256,8 @@ typedef enum {
     MPS_K_NORMS = 5,    /* exact norm recomputation and ||R22||_F             */
     MPS_K_UNGQR = 6,    /* Q_k formation (MFMA)                               */
     MPS_K_SPLIT = 7,    /* R_k P^T scatter into the right site                */
-    MPS_K_COUNT = 8
+    MPS_K_PROPOSE = 8,  /* learned proposal: sketch, features, scores, order  */
+    MPS_K_COUNT = 9
 } mps_kernel_class;
 
 typedef struct {

@@ -142,120 +142,8 @@ extern "C" mps_status qrcp_truncate(int64_t m, int64_t n, int64_t k_max, mps_pre
                              work_bytes, st);
 }
 
-// ---------------------------------------------------------------------------
-// two-site update core (shared by mps_update_bond and the context)
-// ---------------------------------------------------------------------------
-static bool gate_finite(const double* g)
-{
-    for (int q = 0; q < 32; ++q)
-        if (!isfinite(g[q])) return false;
-    return true;
-}
-
-static Gate4 make_gate(const double* g)
-{
-    Gate4 G;
-    for (int q = 0; q < 16; ++q) G.g[q] = make_double2(g[2 * q], g[2 * q + 1]);
-    return G;
-}
-
-// theta is formed in the workspace before any output is written, so the
-// outputs may alias the input sites.
-template <typename T>
-static mps_status update_core(int64_t chi_l, int64_t chi_m, int64_t chi_r, int64_t chi_cap, mps_precision prec,
-                              const T* A, const T* B, const double* g, T* A_out, T* B_out, int renorm,
-                              mps_update_info* info, void* work, int64_t work_bytes, hipStream_t st)
-{
-    const int64_t m = 2 * chi_l, n = 2 * chi_r;
-    int64_t k = chi_cap < m ? chi_cap : m;
-    k = k < n ? k : n;
-    Carver cv{(char*)work, work_bytes, 0};
-    UpdateWs<T> w;
-    if (!carve_update_ws<T>(cv, w, m, n, k, true)) return fail(MPS_ENOMEM, "update: workspace too small");
-    w.nb = panel_width(m, n);
-    w.d.tol = recompute_tol(prec);
-    w.d.pivoting = 1;
-    QrcpDev<T>& d = w.d;
-
-    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, st, d.ctl, d.dsc);
-    // a1: theta0 = A_mat (m x chi_m) * B_mat (chi_m x n)
-    hipEvent_t e1 = prof_begin(st);
-    if (!zgemm<T>(st, OP_N, false, OP_N, false, m, n, chi_m, C_ONE, A, m, B, chi_m, C_ZERO, d.A, d.lda, w.gsplit,
-                  w.gsplit_bytes))
-        return fail(MPS_EINVAL, "update: gemm form unavailable");
-    prof_end(e1, st, PK_CONTRACT, (double)sizeof(T) * ((double)m * chi_m + (double)chi_m * n + (double)m * n),
-             8.0 * (double)m * (double)n * (double)chi_m);
-    // a2 + a3
-    hipEvent_t e2 = prof_begin(st);
-    hipLaunchKernelGGL((k_gate_norms<T>), dim3((unsigned)chi_r), dim3(256), 0, st, d, chi_l, make_gate(g));
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, (const double*)d.npart, (int)chi_r, d.dsc,
-                       (int)DSC_NORM2);
-    prof_end(e2, st, PK_GATE, 2.0 * sizeof(T) * (double)m * (double)n, 64.0 * (double)m * (double)n / 4.0);
-    HIPCHK(hipGetLastError(), "update launch");
-    QrcpStats stats;
-    HIPCHK(run_qrcp<T>(w, st, &stats, (int)chi_r), "update factorisation");
-    HIPCHK(form_q<T>(w, A_out, m, st), "update Q");
-    hipEvent_t e3 = prof_begin(st);
-    hipLaunchKernelGGL((k_rpt<T>), dim3((unsigned)n), dim3(256), 0, st, (const T*)d.A, d.lda,
-                       (const int32_t*)d.perm, k, n, B_out, k, (const double*)d.dsc, renorm);
-    prof_end(e3, st, PK_SPLIT, 2.0 * sizeof(T) * (double)k * (double)n, 0.0);
-    double dsc[DSC_COUNT];
-    HIPCHK(hipMemcpyAsync(dsc, d.dsc, sizeof(dsc), hipMemcpyDeviceToHost, st), "update readback");
-    HIPCHK(hipStreamSynchronize(st), "update sync");
-    prof_flush();
-    if (!isfinite(dsc[DSC_NORM2]) || !isfinite(dsc[DSC_EPS2]))
-        return fail(MPS_ENUMERIC, "update: non-finite theta");
-    if (info) {
-        info->k = k;
-        info->trunc_err_sq = dsc[DSC_EPS2];
-        info->norm_sq = dsc[DSC_NORM2];
-        info->retained = dsc[DSC_NORM2] > 0 ? 1.0 - dsc[DSC_EPS2] / dsc[DSC_NORM2] : 1.0;
-        info->fallback = 0;
-        info->panels = stats.panels;
-        info->refreshes = stats.refreshes;
-        info->pad = 0;
-    }
-    return MPS_OK;
-}
-
-extern "C" int64_t mps_update_work_bytes(int64_t chi_l, int64_t chi_m, int64_t chi_r, int64_t chi_cap,
-                                         mps_precision prec, mps_pivot pivot)
-{
-    (void)chi_m;
-    if (chi_l < 1 || chi_r < 1 || chi_cap < 1 || !valid_prec(prec) || pivot != MPS_PIVOT_QRCP) return -1;
-    const int64_t m = 2 * chi_l, n = 2 * chi_r;
-    int64_t k = chi_cap < m ? chi_cap : m;
-    k = k < n ? k : n;
-    int64_t b = prec == MPS_FP64 ? update_ws_bytes<double2>(m, n, k) : update_ws_bytes<float2>(m, n, k);
-    // split-K scratch for the contraction when chi_m is long and theta small
-    return b + 16 * elem_bytes(prec) * (m * n + 64);
-}
-
-extern "C" mps_status mps_update_bond(int64_t chi_l, int64_t chi_m, int64_t chi_r, int64_t chi_cap,
-                                      mps_precision prec, mps_pivot pivot, const void* A, const void* B,
-                                      const double* g, void* A_out, void* B_out, int renormalize,
-                                      mps_update_info* info, void* work, int64_t work_bytes, void* hip_stream)
-{
-    if (chi_l < 1 || chi_m < 1 || chi_r < 1 || chi_cap < 1)
-        return fail(MPS_EINVAL, "mps_update_bond: dimensions must be >= 1");
-    if (chi_l > (1 << 19) || chi_r > (1 << 19) || chi_m > (1 << 20))
-        return fail(MPS_EINVAL, "mps_update_bond: dimension too large");
-    if (!valid_prec(prec)) return fail(MPS_EINVAL, "mps_update_bond: bad precision %d", (int)prec);
-    if (pivot != MPS_PIVOT_QRCP)
-        return fail(MPS_EINVAL, "mps_update_bond: learned pivots need a context with a trained network");
-    if (!A || !B || !g || !A_out || !B_out || !work) return fail(MPS_EINVAL, "mps_update_bond: null pointer");
-    if (!gate_finite(g)) return fail(MPS_ENUMERIC, "mps_update_bond: non-finite gate entry");
-    const int64_t need = mps_update_work_bytes(chi_l, chi_m, chi_r, chi_cap, prec, pivot);
-    if (work_bytes < need)
-        return fail(MPS_ENOMEM, "mps_update_bond: need %lld work bytes, got %lld", (long long)need,
-                    (long long)work_bytes);
-    hipStream_t st = (hipStream_t)hip_stream;
-    if (prec == MPS_FP64)
-        return update_core<double2>(chi_l, chi_m, chi_r, chi_cap, prec, (const double2*)A, (const double2*)B, g,
-                                    (double2*)A_out, (double2*)B_out, renormalize, info, work, work_bytes, st);
-    return update_core<float2>(chi_l, chi_m, chi_r, chi_cap, prec, (const float2*)A, (const float2*)B, g,
-                               (float2*)A_out, (float2*)B_out, renormalize, info, work, work_bytes, st);
-}
+// two-site update, learned proposal entry points
+#include "bond.hpp"
 
 // stateful MPS context
 #include "context.hpp"

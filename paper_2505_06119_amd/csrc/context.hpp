@@ -68,6 +68,8 @@ struct mps_ctx {
     int32_t centre;
     double log_fid;
     bool poisoned;
+    bool has_net;          // pivot network set (learned mode)
+    mps_learned_cfg lcfg;
 };
 
 static int64_t max_bond(int n, int b, int64_t chi)
@@ -106,6 +108,9 @@ static bool ctx_layout(const mps_config* cfg, CtxLayout& L)
     L.ws_bytes = (cfg->prec == MPS_FP64 ? update_ws_bytes<double2>(m, m, L.dmax)
                                         : update_ws_bytes<float2>(m, m, L.dmax)) +
                  16 * eb * (m * m + 64);
+    if (cfg->pivot == MPS_PIVOT_LEARNED)
+        L.ws_bytes += cfg->prec == MPS_FP64 ? learn_ws_bytes<double2>(m, m, L.dmax, PN_ELL_MAX)
+                                            : learn_ws_bytes<float2>(m, m, L.dmax, PN_ELL_MAX);
     pos += (L.ws_bytes + 255) / 256 * 256;
     L.tmp_off = pos;
     pos += (maxcap * eb + 255) / 256 * 256;
@@ -120,7 +125,7 @@ static bool ctx_layout(const mps_config* cfg, CtxLayout& L)
 static bool cfg_valid(const mps_config* cfg)
 {
     return cfg && cfg->n_sites >= 2 && cfg->n_sites <= 4096 && cfg->chi_max >= 1 && cfg->chi_max <= (1 << 16) &&
-           valid_prec(cfg->prec) && (cfg->pivot == MPS_PIVOT_QRCP);
+           valid_prec(cfg->prec) && (cfg->pivot == MPS_PIVOT_QRCP || cfg->pivot == MPS_PIVOT_LEARNED);
 }
 
 extern "C" int64_t mps_arena_bytes(const mps_config* cfg)
@@ -148,8 +153,6 @@ extern "C" mps_status mps_create(const mps_config* cfg, void* dev_arena, int64_t
 {
     if (!out) return fail(MPS_EINVAL, "mps_create: out is NULL");
     *out = nullptr;
-    if (cfg && cfg->pivot == MPS_PIVOT_LEARNED)
-        return fail(MPS_EINVAL, "mps_create: learned pivots are not available in this build");
     if (!cfg_valid(cfg)) return fail(MPS_EINVAL, "mps_create: invalid configuration");
     if (!dev_arena) return fail(MPS_EINVAL, "mps_create: arena is NULL");
     CtxLayout L;
@@ -177,6 +180,7 @@ extern "C" mps_status mps_create(const mps_config* cfg, void* dev_arena, int64_t
     c->centre = 0;
     c->log_fid = 0.0;
     c->poisoned = false;
+    c->has_net = false;
     mps_status s = c->prec == MPS_FP64 ? ctx_init_sites<double2>(c) : ctx_init_sites<float2>(c);
     if (s != MPS_OK) {
         delete c;
@@ -286,14 +290,26 @@ static mps_status ctx_apply_gate(mps_ctx* c, int i, const double* g, mps_update_
         if (r != MPS_OK) return r;
     }
     mps_update_info loc;
+    const mps_learned_cfg* lc = c->cfg.pivot == MPS_PIVOT_LEARNED ? &c->lcfg : nullptr;
     mps_status r = update_core<T>(c->dims[i], c->dims[i + 1], c->dims[i + 2], c->chi_max, c->prec,
                                   (const T*)c->site[i], (const T*)c->site[i + 1], g, (T*)c->site[i],
-                                  (T*)c->site[i + 1], 1, &loc, c->ws, c->ws_bytes, c->st);
+                                  (T*)c->site[i + 1], 1, lc, &loc, c->ws, c->ws_bytes, c->st);
     if (r != MPS_OK) return r;
     c->dims[i + 1] = loc.k;
     c->centre = i + 1;
     if (loc.retained > 0) c->log_fid += log(loc.retained);
     if (info) *info = loc;
+    return MPS_OK;
+}
+
+extern "C" mps_status mps_set_pivot_network(mps_ctx* ctx, const mps_learned_cfg* cfg)
+{
+    if (!ctx) return fail(MPS_EINVAL, "mps_set_pivot_network: NULL context");
+    if (ctx->cfg.pivot != MPS_PIVOT_LEARNED)
+        return fail(MPS_EINVAL, "mps_set_pivot_network: context was not created for learned pivots");
+    if (!learned_cfg_valid(cfg)) return fail(MPS_EINVAL, "mps_set_pivot_network: invalid mps_learned_cfg");
+    ctx->lcfg = *cfg;
+    ctx->has_net = true;
     return MPS_OK;
 }
 
@@ -311,6 +327,8 @@ extern "C" mps_status mps_apply_gate(mps_ctx* ctx, int32_t i, const double* g, m
     if (i < 0 || i >= ctx->n - 1) return fail(MPS_EINVAL, "mps_apply_gate: bond %d out of range", (int)i);
     if (!g) return fail(MPS_EINVAL, "mps_apply_gate: NULL gate");
     if (!gate_finite(g)) return fail(MPS_ENUMERIC, "mps_apply_gate: non-finite gate entry");
+    if (ctx->cfg.pivot == MPS_PIVOT_LEARNED && !ctx->has_net)
+        return fail(MPS_EINVAL, "mps_apply_gate: learned pivots need mps_set_pivot_network first");
     s = ctx->prec == MPS_FP64 ? ctx_apply_gate<double2>(ctx, i, g, info) : ctx_apply_gate<float2>(ctx, i, g, info);
     if (s == MPS_EDEVICE) ctx->poisoned = true;
     return s;
@@ -322,6 +340,8 @@ extern "C" mps_status mps_apply_layer(mps_ctx* ctx, int64_t n, const int32_t* id
     mps_status s = ctx_check(ctx);
     if (s != MPS_OK) return s;
     if (n < 0 || (n > 0 && (!idx || !g))) return fail(MPS_EINVAL, "mps_apply_layer: bad arrays");
+    if (ctx->cfg.pivot == MPS_PIVOT_LEARNED && !ctx->has_net)
+        return fail(MPS_EINVAL, "mps_apply_layer: learned pivots need mps_set_pivot_network first");
     for (int64_t t = 0; t < n; ++t) {
         if (idx[t] < 0 || idx[t] >= ctx->n - 1)
             return fail(MPS_EINVAL, "mps_apply_layer: bond %d out of range", (int)idx[t]);

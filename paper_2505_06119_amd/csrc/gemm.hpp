@@ -276,7 +276,8 @@ static void launch_gemm_t(GemmArgs g, hipStream_t st, void* scratch, int64_t scr
         nz = (int)(want < maxz ? want : maxz);
         if (nz > 16) nz = 16;
         if (nz < 1) nz = 1;
-        if ((int64_t)nz * g.M * g.N * (int64_t)sizeof(T) > scratch_bytes) nz = 1;
+        const int64_t fit = scratch_bytes / (g.M * g.N * (int64_t)sizeof(T));
+        if (nz > fit) nz = (int)(fit > 1 ? fit : 1);
     }
     if (nz > 1) {
         int64_t chunk = (g.K + nz - 1) / nz;

@@ -16,7 +16,8 @@ enum {
     PK_NORMS = 5,     // exact norm recomputation / ||R22||
     PK_UNGQR = 6,     // Q formation
     PK_SPLIT = 7,     // R P^T scatter
-    PK_COUNT = 8
+    PK_PROPOSE = 8,   // learned proposal: sketch, features, scores, order, gather
+    PK_COUNT = 9
 };
 
 struct ProfAcc {

@@ -211,9 +211,11 @@ static bool carve_update_ws(Carver& cv, UpdateWs<T>& w, int64_t m, int64_t n, in
     d.dsc = (double*)cv.take(8 * DSC_COUNT);
     w.Gbuf = (T*)cv.take((int64_t)sizeof(T) * UNGQR_NB * UNGQR_NB);
     w.Tbuf = (T*)cv.take((int64_t)sizeof(T) * UNGQR_NB * UNGQR_NB);
-    w.Wbuf = (T*)cv.take((int64_t)sizeof(T) * UNGQR_NB * (k + 1));
-    w.W2buf = (T*)cv.take((int64_t)sizeof(T) * UNGQR_NB * (k + 1));
-    const int64_t sk = (int64_t)sizeof(T) * 16 * UNGQR_NB * (k > UNGQR_NB ? k : UNGQR_NB);
+    // W / W2 hold nb x (columns right of a panel): up to n (blocked QR) or k (UNGQR)
+    const int64_t wcols = (n > k ? n : k) + 1;
+    w.Wbuf = (T*)cv.take((int64_t)sizeof(T) * UNGQR_NB * wcols);
+    w.W2buf = (T*)cv.take((int64_t)sizeof(T) * UNGQR_NB * wcols);
+    const int64_t sk = (int64_t)sizeof(T) * 16 * UNGQR_NB * (wcols > UNGQR_NB ? wcols : UNGQR_NB);
     w.gsplit = cv.take(sk);
     w.gsplit_bytes = sk;
     return d.nu && d.nuref && d.perm && d.F && d.tau && d.diagR && d.xbuf && d.xlo && d.apart && d.hh && d.fsave &&
@@ -232,12 +234,74 @@ struct QrcpStats {
 
 // a4-a10 on d.A; expects nu/nuref/perm/ctl[PIV] set up (pivoting) and the
 // control block reset.  Synchronises the stream once per panel.
+// Householder QR of d.A with the columns in their given order (a centre move,
+// or pivoted QR with a pivot order known in advance).  Only the panel's own
+// columns go through the per-column steps; the trailing columns receive the
+// panel's block reflector I - V T V^H at the panel end, as three MFMA GEMMs
+//     W = V^H A_t,  W2 = T^H W,  A_t -= V W2      (A_t = A[p0:, pend:]).
+// Nothing depends on data on the host, so no synchronisation is needed.
+template <typename T>
+static hipError_t run_blocked_fixed(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats)
+{
+    QrcpDev<T>& d = w.d;
+    const int64_t m = d.m, n = d.n, k = d.k;
+    const int nb = w.nb < UNGQR_NB ? w.nb : UNGQR_NB;
+    const unsigned na = (unsigned)rup(m, 256);
+    hipLaunchKernelGGL(k_ctl_panel, dim3(1), dim3(64), 0, st, d.ctl, (int32_t)0);
+    for (int64_t p0 = 0; p0 < k; p0 += nb) {
+        const int64_t pend = (p0 + nb < k) ? p0 + nb : k;
+        const int nbe = (int)(pend - p0);
+        for (int64_t jc = p0; jc < pend; ++jc) {
+            const int jj = (int)(jc - p0);
+            hipEvent_t ea = prof_begin(st);
+            hipLaunchKernelGGL((k_step_a<T>), dim3(na), dim3(256), 0, st, d, jc, p0, jj, 0);
+            prof_end(ea, st, PK_STEP_A, (double)sizeof(T) * (double)(m - jc) * (jj + 1), 8.0 * (m - jc) * jj);
+            const int64_t ncol = pend - jc - 1;
+            const unsigned nc = (unsigned)(ncol > 0 ? rup(ncol, QR_CW) : 1);
+            hipEvent_t ec = prof_begin(st);
+            hipLaunchKernelGGL((k_step_c<T>), dim3(nc), dim3(256), 0, st, d, jc, p0, jj, pend, (int)na);
+            prof_end(ec, st, PK_STEP_C, (double)sizeof(T) * (double)(m - jc) * (double)(ncol > 0 ? ncol : 0),
+                     8.0 * (double)(m - jc) * (double)(ncol > 0 ? ncol : 0));
+        }
+        if (stats) stats->panels++;
+        if (pend >= n) continue;
+        const T* V = d.A + p0 + d.lda * p0;
+        const int64_t rows = m - p0, cols = n - pend;
+        T* At = d.A + p0 + d.lda * pend;
+        hipEvent_t et = prof_begin(st);
+        if (!zgemm<T>(st, OP_C, true, OP_N, true, nbe, nbe, rows, C_ONE, V, d.lda, V, d.lda, C_ZERO, w.Gbuf,
+                      UNGQR_NB, w.gsplit, w.gsplit_bytes))
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_larft<T>), dim3(1), dim3(64), 0, st, w.Gbuf, d.tau + p0, nbe, w.Tbuf);
+        if (!zgemm<T>(st, OP_C, true, OP_N, false, nbe, cols, rows, C_ONE, V, d.lda, At, d.lda, C_ZERO, w.Wbuf,
+                      UNGQR_NB, w.gsplit, w.gsplit_bytes))
+            return hipErrorInvalidValue;
+        if (!zgemm<T>(st, OP_C, false, OP_N, false, nbe, cols, nbe, C_ONE, w.Tbuf, UNGQR_NB, w.Wbuf, UNGQR_NB,
+                      C_ZERO, w.W2buf, UNGQR_NB, nullptr, 0))
+            return hipErrorInvalidValue;
+        if (!zgemm<T>(st, OP_N, true, OP_N, false, rows, cols, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, C_ONE,
+                      At, d.lda, nullptr, 0))
+            return hipErrorInvalidValue;
+        const double rc = (double)rows * (double)cols;
+        prof_end(et, st, PK_TRAIL, (double)sizeof(T) * 3.0 * rc, 8.0 * nbe * (2.0 * rc + (double)nbe * cols));
+    }
+    // a10: ||R22||_F^2 over the final trailing block
+    if (m > k && n > k) {
+        const unsigned nblk = (unsigned)rup(n - k, QR_CW);
+        hipLaunchKernelGGL((k_colnorms<T>), dim3(nblk), dim3(256), 0, st, d, k, k, 0, 0);
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, (const double*)d.npart, (int)nblk, d.dsc,
+                           (int)DSC_EPS2);
+    }
+    return hipGetLastError();
+}
+
 // nparts: argmax partials left by the kernel that set up the norms (ignored
 // without pivoting).
 template <typename T>
 static hipError_t run_qrcp(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats, int nparts)
 {
     QrcpDev<T>& d = w.d;
+    if (!d.pivoting) return run_blocked_fixed<T>(w, st, stats);
     const int64_t m = d.m, n = d.n, k = d.k;
     const int nb = w.nb;
     const unsigned na = (unsigned)rup(m, 256);

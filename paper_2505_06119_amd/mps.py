@@ -34,7 +34,20 @@ class MpsError(RuntimeError):
 class UpdateInfo(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int64), ("trunc_err_sq", ctypes.c_double), ("norm_sq", ctypes.c_double),
                 ("retained", ctypes.c_double), ("fallback", ctypes.c_int32), ("panels", ctypes.c_int32),
-                ("refreshes", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("refreshes", ctypes.c_int32), ("pad", ctypes.c_int32), ("learned_err_sq", ctypes.c_double),
+                ("qrcp_err_sq", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
+
+
+PIVNET_PARAMS = 97
+PIVNET_FEATURES = 4
+
+
+class LearnedCfg(ctypes.Structure):
+    _fields_ = [("params", ctypes.c_void_p), ("sketch_rows", ctypes.c_int32), ("verify", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("fallback_ratio", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
@@ -69,7 +82,27 @@ def lib() -> ctypes.CDLL:
     L.mps_update_work_bytes.argtypes = [i64, i64, i64, i64, i32, i32]
     L.mps_update_bond.restype = i32
     L.mps_update_bond.argtypes = [i64, i64, i64, i64, i32, i32, p, p, pd, p, p, ctypes.c_int,
-                                  ctypes.POINTER(UpdateInfo), p, i64, p]
+                                  ctypes.POINTER(LearnedCfg), ctypes.POINTER(UpdateInfo), p, i64, p]
+    L.mps_theta.restype = i32
+    L.mps_theta.argtypes = [i64, i64, i64, i32, p, p, pd, p, i64, p, i64, p]
+    L.pivnet_work_bytes.restype = i64
+    L.pivnet_work_bytes.argtypes = [i64, i64, i32, i32]
+    L.pivnet_features.restype = i32
+    L.pivnet_features.argtypes = [i64, i64, i32, p, i64, i32, ctypes.c_uint64, p, p, i64, p]
+    L.pivnet_forward.restype = i32
+    L.pivnet_forward.argtypes = [p, p, i64, p, p]
+    L.pivnet_grad.restype = i32
+    L.pivnet_grad.argtypes = [p, p, p, i64, p, p, i64, p]
+    L.pivnet_adam.restype = i32
+    L.pivnet_adam.argtypes = [p, p, p, p, i32, ctypes.c_float, p]
+    L.pivnet_rank.restype = i32
+    L.pivnet_rank.argtypes = [p, i64, p, p]
+    L.mps_set_pivot_network.restype = i32
+    L.mps_set_pivot_network.argtypes = [p, ctypes.POINTER(LearnedCfg)]
+    L.mps_profile.restype = i32
+    L.mps_profile.argtypes = [ctypes.c_int]
+    L.mps_profile_read.restype = i32
+    L.mps_profile_read.argtypes = [p, i32]
     L.mps_arena_bytes.restype = i64
     L.mps_arena_bytes.argtypes = [ctypes.POINTER(Config)]
     L.mps_create.restype = i32
@@ -193,9 +226,18 @@ def mps_update_work_bytes(chi_l, chi_m, chi_r, chi_cap, prec, pivot=MPS_PIVOT_QR
     return int(lib().mps_update_work_bytes(chi_l, chi_m, chi_r, chi_cap, prec, pivot))
 
 
+def learned_cfg(params, sketch_rows=64, verify=False, seed=1234, fallback_ratio=1.01) -> LearnedCfg:
+    """mps_learned_cfg for a device float32 parameter tensor of PIVNET_PARAMS entries."""
+    return LearnedCfg(params.data_ptr(), int(sketch_rows), 1 if verify else 0, int(seed), float(fallback_ratio))
+
+
 def mps_update_bond(A, B, g, chi_l, chi_m, chi_r, chi_cap, prec, renormalize=True, A_out=None, B_out=None,
-                    work=None, pivot=MPS_PIVOT_QRCP, stream=None, info=None) -> dict:
-    """Two-site update on device sites A (chi_l x 2 x chi_m) and B (chi_m x 2 x chi_r)."""
+                    work=None, pivot=MPS_PIVOT_QRCP, stream=None, info=None, learned=None) -> dict:
+    """Two-site update on device sites A (chi_l x 2 x chi_m) and B (chi_m x 2 x chi_r).
+
+    learned: a LearnedCfg (see learned_cfg) to use the learned pivot order."""
+    if learned is not None:
+        pivot = MPS_PIVOT_LEARNED
     torch = _torch()
     k = min(chi_cap, 2 * chi_l, 2 * chi_r)
     if A_out is None:
@@ -209,10 +251,74 @@ def mps_update_bond(A, B, g, chi_l, chi_m, chi_r, chi_cap, prec, renormalize=Tru
     if info is None:
         info = UpdateInfo()
     _check(lib().mps_update_bond(chi_l, chi_m, chi_r, chi_cap, prec, pivot, _ptr(A), _ptr(B), gp, _ptr(A_out),
-                                 _ptr(B_out), 1 if renormalize else 0, ctypes.byref(info), _ptr(work), work.numel(),
-                                 stream if stream is not None else stream_ptr()))
+                                 _ptr(B_out), 1 if renormalize else 0,
+                                 ctypes.byref(learned) if learned is not None else None, ctypes.byref(info),
+                                 _ptr(work), work.numel(), stream if stream is not None else stream_ptr()))
     del gbuf
     return {"A": A_out, "B": B_out, "info": info.as_dict(), "k": int(info.k)}
+
+
+def mps_theta(A, B, g, chi_l, chi_m, chi_r, prec, work=None, stream=None):
+    """theta = G (A B) as a column-major (2 chi_l) x (2 chi_r) device matrix."""
+    torch = _torch()
+    theta = empty_colmajor(2 * chi_l, 2 * chi_r, prec)
+    if work is None:
+        work = torch.empty(max(mps_update_work_bytes(chi_l, chi_m, chi_r, 1, prec), 1), dtype=torch.uint8,
+                           device=A.device)
+    gbuf, gp = gate_buffer(g)
+    _check(lib().mps_theta(chi_l, chi_m, chi_r, prec, _ptr(A), _ptr(B), gp, _ptr(theta), 2 * chi_l, _ptr(work),
+                           work.numel(), stream if stream is not None else stream_ptr()))
+    del gbuf
+    return theta
+
+
+# --- pivot-proposal network ------------------------------------------------------------
+
+def pivnet_features(theta, prec, sketch_rows=64, seed=1234, work=None, stream=None):
+    """Sketch features (n x 4 float32) of a column-major device matrix."""
+    torch = _torch()
+    m, n = theta.shape
+    ld = theta.stride(1) if n > 1 else max(m, 1)
+    phi = torch.empty((n, PIVNET_FEATURES), dtype=torch.float32, device=theta.device)
+    if work is None:
+        work = torch.empty(int(lib().pivnet_work_bytes(m, n, sketch_rows, prec)), dtype=torch.uint8,
+                           device=theta.device)
+    _check(lib().pivnet_features(m, n, prec, _ptr(theta), ld, sketch_rows, seed, _ptr(phi), _ptr(work),
+                                 work.numel(), stream if stream is not None else stream_ptr()))
+    return phi
+
+
+def pivnet_forward(params, phi, stream=None):
+    torch = _torch()
+    n = phi.shape[0]
+    scores = torch.empty(n, dtype=torch.float32, device=phi.device)
+    _check(lib().pivnet_forward(_ptr(params), _ptr(phi), n, _ptr(scores),
+                                stream if stream is not None else stream_ptr()))
+    return scores
+
+
+def pivnet_grad(params, phi, labels, stream=None):
+    """(gradient of the mean logistic loss, loss) on the device."""
+    torch = _torch()
+    n = phi.shape[0]
+    grad = torch.empty(PIVNET_PARAMS + 1, dtype=torch.float32, device=phi.device)
+    work = torch.empty(4 * (PIVNET_PARAMS + 1) * ((n + 255) // 256), dtype=torch.uint8, device=phi.device)
+    _check(lib().pivnet_grad(_ptr(params), _ptr(phi), _ptr(labels), n, _ptr(grad), _ptr(work), work.numel(),
+                             stream if stream is not None else stream_ptr()))
+    return grad
+
+
+def pivnet_adam(params, grad, m1, m2, t, lr, stream=None):
+    _check(lib().pivnet_adam(_ptr(params), _ptr(grad), _ptr(m1), _ptr(m2), int(t), float(lr),
+                             stream if stream is not None else stream_ptr()))
+
+
+def pivnet_rank(scores, stream=None):
+    torch = _torch()
+    n = scores.shape[0]
+    order = torch.empty(n, dtype=torch.int32, device=scores.device)
+    _check(lib().pivnet_rank(_ptr(scores), n, _ptr(order), stream if stream is not None else stream_ptr()))
+    return order
 
 
 # --- stateful MPS ------------------------------------------------------------------------
@@ -245,6 +351,10 @@ class MPS:
             self.close()
         except Exception:
             pass
+
+    def set_pivot_network(self, cfg: LearnedCfg):
+        self._lcfg = cfg
+        _check(lib().mps_set_pivot_network(self._h, ctypes.byref(cfg)))
 
     def apply_gate(self, i: int, g) -> dict:
         info = UpdateInfo()

@@ -68,12 +68,18 @@ def test_einval_on_host(L):
     st = L.qrcp_truncate(8, 4, 4, mps.MPS_FP64, p, 8, p, 8, p, 4, p, p, None, None, None, p, 16, z)
     assert st == 2                 # workspace too small
     g = (ctypes.c_double * 32)()
-    st = L.mps_update_bond(0, 4, 4, 4, 0, 0, p, p, g, p, p, 1, None, p, 1 << 30, z)
+    st = L.mps_update_bond(0, 4, 4, 4, 0, 0, p, p, g, p, p, 1, None, None, p, 1 << 30, z)
     assert st == 1
-    st = L.mps_update_bond(4, 4, 4, 4, 0, 1, p, p, g, p, p, 1, None, p, 1 << 30, z)
+    st = L.mps_update_bond(4, 4, 4, 4, 0, 1, p, p, g, p, p, 1, None, None, p, 1 << 30, z)
     assert st == 1 and "learned" in mps.last_error()
+    bad_cfg = mps.LearnedCfg(256, 0, 0, 1, 1.01)             # sketch_rows = 0
+    st = L.mps_update_bond(4, 4, 4, 4, 0, 1, p, p, g, p, p, 1, ctypes.byref(bad_cfg), None, p, 1 << 30, z)
+    assert st == 1
+    assert L.pivnet_work_bytes(8, 8, 0, 0) == -1
+    assert L.pivnet_forward(None, None, 4, None, z) == 1
+    assert L.pivnet_adam(p, p, p, p, 0, ctypes.c_float(1e-3), z) == 1
     g[3] = float("nan")
-    st = L.mps_update_bond(4, 4, 4, 4, 0, 0, p, p, g, p, p, 1, None, p, 1 << 30, z)
+    st = L.mps_update_bond(4, 4, 4, 4, 0, 0, p, p, g, p, p, 1, None, None, p, 1 << 30, z)
     assert st == 4
     h = ctypes.c_void_p()
     bad = mps.Config(1, 8, 0, 0, 1.01, 64, 0, 0)
