@@ -281,3 +281,99 @@ def qft_circuit(n: int, inverse: bool = False):
     if inverse:
         gates = [(i, g.conj().T) for i, g in reversed(gates)]
     return [[g] for g in gates]
+
+
+def grid_couplers(rows: int, cols: int, pattern: str):
+    """Coupler pairs (qubit labels y*cols + x) of one entangling pattern on a
+    rectangular grid: A/B horizontal pairs starting at even/odd x, C/D vertical
+    pairs starting at even/odd y (stand-in for the Sycamore patterns)."""
+    pairs = []
+    if pattern in "AB":
+        x0 = 0 if pattern == "A" else 1
+        for y in range(rows):
+            for x in range(x0, cols - 1, 2):
+                pairs.append((y * cols + x, y * cols + x + 1))
+    else:
+        y0 = 0 if pattern == "C" else 1
+        for y in range(y0, rows - 1, 2):
+            for x in range(cols):
+                pairs.append((y * cols + x, (y + 1) * cols + x))
+    return pairs
+
+
+def grid_rcs(r: np.random.Generator, rows: int, cols: int, cycles: int, patterns: str = "ABCDCDAB"):
+    """Random circuit on a rows x cols grid mapped to a 1D chain.
+
+    Each cycle: a single-qubit gate drawn uniformly from {sqrt X, sqrt Y,
+    sqrt W} on every qubit, then fSim(pi/2, pi/6) on the couplers of the next
+    pattern.  Horizontal patterns run in the row-snake embedding, vertical ones
+    in the column snake; the embedding changes by bubble-sort SWAPs (paper
+    Sec. III-D.2 and III-C site permutation).  Returns (layers, order): layers
+    of (bond, 4x4 gate) on chain positions, and the final qubit label at every
+    chain position."""
+    row_order, col_order = grid_snakes(rows, cols)
+    n = rows * cols
+    order = list(row_order)
+    layers = []
+    singles = [gate_sqrt_x(), gate_sqrt_y(), gate_sqrt_w()]
+    for c in range(cycles):
+        pat = patterns[c % len(patterns)]
+        want = row_order if pat in "AB" else col_order
+        if order != want:
+            for i in bubble_swaps(order, want):
+                layers.append([(i, gate_swap())])
+            order = list(want)
+        choice = r.integers(0, 3, size=n)
+        layer = []
+        for p in range(0, n - 1, 2):                       # pair sites (p, p+1) for the 1q gates
+            layer.append((p, np.kron(singles[choice[order[p]]], singles[choice[order[p + 1]]])))
+        if n % 2:
+            layer.append((n - 2, kron1(singles[choice[order[n - 1]]], False)))
+            layers.append(layer[:-1])
+            layers.append([layer[-1]])
+        else:
+            layers.append(layer)
+        pos = {q: p for p, q in enumerate(order)}
+        two = []
+        for a, b in grid_couplers(rows, cols, pat):
+            pa, pb = sorted((pos[a], pos[b]))
+            assert pb == pa + 1
+            two.append((pa, gate_fsim()))
+        two.sort(key=lambda t: t[0])
+        even = [t for t in two if t[0] % 2 == 0]
+        odd = [t for t in two if t[0] % 2 == 1]
+        for sub in (even, odd):
+            if sub:
+                layers.append(sub)
+    return layers, order
+
+
+def qpe_circuit(t: int, alphas, target_init: str = "plus"):
+    """Quantum phase estimation on a chain: t counting qubits (positions
+    0..t-1, position 0 the most significant) and one target qubit per angle
+    in ``alphas`` (positions t..), for U = tensor_q diag(1, exp(i alpha_q)).
+
+    Targets start in |+> (target_init="plus") or |1> ("one", an eigenstate
+    with eigenphase sum(alphas)); counting qubit j controls U^(2^(t-1-j)) as
+    controlled phases routed by SWAPs; the inverse QFT of Appendix A (with the
+    adjoint phase gates) finishes.  Returns a flat list of one-gate layers."""
+    s = len(alphas)
+    n = t + s
+    gates = []
+    for q in range(t):
+        gates.append(one_qubit_as_two_site(n, q, gate_h()))
+    xg = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+    for q in range(s):
+        g1 = gate_h() if target_init == "plus" else xg
+        gates.append(one_qubit_as_two_site(n, t + q, g1))
+    for j in range(t):
+        power = 2 ** (t - 1 - j)
+        for q in range(s):
+            tpos = t + q
+            for p in range(tpos - 1, j, -1):
+                gates.append((p, gate_swap()))
+            gates.append((j, gate_cphase(power * alphas[q])))
+            for p in range(j + 1, tpos):
+                gates.append((p, gate_swap()))
+    gates += [g for layer in qft_circuit(t, inverse=True) for g in layer]
+    return [[g] for g in gates]

@@ -1,0 +1,96 @@
+"""Circuit workloads (grid random circuit with SWAP re-embedding, phase
+estimation): oracle MPS against brute force and closed forms (no GPU), and
+the HIP path against the oracle (GPU)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2505_06119_amd import synth
+
+
+def test_grid_couplers_and_embeddings():
+    rows, cols = 5, 8
+    row_o, col_o = synth.grid_snakes(rows, cols)
+    assert sorted(row_o) == list(range(40)) and sorted(col_o) == list(range(40))
+    for pat in "ABCD":
+        pairs = synth.grid_couplers(rows, cols, pat)
+        order = row_o if pat in "AB" else col_o
+        pos = {q: p for p, q in enumerate(order)}
+        for a, b in pairs:
+            assert abs(pos[a] - pos[b]) == 1             # neighbours in the chosen embedding
+    swaps = synth.bubble_swaps(row_o, col_o)
+    # bubble sort performs exactly one swap per inversion
+    key = [col_o.index(q) for q in row_o]
+    inv = sum(1 for i in range(40) for j in range(i + 1, 40) if key[i] > key[j])
+    assert len(swaps) == inv
+
+
+def test_grid_rcs_oracle_exact():
+    layers, order = synth.grid_rcs(synth.rng(5), 3, 4, 6)
+    m = oracle.MPS(synth.product_state_sites(12), chi_cap=64)
+    m.apply_layers(layers)
+    np.testing.assert_allclose(oracle.statevector(m.sites), oracle.brute_force(12, layers), atol=1e-12)
+
+
+@pytest.mark.parametrize("mm", [3, 11])
+def test_qpe_exact_phase_oracle(mm):
+    t = 4
+    layers = synth.qpe_circuit(t, [2 * np.pi * mm / 2 ** t], target_init="one")
+    m = oracle.MPS(synth.product_state_sites(t + 1), chi_cap=16)
+    m.apply_layers(layers)
+    p = np.abs(oracle.statevector(m.sites).reshape(2 ** t, 2)) ** 2
+    assert abs(p.sum(axis=1)[mm] - 1.0) < 1e-12
+
+
+def test_qpe_superposed_targets_closed_form():
+    """Targets in |+>: P(y) = 2^-s sum_b |N^-1 sum_x exp(2 pi i x (phi_b - y/N))|^2."""
+    t = 4
+    alphas = [0.7, 2.1]
+    layers = synth.qpe_circuit(t, alphas, target_init="plus")
+    n = t + len(alphas)
+    m = oracle.MPS(synth.product_state_sites(n), chi_cap=64)
+    m.apply_layers(layers)
+    p = (np.abs(oracle.statevector(m.sites).reshape(2 ** t, -1)) ** 2).sum(axis=1)
+    N = 2 ** t
+    x = np.arange(N)
+    ref = np.zeros(N)
+    for b0 in (0, 1):
+        for b1 in (0, 1):
+            phi = (b0 * alphas[0] + b1 * alphas[1]) / (2 * np.pi)
+            for y in range(N):
+                ref[y] += abs(np.exp(2j * np.pi * x * (phi - y / N)).sum() / N) ** 2 / 4
+    np.testing.assert_allclose(p, ref, atol=1e-12)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", [0, 1])
+def test_grid_rcs_gpu_truncated_vs_oracle(prec):
+    """3x4 grid, 8 cycles (ABCDCDAB with re-embedding SWAPs), chi cap 16."""
+    from paper_2505_06119_amd import mps
+    print(f"case grid rcs prec={prec}", flush=True)
+    layers, _ = synth.grid_rcs(synth.rng(6), 3, 4, 8)
+    st = mps.MPS(12, 16, prec)
+    st.apply_layers(layers)
+    om = oracle.MPS(synth.product_state_sites(12), chi_cap=16)
+    om.apply_layers(layers)
+    tol = 1e-10 if prec == 0 else 1e-4
+    f_o = oracle.norm_fidelity(om.sites)
+    f_g = np.exp(st.log_norm_fidelity())
+    assert f_o < 0.9999
+    assert abs(f_g - f_o) <= tol * 10 * f_o
+    sv_o = oracle.statevector(om.sites)
+    sv_g = oracle.statevector(st.sites()) * np.sqrt(f_g)
+    fid = abs(np.vdot(sv_o, sv_g)) ** 2 / (np.vdot(sv_o, sv_o).real * np.vdot(sv_g, sv_g).real)
+    assert 1 - fid <= tol * 10
+
+
+@pytest.mark.gpu
+def test_qpe_gpu_exact_phase():
+    from paper_2505_06119_amd import mps
+    print("case qpe", flush=True)
+    t, mm = 5, 19
+    layers = synth.qpe_circuit(t, [2 * np.pi * mm / 2 ** t], target_init="one")
+    st = mps.MPS(t + 1, 32, mps.MPS_MIXED)
+    st.apply_layers(layers)
+    bits = [(mm >> (t - 1 - j)) & 1 for j in range(t)] + [1]
+    assert abs(abs(st.amplitude(bits)) - 1.0) < 1e-4
