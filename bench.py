@@ -114,6 +114,26 @@ def deviation(torch, res, ref, chi):
             "within_1e-4": bool(dev <= 1e-4 and 1.0 - sf <= 1e-4)}
 
 
+def measured_traffic():
+    """HBM bytes per k_step_c launch from the committed rocprofv3 counter
+    summary, or None when the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_step_c_chi4096_mixed.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256_16"):
+            k, v = line.split(":", 1)
+            fields[k] = v.strip()
+    h = hashlib.sha256()
+    for f in ("common.hpp", "qrcp.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2505_06119_amd", "csrc", f), "rb").read())
+    if fields.get("kernel_source_sha256_16") != h.hexdigest()[:16] or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def kernel_table(p, steps):
     return {kname: {"launches": v["launches"], "ms_per_step": v["ms"] / steps,
                     "GB/s": (v["bytes"] / (v["ms"] / 1e3) / 1e9) if v["ms"] > 0 else None,
@@ -149,6 +169,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one plain 512 MiB device copy (reference dispatch for HBM counters)")
+    ap.add_argument("--save-inputs", default=None, help="generate the input pair, save it here and exit")
+    ap.add_argument("--load-inputs", default=None, help="use an input pair saved by --save-inputs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the two-site update is built for a single MI355X "
@@ -161,13 +185,31 @@ def main():
     L = M.lib()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     chi = args.chi
+    if args.copy_calibration:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")   # 512 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] copy calibration: 536870912 bytes read, 536870912 bytes written")
+        del src, dst
 
-    log(f"[bench] generating chi={chi} canonical pair on the GPU")
-    r = synth.rng(args.seed)
     scale = 150.0 * chi / 1024.0
-    a, b = synth.canonical_pair_device(r, chi, chi, chi, synth.exp_spectrum(chi, scale))
-    g = synth.haar_unitary(r, 4)
+    if args.load_inputs:
+        saved = torch.load(args.load_inputs, weights_only=True)
+        a, b = saved["a"].cuda(), saved["b"].cuda()
+        g = saved["g"].numpy()
+        assert a.shape == (chi, 2, chi), "saved inputs have another chi"
+        log(f"[bench] loaded chi={chi} inputs from {args.load_inputs}")
+    else:
+        log(f"[bench] generating chi={chi} canonical pair on the GPU")
+        r = synth.rng(args.seed)
+        a, b = synth.canonical_pair_device(r, chi, chi, chi, synth.exp_spectrum(chi, scale))
+        g = synth.haar_unitary(r, 4)
     torch.cuda.synchronize()
+    if args.save_inputs:
+        torch.save({"a": a.cpu(), "b": b.cpu(), "g": torch.from_numpy(g)}, args.save_inputs)
+        log(f"[bench] saved inputs to {args.save_inputs}")
+        return
 
     runs = {"mixed": time_path(M, L, torch, "mixed", M.MPS_MIXED, a, b, g, chi, args.steps, args.warmup)}
     if not args.no_fp64:
@@ -212,9 +254,12 @@ def main():
     sc = hr["prof"]["step_c"]
     if sc["launches"] > 0 and sc["ms"] > 0:
         ach = sc["bytes"] / (sc["ms"] / 1e3) / 1e9
+        traffic = measured_traffic() if head == "mixed" and chi == 4096 else None
         res["roofline"] = {"bound": "hbm", "kernel": "k_step_c (trailing GEMV of one pivot step)",
                            "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                           "traffic": None, "launches": sc["launches"],
+                           "traffic": traffic, "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + "
+                                                               "WRITE_SIZE, copy-calibrated)",
+                           "launches": sc["launches"],
                            "avg_us": 1000.0 * sc["ms"] / sc["launches"],
                            "alg_bytes_per_launch": sc["bytes"] / sc["launches"]}
     tg = hr["prof"]["trail_gemm"]
