@@ -69,7 +69,7 @@ typedef struct {
     double qrcp_err_sq;   /* ||R22||^2 of plain pivoted QR when it ran (-1: n/a)      */
 } mps_update_info;
 
-/* Learned pivot proposal (spec addition, not in the paper): a Gaussian
+/* Learned pivot proposal (an addition of this library, not in the paper): a Gaussian
  * sketch Y = Omega theta (sketch_rows x n, Omega from a SplitMix64 counter
  * generator seeded with `seed`), per-column sketch features, and a small
  * network (MPS_PIVNET_PARAMS float32 parameters: 4 features -> 16 tanh units

@@ -1,7 +1,7 @@
 """FP64 reference of the learned pivot proposal -- TEST INFRASTRUCTURE ONLY.
 
 The proposal replaces the per-column pivot search of pivoted QR by a column
-order predicted from a Gaussian sketch of theta (a spec addition; the
+order predicted from a Gaussian sketch of theta (an addition of this library; the
 paper uses plain pivoted QR).  This module computes, plainly and in FP64:
 
 * ``omega``     the sketch matrix: the SplitMix64 output function (Steele, Lea
