@@ -4,6 +4,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <string>
@@ -46,9 +47,19 @@ static inline int64_t elem_bytes(mps_precision p) { return p == MPS_FP64 ? 16 : 
 static inline bool valid_prec(int p) { return p == MPS_FP64 || p == MPS_MIXED; }
 
 // Default panel width of the delayed-update QRCP.
+// Panel width of the delayed-update QRCP: wider panels raise the arithmetic
+// intensity of the rank-nb trailing update but lengthen every pivot step's
+// F-correction; MPS_PANEL_WIDTH (16, 32 or 64) overrides the rule for tuning.
 static int panel_width(int64_t m, int64_t n)
 {
     (void)m;
+    static int forced = -1;
+    if (forced < 0) {
+        const char* e = getenv("MPS_PANEL_WIDTH");
+        const int v = e ? atoi(e) : 0;
+        forced = (v == 16 || v == 32 || v == 64) ? v : 0;
+    }
+    if (forced > 0) return n <= 64 && forced > 16 ? 16 : forced;
     if (n <= 64) return 16;
     return 32;
 }

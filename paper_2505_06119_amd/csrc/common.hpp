@@ -56,6 +56,101 @@ __device__ __forceinline__ double2 wave_sum(double2 v)
     return v;
 }
 
+// Wavefront reduce-scatter of NV doubles (NV a power of two, <= 64): at the
+// level with exchange distance `off` every lane keeps one half of its values
+// and receives its partner's copy of that half, so the values held per lane
+// halve at each level (NV - 1 exchanges instead of 6 NV for NV all-reduces).
+// On return lane L holds the wave total of value L / (64 / NV) (lanes that
+// share that index hold the same total).
+template <int NV>
+__device__ __forceinline__ double wave_reduce_scatter(double (&v)[NV])
+{
+    static_assert(NV >= 1 && NV <= 64 && (NV & (NV - 1)) == 0, "NV must be a power of two <= 64");
+    const int lane = threadIdx.x & 63;
+    if constexpr (NV > 1) {
+        constexpr int H = NV / 2;
+        constexpr int OFF = 32;
+        const bool up = (lane & OFF) != 0;
+#pragma unroll
+        for (int q = 0; q < H; ++q) {
+            const double send = up ? v[q] : v[q + H];
+            const double keep = up ? v[q + H] : v[q];
+            v[q] = keep + __shfl_xor(send, OFF, MPS_WAVE);
+        }
+    }
+    if constexpr (NV > 2) {
+        constexpr int H = NV / 4;
+        constexpr int OFF = 16;
+        const bool up = (lane & OFF) != 0;
+#pragma unroll
+        for (int q = 0; q < H; ++q) {
+            const double send = up ? v[q] : v[q + H];
+            const double keep = up ? v[q + H] : v[q];
+            v[q] = keep + __shfl_xor(send, OFF, MPS_WAVE);
+        }
+    }
+    if constexpr (NV > 4) {
+        constexpr int H = NV / 8;
+        constexpr int OFF = 8;
+        const bool up = (lane & OFF) != 0;
+#pragma unroll
+        for (int q = 0; q < H; ++q) {
+            const double send = up ? v[q] : v[q + H];
+            const double keep = up ? v[q + H] : v[q];
+            v[q] = keep + __shfl_xor(send, OFF, MPS_WAVE);
+        }
+    }
+    if constexpr (NV > 8) {
+        constexpr int H = NV / 16;
+        constexpr int OFF = 4;
+        const bool up = (lane & OFF) != 0;
+#pragma unroll
+        for (int q = 0; q < H; ++q) {
+            const double send = up ? v[q] : v[q + H];
+            const double keep = up ? v[q + H] : v[q];
+            v[q] = keep + __shfl_xor(send, OFF, MPS_WAVE);
+        }
+    }
+    if constexpr (NV > 16) {
+        constexpr int H = NV / 32;
+        constexpr int OFF = 2;
+        const bool up = (lane & OFF) != 0;
+#pragma unroll
+        for (int q = 0; q < H; ++q) {
+            const double send = up ? v[q] : v[q + H];
+            const double keep = up ? v[q + H] : v[q];
+            v[q] = keep + __shfl_xor(send, OFF, MPS_WAVE);
+        }
+    }
+    if constexpr (NV > 32) {
+        const bool up = (lane & 1) != 0;
+        const double send = up ? v[0] : v[1];
+        const double keep = up ? v[1] : v[0];
+        v[0] = keep + __shfl_xor(send, 1, MPS_WAVE);
+    }
+    double r = v[0];
+#pragma unroll
+    for (int off = 32 / NV; off > 0; off >>= 1) r += __shfl_xor(r, off, MPS_WAVE);
+    return r;
+}
+
+// Block (256 threads) sum of NV doubles per thread into out[0..NV) (LDS),
+// using lds[4 * NV] as staging; ends with a barrier, after which out[] is
+// visible to every thread.  The per-wave totals are added in wave order.
+template <int NV>
+__device__ __forceinline__ void block_sum_rs(double (&v)[NV], double* lds, double* out)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const double r = wave_reduce_scatter<NV>(v);
+    constexpr int REP = 64 / NV;
+    if (lane % REP == 0) lds[wid * NV + lane / REP] = r;
+    __syncthreads();
+    if (threadIdx.x < NV)
+        out[threadIdx.x] = ((lds[threadIdx.x] + lds[NV + threadIdx.x]) + lds[2 * NV + threadIdx.x]) +
+                           lds[3 * NV + threadIdx.x];
+    __syncthreads();
+}
+
 // Sum over a 256-thread block; every thread receives the total.  `scratch`
 // must hold 4 doubles (one per wave) and is reused after a barrier.
 __device__ __forceinline__ double block_sum256(double v, double* scratch)
@@ -107,33 +202,3 @@ __device__ __forceinline__ ArgBest block_argmax256(ArgBest a, ArgBest* scratch)
     return b;
 }
 
-// "Last block done" ticket: every block calls it after publishing its partial
-// results; exactly one block (the last to arrive) gets true and may then read
-// all partials.  The counter is reset by the last block for the next launch.
-__device__ __forceinline__ bool last_block_ticket(unsigned int* counter, unsigned int nblocks, int* flag_lds)
-{
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned int t = atomicAdd(counter, 1u);
-        *flag_lds = (t == nblocks - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    bool last = *flag_lds != 0;
-    if (last) {
-        __threadfence();
-        if (threadIdx.x == 0) atomicExch(counter, 0u);
-    }
-    return last;
-}
-
-// Loads that must observe writes made by other blocks of the same launch
-// (published before a last_block_ticket) go around the non-coherent caches.
-__device__ __forceinline__ double ld_coherent(const double* p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ int32_t ld_coherent(const int32_t* p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}

@@ -97,60 +97,94 @@ __device__ __forceinline__ void block_sum_vec(double (&v)[NV], double* lds /* 4*
 // ---------------------------------------------------------------------------
 // step A: pivot choice + swap + bring-up of the pivot column + partial sums.
 // grid: ceil(m / 256) blocks, one row per thread.  nparts: number of argmax
-// partials left by the previous launch.
+// partials left by the previous launch.  JMAX bounds the panel position jj
+// (16, 32 or 64): the row's panel reflectors V[i, p0:j] stay in registers
+// from the bring-up to the partial sums.  Everything that does not depend on
+// the pivot (the stop flag, the argmax partials, V[i, p0:j] and A[i, j]) is
+// loaded in one round before the pivot is known, so a step costs two
+// dependent memory round trips.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int JMAX>
 __global__ __launch_bounds__(256) void k_step_a(QrcpDev<T> d, int64_t j, int64_t p0, int jj, int nparts)
 {
-    __shared__ double2 fp[QR_NBMAX];
-    __shared__ double red_lds[4 * 16];
-    __shared__ double red_out[16];
+    __shared__ double2 fp[JMAX];
+    __shared__ double s_red[4 * 2 * JMAX];
+    __shared__ double s_rest[4];
     __shared__ ArgBest arg_lds[4];
-    if (d.ctl[CTL_STOP]) return;
+    __shared__ int s_fl;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const T zero = from_d<T>(czero());
+    const int32_t stop = d.ctl[CTL_STOP];
+    const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+    const bool in = i < d.m, below = in && i >= j;
+    // loads are unconditional from clamped in-range addresses and masked
+    // afterwards, so they issue back to back without branches
+    const int64_t ic = in ? i : d.m - 1;
+    const T* arow = d.A + ic;
+    // the reflector row is held as two scalar arrays (real, imaginary parts)
+    // so that it stays in registers
+    using S = typename std::conditional<sizeof(T) == 8, float, double>::type;
+    S vre[JMAX], vim[JMAX];
+#pragma unroll
+    for (int t = 0; t < JMAX; ++t) {
+        const int64_t col = p0 + (t < jj ? t : 0);   // p0 <= j: always a valid column
+        const T v = arow[d.lda * col];
+        const bool keep = below && t < jj;
+        vre[t] = keep ? v.x : (S)0;
+        vim[t] = keep ? v.y : (S)0;
+    }
+    const T aj = arow[d.lda * j];
 
-    const int tid = threadIdx.x;
     int64_t p = j;
     if (d.pivoting) {
+        if (tid == 0) s_fl = 0;
         ArgBest b;
         b.val = -1.0;
         b.key = 0x7fffffff;
         b.slot = -1;
-        double fl = 0.0;
+        int fl = 0;
         for (int q0 = 0; q0 < nparts; q0 += 256 * 8) {
-            // issue up to 8 partial loads per thread before using any
+            // up to 8 partial loads per thread in flight before using any
             ArgBest e[8];
             int32_t f[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int q = q0 + tid + 256 * u;
-                if (q < nparts) {
-                    e[u] = d.cpart[q];
-                    f[u] = d.cflag[q];
-                } else {
-                    e[u].slot = -1;
-                    f[u] = 0;
-                }
+                const int qc = q < nparts ? q : 0;
+                e[u] = d.cpart[qc];
+                f[u] = d.cflag[qc];
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                if (e[u].slot >= 0 && arg_better(e[u].val, e[u].key, b.val, b.key)) b = e[u];
-                fl += f[u] ? 1.0 : 0.0;
+                const bool ok = q0 + tid + 256 * u < nparts;
+                if (ok && e[u].slot >= 0 && arg_better(e[u].val, e[u].key, b.val, b.key)) b = e[u];
+                fl |= ok ? f[u] : 0;
             }
         }
-        b = block_argmax256(b, arg_lds);
-        fl = block_sum256(fl, red_lds);
-        if (fl > 0.0) {
+        b = wave_argmax(b);
+        __syncthreads();   // orders the s_fl reset before the flag stores
+        if (fl) s_fl = 1;
+        if (lane == 0) arg_lds[wid] = b;
+        __syncthreads();
+        ArgBest bb = arg_lds[0];
+        for (int w = 1; w < 4; ++w)
+            if (arg_better(arg_lds[w].val, arg_lds[w].key, bb.val, bb.key)) bb = arg_lds[w];
+        if (stop) return;
+        if (s_fl) {
             // a residual norm of the previous step became unreliable: end the panel
             if (blockIdx.x == 0 && tid == 0) d.ctl[CTL_STOP] = 1;
             return;
         }
-        if (b.slot >= j) p = b.slot;
+        if (bb.slot >= j) p = bb.slot;
         if (blockIdx.x == 0 && tid == 0) d.ctl[CTL_PIV] = (int32_t)p;
+    } else if (stop) {
+        return;
     }
     if (tid < jj) fp[tid] = to_d(d.F[p + d.ldf * tid]);
+    const T ap = arow[d.lda * p];
     if (blockIdx.x == 0 && p != j) {
         if (tid < jj) {
-            T fj = d.F[j + d.ldf * tid];
+            const T fj = d.F[j + d.ldf * tid];
             d.fsave[tid] = to_d(fj);
             d.F[j + d.ldf * tid] = d.F[p + d.ldf * tid];
         }
@@ -162,62 +196,76 @@ __global__ __launch_bounds__(256) void k_step_a(QrcpDev<T> d, int64_t j, int64_t
     }
     __syncthreads();
 
-    const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+    if (in && p != j) {
+        d.A[i + d.lda * j] = ap;
+        d.A[i + d.lda * p] = aj;
+    }
     double2 x = czero();
-    bool has = false;
-    if (i < d.m) {
-        T aj = d.A[i + d.lda * j];
-        T ap = d.A[i + d.lda * p];
-        if (p != j) {
-            d.A[i + d.lda * j] = ap;
-            d.A[i + d.lda * p] = aj;
-        }
-        if (i >= j) {
-            x = to_d(ap);
-            // V row loads issued 8 at a time so their latencies overlap
-            for (int t0 = 0; t0 < jj; t0 += 8) {
-                T vr[8];
+    if (below) {
+        x = to_d(ap);
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (t0 + u < jj) vr[u] = d.A[i + d.lda * (p0 + t0 + u)];
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (t0 + u < jj) x = csub(x, cmul(to_d(vr[u]), cconj(fp[t0 + u])));
-            }
-            d.xbuf[i] = x;
-            d.xlo[i] = from_d<T>(x);
-            has = true;
-            if (i == j) d.hh[0] = x;
-        }
+        for (int t = 0; t < JMAX; ++t)
+            if (t < jj) x = csub(x, cmul(make_double2(vre[t], vim[t]), cconj(fp[t])));
+        d.xbuf[i] = x;
+        d.xlo[i] = from_d<T>(x);
+        if (i == j) d.hh[0] = x;
     }
-    double* part = d.apart + (int64_t)blockIdx.x * APART_STRIDE;
+
+    // partials: rest = sum_{i>j} |x_i|^2 and W_t = sum_i conj(V[i, t]) x_i
     {
-        double v[1] = {(has && i > j) ? cabs2(x) : 0.0};
-        block_sum_vec<1>(v, red_lds, red_out);
-        if (tid == 0) part[0] = red_out[0];
+        const double r = wave_sum((below && i > j) ? cabs2(x) : 0.0);
+        if (lane == 0) s_rest[wid] = r;
     }
-    for (int t0 = 0; t0 < jj; t0 += 8) {
-        double v[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int t = t0 + u;
-            double2 w = czero();
-            if (has && t < jj) w = cmulc(to_d(d.A[i + d.lda * (p0 + t)]), x);
-            v[2 * u] = w.x;
-            v[2 * u + 1] = w.y;
+    for (int c0 = 0; c0 < JMAX; c0 += 16) {
+        if (c0 < jj) {
+            double v[32];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const double2 w =
+                    c0 + u < jj ? cmulc(make_double2(vre[c0 + u], vim[c0 + u]), x) : czero();
+                v[2 * u] = w.x;
+                v[2 * u + 1] = w.y;
+            }
+            const double r = wave_reduce_scatter<32>(v);   // lane L: value L / 2 of the chunk
+            if ((lane & 1) == 0) s_red[wid * 2 * JMAX + 2 * c0 + (lane >> 1)] = r;
         }
-        block_sum_vec<16>(v, red_lds, red_out);
-        if (tid < 16 && t0 + tid / 2 < jj) part[2 + 2 * t0 + tid] = red_out[tid];
     }
+    __syncthreads();
+    double* part = d.apart + (int64_t)blockIdx.x * APART_STRIDE;
+    if (tid < 2 * jj)
+        part[2 + tid] = ((s_red[tid] + s_red[2 * JMAX + tid]) + s_red[4 * JMAX + tid]) + s_red[6 * JMAX + tid];
+    if (tid == 255) part[0] = ((s_rest[0] + s_rest[1]) + s_rest[2]) + s_rest[3];
+}
+
+// Launch step A with the register budget that covers panel position jj.
+template <typename T>
+static void launch_step_a(const QrcpDev<T>& d, unsigned nblocks, int64_t j, int64_t p0, int jj, int nparts,
+                          hipStream_t st)
+{
+    if (jj <= 16)
+        hipLaunchKernelGGL((k_step_a<T, 16>), dim3(nblocks), dim3(256), 0, st, d, j, p0, jj, nparts);
+    else if (jj <= 32)
+        hipLaunchKernelGGL((k_step_a<T, 32>), dim3(nblocks), dim3(256), 0, st, d, j, p0, jj, nparts);
+    else
+        hipLaunchKernelGGL((k_step_a<T, 64>), dim3(nblocks), dim3(256), 0, st, d, j, p0, jj, nparts);
 }
 
 // Partial GEMV of one thread: acc[2u], acc[2u+1] += sum over this thread's
 // rows i > j of conj(A[i, cbase+u]) x_i, for the CW columns cbase.. (< cend).
-// x is read in storage precision (xlo); accumulation is FP64.  Storage is
-// read in 16-byte vectors: two complex64 rows or one complex128 row per load,
-// two loads per column in flight per thread.  The leading dimension is even,
-// so every column starts 16-byte aligned.
-template <typename T, int CW>
+// x is read in storage precision (xlo); every product is formed and
+// accumulated in FP64 (for complex64 data the products are exact, so the sum
+// is the FP64 sum of the exact terms).  Storage is read in 16-byte vectors
+// (two complex64 rows or one complex128 row per load), RU row groups per
+// column in flight per thread.  The leading dimension is even, so every column
+// starts 16-byte aligned.
+//
+// complex64: an empty asm statement on each loaded vector keeps the FP32 ->
+// FP64 conversions at the point of use.  Left free, the compiler converts
+// every vector as soon as it arrives, which doubles the live registers,
+// lowers occupancy and with it the loads in flight per CU (measured: 4.6 TB/s
+// instead of 6.0 TB/s on an 8192 x 8192 complex64 block with RU = 1).
+template <typename T, int CW, int RU = (sizeof(T) == 8 ? 1 : 4)>
 __device__ __forceinline__ void gemv_cols(const QrcpDev<T>& d, int64_t j, int64_t cbase, int64_t cend,
                                           double (&acc)[2 * CW])
 {
@@ -225,64 +273,60 @@ __device__ __forceinline__ void gemv_cols(const QrcpDev<T>& d, int64_t j, int64_
     for (int u = 0; u < 2 * CW; ++u) acc[u] = 0.0;
     const int tid = threadIdx.x;
     const int64_t ncols = cend - cbase;
+    const int64_t m = d.m;
     if constexpr (sizeof(T) == 8) {
         // complex64: pairs of rows (r, r+1), r even, starting at the pair holding row j+1
         const int64_t r0 = (j + 1) & ~(int64_t)1;
-        const int64_t m = d.m;
-        for (int64_t r = r0 + 2 * tid; r < m; r += 1024) {
-            const int64_t r2 = r + 512;
-            const bool has2 = r2 < m;
-            const float4 xa = *(const float4*)(d.xlo + r);
-            float4 xb = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (has2) xb = *(const float4*)(d.xlo + r2);
-            float4 av[CW], bv[CW];
+        for (int64_t rb = r0 + 2 * tid; rb < m; rb += 512 * RU) {
+            float4 xv[RU], av[RU][CW];
 #pragma unroll
-            for (int u = 0; u < CW; ++u) {
-                if (u < ncols) {
-                    const T* col = d.A + d.lda * (cbase + u);
-                    av[u] = *(const float4*)(col + r);
-                    bv[u] = has2 ? *(const float4*)(col + r2) : make_float4(0.f, 0.f, 0.f, 0.f);
-                }
+            for (int q = 0; q < RU; ++q) {
+                const int64_t r = rb + 512 * q;
+                const bool ok = r < m;
+                xv[q] = ok ? *(const float4*)(d.xlo + r) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                for (int u = 0; u < CW; ++u)
+                    av[q][u] = (ok && u < ncols) ? *(const float4*)(d.A + d.lda * (cbase + u) + r)
+                                                 : make_float4(0.f, 0.f, 0.f, 0.f);
             }
-            // rows outside (j, m) contribute nothing (select, so no NaN leaks in)
-            const bool a0 = r > j, a1 = r + 1 < m, b1 = r2 + 1 < m;
 #pragma unroll
-            for (int u = 0; u < CW; ++u) {
-                if (u < ncols) {
-                    double2 p = czero();
-                    if (a0) p = cadd(p, cmulc(make_double2(av[u].x, av[u].y), make_double2(xa.x, xa.y)));
-                    if (a1) p = cadd(p, cmulc(make_double2(av[u].z, av[u].w), make_double2(xa.z, xa.w)));
-                    if (has2) {
-                        p = cadd(p, cmulc(make_double2(bv[u].x, bv[u].y), make_double2(xb.x, xb.y)));
-                        if (b1) p = cadd(p, cmulc(make_double2(bv[u].z, bv[u].w), make_double2(xb.z, xb.w)));
-                    }
-                    acc[2 * u] += p.x;
-                    acc[2 * u + 1] += p.y;
+            for (int q = 0; q < RU; ++q) {
+                const int64_t r = rb + 512 * q;
+                // rows outside (j, m) contribute nothing (select, so no NaN leaks in)
+                const bool lo = r > j && r < m, hi = r + 1 < m;
+                float4 xq = xv[q];
+                asm volatile("" : "+v"(xq.x), "+v"(xq.y), "+v"(xq.z), "+v"(xq.w));
+                const double x0r = lo ? (double)xq.x : 0.0, x0i = lo ? (double)xq.y : 0.0;
+                const double x1r = hi ? (double)xq.z : 0.0, x1i = hi ? (double)xq.w : 0.0;
+#pragma unroll
+                for (int u = 0; u < CW; ++u) {
+                    float4 a = av[q][u];
+                    asm volatile("" : "+v"(a.x), "+v"(a.y), "+v"(a.z), "+v"(a.w));
+                    const double ar = a.x, ai = a.y, br = a.z, bi = a.w;
+                    // conj(a0) x0 + conj(a1) x1
+                    acc[2 * u] = fma(ar, x0r, fma(ai, x0i, fma(br, x1r, fma(bi, x1i, acc[2 * u]))));
+                    acc[2 * u + 1] = fma(ar, x0i, fma(-ai, x0r, fma(br, x1i, fma(-bi, x1r, acc[2 * u + 1]))));
                 }
             }
         }
     } else {
         // complex128: one row per 16-byte load
-        const int64_t m = d.m;
-        for (int64_t r = j + 1 + tid; r < m; r += 512) {
-            const int64_t r2 = r + 256;
-            const bool has2 = r2 < m;
-            const double2 xa = to_d(d.xlo[r]);
-            const double2 xb = has2 ? to_d(d.xlo[r2]) : czero();
-            double2 av[CW], bv[CW];
+        for (int64_t rb = j + 1 + tid; rb < m; rb += 256 * RU) {
+            double2 xv[RU], av[RU][CW];
 #pragma unroll
-            for (int u = 0; u < CW; ++u) {
-                if (u < ncols) {
-                    const T* col = d.A + d.lda * (cbase + u);
-                    av[u] = to_d(col[r]);
-                    bv[u] = has2 ? to_d(col[r2]) : czero();
-                }
+            for (int q = 0; q < RU; ++q) {
+                const int64_t r = rb + 256 * q;
+                const bool ok = r < m;
+                xv[q] = ok ? to_d(d.xlo[r]) : czero();
+#pragma unroll
+                for (int u = 0; u < CW; ++u)
+                    av[q][u] = (ok && u < ncols) ? to_d(d.A[d.lda * (cbase + u) + r]) : czero();
             }
 #pragma unroll
-            for (int u = 0; u < CW; ++u) {
-                if (u < ncols) {
-                    double2 p = cmulc(av[u], xa);
-                    if (has2) p = cadd(p, cmulc(bv[u], xb));
+            for (int q = 0; q < RU; ++q) {
+#pragma unroll
+                for (int u = 0; u < CW; ++u) {
+                    const double2 p = cmulc(av[q][u], xv[q]);
                     acc[2 * u] += p.x;
                     acc[2 * u + 1] += p.y;
                 }
@@ -290,7 +334,6 @@ __device__ __forceinline__ void gemv_cols(const QrcpDev<T>& d, int64_t j, int64_
         }
     }
 }
-
 
 // ---------------------------------------------------------------------------
 // step C: reflector from step A's partials, GEMV over the trailing block,
@@ -305,24 +348,40 @@ __global__ __launch_bounds__(256) void k_step_c(QrcpDev<T> d, int64_t j, int64_t
     __shared__ double2 s_par[4];   // beta, tau, scale, alpha
     __shared__ double red_lds[4 * 2 * QR_CW];
     __shared__ double red_out[2 * QR_CW];
-    __shared__ ArgBest arg_lds[4];
-    __shared__ double flag_lds[4];
-    if (d.ctl[CTL_STOP]) return;
+    // the stop flag is read now and tested before the first store, so its
+    // latency overlaps the prologue loads (everything before it only reads)
+    const int32_t stop = d.ctl[CTL_STOP];
 
     const int tid = threadIdx.x;
-    // ---- reflector from step A's partials (identical in every block) ----
-    if (tid < jj) {
-        double2 w = czero();
-        for (int b = 0; b < na; ++b) {
-            w.x += d.apart[(int64_t)b * APART_STRIDE + 2 + 2 * tid];
-            w.y += d.apart[(int64_t)b * APART_STRIDE + 3 + 2 * tid];
+    // ---- reflector from step A's partials (identical in every block).  The
+    //      S = 1 + 2*jj values of each step-A block are summed by G = 256/S
+    //      thread groups in parallel, then the G group sums in a fixed order ----
+    __shared__ double s_red[256];
+    __shared__ double s_tot[2 * QR_NBMAX + 1];
+    __shared__ int s_flag;
+    {
+        const int S = 1 + 2 * jj, G = 256 / S;
+        const int slot = tid % S, grp = tid / S;
+        double acc = 0.0;
+        if (grp < G) {
+            const int off = slot == 0 ? 0 : slot + 1;    // rest at 0, W re/im from 2
+#pragma unroll 4
+            for (int b = grp; b < na; b += G) acc += d.apart[(int64_t)b * APART_STRIDE + off];
         }
-        s_w[tid] = w;
-        s_vj[tid] = to_d(d.A[j + d.lda * (p0 + tid)]);
+        s_red[tid] = acc;
+        if (tid < jj) s_vj[tid] = to_d(d.A[j + d.lda * (p0 + tid)]);
+        if (tid == 0) s_flag = 0;
+        __syncthreads();
+        if (tid < S) {
+            double s = 0.0;
+            for (int g = 0; g < G; ++g) s += s_red[g * S + tid];
+            s_tot[tid] = s;
+        }
+        __syncthreads();
     }
+    if (tid < jj) s_w[tid] = make_double2(s_tot[1 + 2 * tid], s_tot[2 + 2 * tid]);
     if (tid == 64) {
-        double rest = 0.0;
-        for (int b = 0; b < na; ++b) rest += d.apart[(int64_t)b * APART_STRIDE];
+        const double rest = s_tot[0];
         const double2 alpha = d.hh[0];
         double2 tau, scale;
         double beta;
@@ -378,15 +437,16 @@ __global__ __launch_bounds__(256) void k_step_c(QrcpDev<T> d, int64_t j, int64_t
     // ---- GEMV: g_u = sum_{i>j} conj(A[i, c_u]) x_i ----
     double acc[2 * QR_CW];
     gemv_cols<T, QR_CW>(d, j, cbase, cend, acc);
-    block_sum_vec<2 * QR_CW>(acc, red_lds, red_out);   // ends with a barrier: LDS staging visible
+    block_sum_rs<2 * QR_CW>(acc, red_lds, red_out);   // ends with a barrier: LDS staging visible
+    if (stop) return;
 
     // ---- per-column scalar work (one thread per column) ----
-    ArgBest best;
-    best.val = -1.0;
-    best.key = 0x7fffffff;
-    best.slot = -1;
-    double flagged = 0.0;
+    __shared__ ArgBest s_best[QR_CW];
     if (tid < QR_CW) {
+        ArgBest best;
+        best.val = -1.0;
+        best.key = 0x7fffffff;
+        best.slot = -1;
         const int64_t c = cbase + tid;
         if (c < cend) {
             const bool moved = d.pivoting && c == p && p != j;
@@ -411,7 +471,7 @@ __global__ __launch_bounds__(256) void k_step_c(QrcpDev<T> d, int64_t j, int64_t
                 const bool flag = nn <= d.tol * s_nuref[tid];
                 d.nu[c] = nn;
                 if (flag) {
-                    flagged = 1.0;
+                    s_flag = 1;
                 } else {
                     best.val = nn;
                     best.key = s_perm[tid];
@@ -419,25 +479,32 @@ __global__ __launch_bounds__(256) void k_step_c(QrcpDev<T> d, int64_t j, int64_t
                 }
             }
         }
+        s_best[tid] = best;
     }
 
-    // ---- block 0 stores the reflector and R_jj ----
-    if (blockIdx.x == 0) {
-        for (int64_t i = j + 1 + tid; i < d.m; i += 256)
-            d.A[i + d.lda * j] = from_d<T>(cmul(scale, d.xbuf[i]));
-        if (tid == 0) {
-            d.A[j + d.lda * j] = from_d<T>(make_double2(beta, 0.0));
-            d.tau[j] = tau;
-            d.diagR[j] = beta;
-            d.ctl[CTL_JDONE] = (int32_t)(j + 1);
-        }
+    // ---- the reflector column below the diagonal, split evenly over the
+    //      blocks; block 0 also stores R_jj, tau and the progress counter ----
+    {
+        const int64_t len = d.m - j - 1;
+        const int64_t chunk = (len + gridDim.x - 1) / gridDim.x;
+        const int64_t r0 = j + 1 + (int64_t)blockIdx.x * chunk;
+        const int64_t r1 = r0 + chunk < d.m ? r0 + chunk : d.m;
+        for (int64_t i = r0 + tid; i < r1; i += 256) d.A[i + d.lda * j] = from_d<T>(cmul(scale, d.xbuf[i]));
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+        d.A[j + d.lda * j] = from_d<T>(make_double2(beta, 0.0));
+        d.tau[j] = tau;
+        d.diagR[j] = beta;
+        d.ctl[CTL_JDONE] = (int32_t)(j + 1);
     }
     if (!d.pivoting) return;
-    best = block_argmax256(best, arg_lds);
-    flagged = block_sum256(flagged, flag_lds);
+    __syncthreads();   // publishes s_best and s_flag
     if (tid == 0) {
-        d.cpart[blockIdx.x] = best;
-        d.cflag[blockIdx.x] = flagged > 0.0 ? 1 : 0;
+        ArgBest b = s_best[0];
+        for (int u = 1; u < QR_CW; ++u)
+            if (arg_better(s_best[u].val, s_best[u].key, b.val, b.key)) b = s_best[u];
+        d.cpart[blockIdx.x] = b;
+        d.cflag[blockIdx.x] = s_flag;
     }
 }
 

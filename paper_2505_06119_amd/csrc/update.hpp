@@ -254,7 +254,7 @@ static hipError_t run_blocked_fixed(UpdateWs<T>& w, hipStream_t st, QrcpStats* s
         for (int64_t jc = p0; jc < pend; ++jc) {
             const int jj = (int)(jc - p0);
             hipEvent_t ea = prof_begin(st);
-            hipLaunchKernelGGL((k_step_a<T>), dim3(na), dim3(256), 0, st, d, jc, p0, jj, 0);
+            launch_step_a<T>(d, na, jc, p0, jj, 0, st);
             prof_end(ea, st, PK_STEP_A, (double)sizeof(T) * (double)(m - jc) * (jj + 1), 8.0 * (m - jc) * jj);
             const int64_t ncol = pend - jc - 1;
             const unsigned nc = (unsigned)(ncol > 0 ? rup(ncol, QR_CW) : 1);
@@ -313,7 +313,7 @@ static hipError_t run_qrcp(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats, int
         for (int64_t jc = p0; jc < pend; ++jc) {
             const int jj = (int)(jc - p0);
             hipEvent_t ea = prof_begin(st);
-            hipLaunchKernelGGL((k_step_a<T>), dim3(na), dim3(256), 0, st, d, jc, p0, jj, nparts);
+            launch_step_a<T>(d, na, jc, p0, jj, nparts, st);
             prof_end(ea, st, PK_STEP_A, (double)sizeof(T) * (double)(m - jc) * (jj + 1), 8.0 * (m - jc) * jj);
             int64_t ncol = n - jc - 1;
             unsigned nc = (unsigned)(ncol > 0 ? rup(ncol, QR_CW) : 1);
