@@ -241,11 +241,15 @@ mps_status mps_centre(const mps_ctx* ctx, int32_t* out);
 mps_status mps_get_site(mps_ctx* ctx, int32_t j, void* dst, int64_t dst_bytes);
 
 /* ------------------------------------------------------------------------
- * Per-kernel timing.  mps_profile(1) resets and enables process-wide timing
- * of the library's launches with HIP events recorded on the caller's stream
- * (mps_profile(0) disables it).  mps_profile_read fills up to n entries,
- * indexed by mps_kernel_class, with the launch count, the summed event time
- * and the algorithmic bytes and flops of those launches.  Not thread-safe.
+ * Per-kernel timing.  mps_profile(mode) resets the counters and sets the
+ * process-wide timing of the library's launches with HIP events recorded on
+ * the caller's stream: mode 0 off; mode 1 every launch of every class; mode
+ * s >= 2 only one pivot-step GEMV launch (MPS_K_STEP_C) in s, a sample that
+ * leaves the measured run nearly undisturbed (each event marker costs a few
+ * microseconds of stream time).  A negative mode is MPS_EINVAL.
+ * mps_profile_read fills up to n entries, indexed by mps_kernel_class, with
+ * the timed launch count, their summed event time and their algorithmic
+ * bytes and flops.  Not thread-safe.
  * ------------------------------------------------------------------------ */
 typedef enum {
     MPS_K_CONTRACT = 0, /* theta0 = A_i A_{i+1} (MFMA GEMM)                   */
@@ -267,7 +271,7 @@ typedef struct {
     double alg_flops;
 } mps_kernel_stats;
 
-mps_status mps_profile(int enable);
+mps_status mps_profile(int mode);
 mps_status mps_profile_read(mps_kernel_stats* out, int32_t n);
 
 #ifdef __cplusplus

@@ -162,9 +162,12 @@ extern "C" mps_status qrcp_truncate(int64_t m, int64_t n, int64_t k_max, mps_pre
 // ---------------------------------------------------------------------------
 // per-kernel timing
 // ---------------------------------------------------------------------------
-extern "C" mps_status mps_profile(int enable)
+extern "C" mps_status mps_profile(int mode)
 {
-    g_prof.on = enable != 0;
+    if (mode < 0) return fail(MPS_EINVAL, "mps_profile: mode %d < 0", mode);
+    g_prof.on = mode != 0;
+    g_prof.stride = mode > 1 ? mode : 1;
+    g_prof.counter = 0;
     g_prof.pending.clear();
     for (int c = 0; c < PK_COUNT; ++c) g_prof.acc[c] = ProfAcc{0, 0.0, 0.0, 0.0};
     return MPS_OK;

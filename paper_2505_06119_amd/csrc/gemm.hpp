@@ -68,7 +68,10 @@ __device__ __forceinline__ T load_masked(const T* base, int64_t ld, int64_t sr, 
 #define GEMM_BK 16
 #define GEMM_PAD 1
 
-template <typename T, int WM, int WN, bool CA, bool CB, bool MA, bool MB>
+// PF: load the C tile (beta != 0) into registers before the K loop, so that
+// its HBM latency overlaps the operand loads and the MFMAs -- for short-K
+// updates, whose cost is the C read and write.
+template <typename T, int WM, int WN, bool CA, bool CB, bool MA, bool MB, bool PF = false>
 __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g)
 {
     typedef typename MfmaOps<T>::S S;
@@ -87,6 +90,27 @@ __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g)
     if (g.part) {
         kbeg = (int64_t)blockIdx.z * g.kchunk;
         kend = kbeg + g.kchunk < g.K ? kbeg + g.kchunk : g.K;
+    }
+
+    T* C = (T*)g.C;
+    T* P = (T*)g.part;
+    const bool use_beta = (g.beta.x != 0.0 || g.beta.y != 0.0) && !P;
+    T cpf[PF ? WM : 1][PF ? WN : 1][4];
+    if constexpr (PF) {
+        if (use_beta) {
+#pragma unroll
+            for (int i = 0; i < WM; ++i) {
+                const int64_t r = row0 + wr + 16 * i + (lane & 15);
+#pragma unroll
+                for (int j = 0; j < WN; ++j)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int64_t c = col0 + wc + 16 * j + MfmaOps<T>::drow(lane, e);
+                        const int64_t rc = r < g.M ? r : g.M - 1, cc = c < g.N ? c : g.N - 1;
+                        cpf[i][j][e] = C[rc + g.ldc * cc];
+                    }
+            }
+        }
     }
 
     Acc acc_re[WM][WN], acc_im[WM][WN];
@@ -184,14 +208,16 @@ __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g)
 
     // ---- epilogue: lane holds C[row = .. + lane%16][col = .. + drow(lane, e)];
     //      the C loads of one row block are issued together ----
-    T* C = (T*)g.C;
-    T* P = (T*)g.part;
-    const bool use_beta = (g.beta.x != 0.0 || g.beta.y != 0.0) && !P;
 #pragma unroll
     for (int i = 0; i < WM; ++i) {
         const int64_t r = row0 + wr + 16 * i + (lane & 15);
         T cv[WN][4];
-        if (use_beta) {
+        if constexpr (PF) {
+#pragma unroll
+            for (int j = 0; j < WN; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) cv[j][e] = cpf[i][j][e];
+        } else if (use_beta) {
 #pragma unroll
             for (int j = 0; j < WN; ++j)
 #pragma unroll
@@ -245,12 +271,12 @@ static inline int64_t gemm_splitk_bytes(int64_t M, int64_t N, int64_t K, int64_t
     return 16 * M * N * elem;   // at most 16 slices
 }
 
-template <typename T, int WM, int WN, bool CA, bool CB, bool MA, bool MB>
+template <typename T, int WM, int WN, bool CA, bool CB, bool MA, bool MB, bool PF = false>
 static void launch_gemm_cfg(GemmArgs g, hipStream_t st, int nz)
 {
     constexpr int BM = 32 * WM, BN = 32 * WN;
     dim3 grid((unsigned)((g.M + BM - 1) / BM), (unsigned)((g.N + BN - 1) / BN), (unsigned)nz);
-    hipLaunchKernelGGL((k_zgemm<T, WM, WN, CA, CB, MA, MB>), grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL((k_zgemm<T, WM, WN, CA, CB, MA, MB, PF>), grid, dim3(256), 0, st, g);
 }
 
 // Tile shapes per storage type: complex64 uses 128 x 128 tiles for large
@@ -289,8 +315,13 @@ static void launch_gemm_t(GemmArgs g, hipStream_t st, void* scratch, int64_t scr
         g.part = nullptr;
         g.kchunk = g.K;
     }
-    if (big) launch_gemm_cfg<T, BWM, BWN, CA, CB, MA, MB>(g, st, nz);
-    else     launch_gemm_cfg<T, 2, 2, CA, CB, MA, MB>(g, st, nz);
+    const bool beta_nz = g.beta.x != 0.0 || g.beta.y != 0.0;
+    if (big)
+        launch_gemm_cfg<T, BWM, BWN, CA, CB, MA, MB>(g, st, nz);
+    else if (nz == 1 && beta_nz && g.K <= 64)
+        launch_gemm_cfg<T, 2, 2, CA, CB, MA, MB, true>(g, st, nz);
+    else
+        launch_gemm_cfg<T, 2, 2, CA, CB, MA, MB>(g, st, nz);
     if (g.part) {
         int64_t total = g.M * g.N;
         int64_t blocks = (total + 255) / 256;

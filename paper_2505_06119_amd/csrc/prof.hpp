@@ -1,8 +1,10 @@
-// Optional per-kernel timing with HIP events on the launch stream.  When
-// enabled (mps_profile), every timed launch is bracketed by an event pair; the
-// pairs are resolved at the next host synchronisation point of the library
-// and accumulated per kernel class together with the algorithmic bytes and
-// flops of each launch.  Process-global; meant for single-threaded use.
+// Optional per-kernel timing with HIP events on the launch stream.  In mode 1
+// (mps_profile(1)) every timed launch is bracketed by an event pair; in a
+// sampled mode s >= 2 only one pivot-step GEMV launch (k_step_c) in s is, so
+// that the event markers barely perturb the run they measure.  The pairs are
+// resolved at the next host synchronisation point of the library and
+// accumulated per kernel class together with the algorithmic bytes and flops
+// of each launch.  Process-global; meant for single-threaded use.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <vector>
@@ -29,6 +31,8 @@ struct ProfAcc {
 
 struct ProfState {
     bool on = false;
+    int stride = 1;        // 1: every launch of every class; s >= 2: one k_step_c launch in s
+    int64_t counter = 0;
     struct Rec {
         hipEvent_t a, b;
         int cls;
@@ -53,10 +57,12 @@ static hipEvent_t prof_event()
     return e;
 }
 
-// Returns an opaque begin event (or null when profiling is off).
-static inline hipEvent_t prof_begin(hipStream_t st)
+// Returns an opaque begin event (or null when this launch is not timed).
+// cls names the kernel class where the sampled mode has to know it.
+static inline hipEvent_t prof_begin(hipStream_t st, int cls = -1)
 {
     if (!g_prof.on) return nullptr;
+    if (g_prof.stride > 1 && (cls != PK_STEP_C || (g_prof.counter++ % g_prof.stride) != 0)) return nullptr;
     hipEvent_t e = prof_event();
     if (e) (void)hipEventRecord(e, st);
     return e;

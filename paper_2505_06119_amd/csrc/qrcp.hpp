@@ -202,10 +202,12 @@ __global__ __launch_bounds__(256) void k_step_a(QrcpDev<T> d, int64_t j, int64_t
     }
     double2 x = czero();
     if (below) {
-        x = to_d(ap);
+        // four interleaved partial sums shorten the FP64 dependency chain
+        double2 xs[4] = {to_d(ap), czero(), czero(), czero()};
 #pragma unroll
         for (int t = 0; t < JMAX; ++t)
-            if (t < jj) x = csub(x, cmul(make_double2(vre[t], vim[t]), cconj(fp[t])));
+            if (t < jj) xs[t & 3] = csub(xs[t & 3], cmul(make_double2(vre[t], vim[t]), cconj(fp[t])));
+        x = cadd(cadd(xs[0], xs[1]), cadd(xs[2], xs[3]));
         d.xbuf[i] = x;
         d.xlo[i] = from_d<T>(x);
         if (i == j) d.hh[0] = x;
@@ -341,7 +343,7 @@ __device__ __forceinline__ void gemv_cols(const QrcpDev<T>& d, int64_t j, int64_
 // grid: ceil((cend - j - 1) / QR_CW) blocks (at least one); na = step A blocks.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_step_c(QrcpDev<T> d, int64_t j, int64_t p0, int jj, int64_t cend,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 8 : 4))) void k_step_c(QrcpDev<T> d, int64_t j, int64_t p0, int jj, int64_t cend,
                                                 int na)
 {
     __shared__ double2 s_aux[QR_NBMAX], s_vj[QR_NBMAX], s_w[QR_NBMAX];
@@ -440,46 +442,61 @@ __global__ __launch_bounds__(256) void k_step_c(QrcpDev<T> d, int64_t j, int64_t
     block_sum_rs<2 * QR_CW>(acc, red_lds, red_out);   // ends with a barrier: LDS staging visible
     if (stop) return;
 
-    // ---- per-column scalar work (one thread per column) ----
+    // ---- per-column scalar work: wave 0, 16 lanes per column, each lane
+    //      summing the panel terms t = lane % 16 (mod 16), then a 16-lane
+    //      shuffle reduction; lane 0 of each group finishes its column ----
     __shared__ ArgBest s_best[QR_CW];
-    if (tid < QR_CW) {
-        ArgBest best;
-        best.val = -1.0;
-        best.key = 0x7fffffff;
-        best.slot = -1;
-        const int64_t c = cbase + tid;
-        if (c < cend) {
-            const bool moved = d.pivoting && c == p && p != j;
-            const double2 g = make_double2(red_out[2 * tid], red_out[2 * tid + 1]);
-            const double2 ajc = s_arow[tid];
-            double2 w = cadd(cconj(ajc), cmul(scale, g));
-            double2 corr = czero(), rrow = ajc;
-            for (int t = 0; t < jj; ++t) {
-                const double2 f = s_f[tid][t];
+    if (tid < 64) {
+        const int u = tid >> 4, tq = tid & 15;
+        const int64_t c = cbase + u;
+        const bool valid = c < cend;
+        const bool moved = valid && d.pivoting && c == p && p != j;
+        double2 corr = czero(), rs = czero();   // sum_t F[c,t] aux_t, sum_t V[j,t] conj(F[c,t])
+        if (valid) {
+            for (int t = tq; t < jj; t += 16) {
+                const double2 f = s_f[u][t];
                 corr = cadd(corr, cmul(f, s_aux[t]));
-                rrow = csub(rrow, cmul(s_vj[t], cconj(f)));
+                rs = cadd(rs, cmul(s_vj[t], cconj(f)));
                 if (moved) d.F[c + d.ldf * t] = from_d<T>(f);
             }
-            const T fnew_t = from_d<T>(cmul(tau, csub(w, corr)));
-            const double2 fnew = to_d(fnew_t);
-            d.F[c + d.ldf * jj] = fnew_t;
-            rrow = csub(rrow, cconj(fnew));
-            d.A[j + d.lda * c] = from_d<T>(rrow);
-            if (d.pivoting) {
-                double nn = s_nu[tid] - cabs2(rrow);
-                if (nn < 0.0) nn = 0.0;
-                const bool flag = nn <= d.tol * s_nuref[tid];
-                d.nu[c] = nn;
-                if (flag) {
-                    s_flag = 1;
-                } else {
-                    best.val = nn;
-                    best.key = s_perm[tid];
-                    best.slot = (int32_t)c;
+        }
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) {
+            corr.x += __shfl_xor(corr.x, off, MPS_WAVE);
+            corr.y += __shfl_xor(corr.y, off, MPS_WAVE);
+            rs.x += __shfl_xor(rs.x, off, MPS_WAVE);
+            rs.y += __shfl_xor(rs.y, off, MPS_WAVE);
+        }
+        if (tq == 0) {
+            ArgBest best;
+            best.val = -1.0;
+            best.key = 0x7fffffff;
+            best.slot = -1;
+            if (valid) {
+                const double2 g = make_double2(red_out[2 * u], red_out[2 * u + 1]);
+                const double2 ajc = s_arow[u];
+                const double2 w = cadd(cconj(ajc), cmul(scale, g));
+                const T fnew_t = from_d<T>(cmul(tau, csub(w, corr)));
+                const double2 fnew = to_d(fnew_t);
+                d.F[c + d.ldf * jj] = fnew_t;
+                const double2 rrow = csub(csub(ajc, rs), cconj(fnew));
+                d.A[j + d.lda * c] = from_d<T>(rrow);
+                if (d.pivoting) {
+                    double nn = s_nu[u] - cabs2(rrow);
+                    if (nn < 0.0) nn = 0.0;
+                    const bool flag = nn <= d.tol * s_nuref[u];
+                    d.nu[c] = nn;
+                    if (flag) {
+                        s_flag = 1;
+                    } else {
+                        best.val = nn;
+                        best.key = s_perm[u];
+                        best.slot = (int32_t)c;
+                    }
                 }
             }
+            s_best[u] = best;
         }
-        s_best[tid] = best;
     }
 
     // ---- the reflector column below the diagonal, split evenly over the

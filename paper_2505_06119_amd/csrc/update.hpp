@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void k_copy_cols(const T* src, int64_t lds, T*
         dst[i + ldd * c] = src[i + lds * c];
 }
 
-#define UNGQR_NB 32
+#define UNGQR_NB 64
 
 // T factor of a block reflector (forward, columnwise): H_0..H_{nb-1} = I - V T V^H
 // with T[t,t] = tau_t and T[0:t, t] = -tau_t T[0:t, 0:t] (V^H V)[0:t, t].
@@ -258,7 +258,7 @@ static hipError_t run_blocked_fixed(UpdateWs<T>& w, hipStream_t st, QrcpStats* s
             prof_end(ea, st, PK_STEP_A, (double)sizeof(T) * (double)(m - jc) * (jj + 1), 8.0 * (m - jc) * jj);
             const int64_t ncol = pend - jc - 1;
             const unsigned nc = (unsigned)(ncol > 0 ? rup(ncol, QR_CW) : 1);
-            hipEvent_t ec = prof_begin(st);
+            hipEvent_t ec = prof_begin(st, PK_STEP_C);
             hipLaunchKernelGGL((k_step_c<T>), dim3(nc), dim3(256), 0, st, d, jc, p0, jj, pend, (int)na);
             prof_end(ec, st, PK_STEP_C, (double)sizeof(T) * (double)(m - jc) * (double)(ncol > 0 ? ncol : 0),
                      8.0 * (double)(m - jc) * (double)(ncol > 0 ? ncol : 0));
@@ -317,7 +317,7 @@ static hipError_t run_qrcp(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats, int
             prof_end(ea, st, PK_STEP_A, (double)sizeof(T) * (double)(m - jc) * (jj + 1), 8.0 * (m - jc) * jj);
             int64_t ncol = n - jc - 1;
             unsigned nc = (unsigned)(ncol > 0 ? rup(ncol, QR_CW) : 1);
-            hipEvent_t ec = prof_begin(st);
+            hipEvent_t ec = prof_begin(st, PK_STEP_C);
             hipLaunchKernelGGL((k_step_c<T>), dim3(nc), dim3(256), 0, st, d, jc, p0, jj, n, (int)na);
             nparts = (int)nc;
             // algorithmic traffic of one step: one read of the trailing block
