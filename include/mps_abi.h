@@ -64,7 +64,7 @@ typedef struct {
     int32_t fallback;     /* learned pivots rejected, plain QRCP used (0/1)          */
     int32_t panels;       /* QR panels processed                                     */
     int32_t refreshes;    /* exact recomputations of the residual column norms       */
-    int32_t pad;
+    int32_t window_misses;/* candidate-window panels the greedy replay cut short     */
     double learned_err_sq;/* learned pivots: ||R22||^2 of the proposed order (-1: n/a) */
     double qrcp_err_sq;   /* ||R22||^2 of plain pivoted QR when it ran (-1: n/a)      */
 } mps_update_info;
@@ -241,6 +241,20 @@ mps_status mps_centre(const mps_ctx* ctx, int32_t* out);
 mps_status mps_get_site(mps_ctx* ctx, int32_t j, void* dst, int64_t dst_bytes);
 
 /* ------------------------------------------------------------------------
+ * Tuning of the pivoted QR, process-wide (not thread-safe; affects later
+ * calls).  panel_width: 16, 32 or 64 pivot steps per delayed-update panel
+ * (0: automatic, 16 for n <= 64 and 32 otherwise).  qr_window: width W of the
+ * candidate window of the pivoted panels (-1: automatic, 256; 0: off, every
+ * pivot step reads the whole trailing block; otherwise 64 <= W <= 512).  A
+ * window panel factorises up to panel_width steps inside the W columns of
+ * largest residual norm and accepts them only as far as a greedy replay
+ * against all other columns confirms them, so the pivots are those of the
+ * full search; a window narrower than the panel width is not used.  Returns
+ * MPS_EINVAL for values outside these sets (nothing changes then).
+ * ------------------------------------------------------------------------ */
+mps_status mps_set_tuning(int32_t panel_width, int32_t qr_window);
+
+/* ------------------------------------------------------------------------
  * Per-kernel timing.  mps_profile(mode) resets the counters and sets the
  * process-wide timing of the library's launches with HIP events recorded on
  * the caller's stream: mode 0 off; mode 1 every launch of every class; mode
@@ -261,7 +275,8 @@ typedef enum {
     MPS_K_UNGQR = 6,    /* Q_k formation (MFMA)                               */
     MPS_K_SPLIT = 7,    /* R_k P^T scatter into the right site                */
     MPS_K_PROPOSE = 8,  /* learned proposal: sketch, features, scores, order  */
-    MPS_K_COUNT = 9
+    MPS_K_WINDOW = 9,   /* candidate-window selection, swaps, greedy replay   */
+    MPS_K_COUNT = 10
 } mps_kernel_class;
 
 typedef struct {

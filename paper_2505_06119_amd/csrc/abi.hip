@@ -4,7 +4,6 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
-#include <stdlib.h>
 #include <string.h>
 
 #include <string>
@@ -46,22 +45,40 @@ extern "C" const char* mps_last_error(void) { return g_err.c_str(); }
 static inline int64_t elem_bytes(mps_precision p) { return p == MPS_FP64 ? 16 : 8; }
 static inline bool valid_prec(int p) { return p == MPS_FP64 || p == MPS_MIXED; }
 
-// Default panel width of the delayed-update QRCP.
+// Tuning of the pivoted QR (mps_set_tuning): panel width (0: automatic) and
+// candidate-window width (-1: automatic, 0: off).
+static int g_panel_width = 0;
+static int g_qr_window = -1;
+#define QR_WIN_DEFAULT 256
+
 // Panel width of the delayed-update QRCP: wider panels raise the arithmetic
 // intensity of the rank-nb trailing update but lengthen every pivot step's
-// F-correction; MPS_PANEL_WIDTH (16, 32 or 64) overrides the rule for tuning.
+// F-correction.
 static int panel_width(int64_t m, int64_t n)
 {
     (void)m;
-    static int forced = -1;
-    if (forced < 0) {
-        const char* e = getenv("MPS_PANEL_WIDTH");
-        const int v = e ? atoi(e) : 0;
-        forced = (v == 16 || v == 32 || v == 64) ? v : 0;
-    }
-    if (forced > 0) return n <= 64 && forced > 16 ? 16 : forced;
+    if (g_panel_width > 0) return n <= 64 && g_panel_width > 16 ? 16 : g_panel_width;
     if (n <= 64) return 16;
     return 32;
+}
+
+// Candidate-window width for a pivoted factorisation with panel width nb
+// (0: no window panels).
+static int qr_window(int nb)
+{
+    const int w = g_qr_window < 0 ? QR_WIN_DEFAULT : g_qr_window;
+    return w >= nb && w <= QR_WIN_MAX ? w : 0;
+}
+
+extern "C" mps_status mps_set_tuning(int32_t panel_width_, int32_t qr_window_)
+{
+    if (panel_width_ != 0 && panel_width_ != 16 && panel_width_ != 32 && panel_width_ != 64)
+        return fail(MPS_EINVAL, "mps_set_tuning: panel width %d not in {0, 16, 32, 64}", (int)panel_width_);
+    if (qr_window_ < -1 || qr_window_ > QR_WIN_MAX || (qr_window_ > 0 && qr_window_ < 64))
+        return fail(MPS_EINVAL, "mps_set_tuning: window %d not -1, 0 or in [64, %d]", (int)qr_window_, QR_WIN_MAX);
+    g_panel_width = panel_width_;
+    g_qr_window = qr_window_;
+    return MPS_OK;
 }
 
 static double recompute_tol(mps_precision p)
@@ -102,6 +119,7 @@ static mps_status qrcp_impl(int64_t m, int64_t n, int64_t k, mps_precision prec,
     if (!carve_update_ws<T>(cv, w, m, n, k, true))
         return fail(MPS_ENOMEM, "qrcp_truncate: work_bytes %lld too small", (long long)work_bytes);
     w.nb = panel_width(m, n);
+    w.win = qr_window(w.nb);
     w.d.tol = recompute_tol(prec);
     w.d.pivoting = 1;
     if (n > 0 && m > 0) {

@@ -71,12 +71,15 @@ __device__ __forceinline__ T load_masked(const T* base, int64_t ld, int64_t sr, 
 // PF: load the C tile (beta != 0) into registers before the K loop, so that
 // its HBM latency overlaps the operand loads and the MFMAs -- for short-K
 // updates, whose cost is the C read and write.
-template <typename T, int WM, int WN, bool CA, bool CB, bool MA, bool MB, bool PF = false>
+// BK: K depth of one LDS stage.  Long-K slices of small-tile products use 64
+// (complex64) or 32 (complex128), so that each stage streams more of the
+// operands per synchronisation.
+template <typename T, int WM, int WN, bool CA, bool CB, bool MA, bool MB, bool PF = false, int BK = GEMM_BK>
 __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g)
 {
     typedef typename MfmaOps<T>::S S;
     typedef typename MfmaOps<T>::Acc Acc;
-    constexpr int BM = 32 * WM, BN = 32 * WN, BK = GEMM_BK;
+    constexpr int BM = 32 * WM, BN = 32 * WN;
     __shared__ S As_re[BK][BM + GEMM_PAD], As_im[BK][BM + GEMM_PAD];
     __shared__ S Bs_re[BK][BN + GEMM_PAD], Bs_im[BK][BN + GEMM_PAD];
 
@@ -178,7 +181,7 @@ __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g)
         store_tile();
         __syncthreads();
         if (k0 + BK < kend) load_tile(k0 + BK);
-#pragma unroll
+#pragma unroll 4
         for (int ks = 0; ks < BK; ks += 4) {
             const int kk = ks + (lane >> 4);
             S ar[WM], ai[WM], br[WN], bi[WN], nbi[WN];
@@ -271,12 +274,12 @@ static inline int64_t gemm_splitk_bytes(int64_t M, int64_t N, int64_t K, int64_t
     return 16 * M * N * elem;   // at most 16 slices
 }
 
-template <typename T, int WM, int WN, bool CA, bool CB, bool MA, bool MB, bool PF = false>
+template <typename T, int WM, int WN, bool CA, bool CB, bool MA, bool MB, bool PF = false, int BK = GEMM_BK>
 static void launch_gemm_cfg(GemmArgs g, hipStream_t st, int nz)
 {
     constexpr int BM = 32 * WM, BN = 32 * WN;
     dim3 grid((unsigned)((g.M + BM - 1) / BM), (unsigned)((g.N + BN - 1) / BN), (unsigned)nz);
-    hipLaunchKernelGGL((k_zgemm<T, WM, WN, CA, CB, MA, MB, PF>), grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL((k_zgemm<T, WM, WN, CA, CB, MA, MB, PF, BK>), grid, dim3(256), 0, st, g);
 }
 
 // Tile shapes per storage type: complex64 uses 128 x 128 tiles for large
@@ -293,21 +296,29 @@ static void launch_gemm_t(GemmArgs g, hipStream_t st, void* scratch, int64_t scr
     // Large tiles only pay off for long K; a rank-k update with k <= 64 is
     // memory-bound and wants many resident blocks to overlap C traffic.
     const bool big = g.M >= 512 && g.N >= 512 && g.K > 64;
-    const int64_t BM = big ? 32 * BWM : 64, BN = big ? 32 * BWN : 64;
+    // at most 32 rows (the V^H A products of a panel): 32 x 128 tiles
+    const bool thin = !big && g.M <= 32;
+    const int64_t BM = big ? 32 * BWM : (thin ? 32 : 64), BN = big ? 32 * BWN : (thin ? 128 : 64);
     const int64_t tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
     int nz = 1;
     if (g.K > 0 && tiles < 256 && g.K >= 512 && scratch) {
-        int64_t want = 512 / tiles;
-        int64_t maxz = g.K / 256;
+        // enough K slices for ~2048 blocks: a short-M, long-K product streams
+        // its B operand and needs every CU busy with several blocks
+        int64_t want = 2048 / tiles;
+        int64_t maxz = g.K / 128;
         nz = (int)(want < maxz ? want : maxz);
-        if (nz > 16) nz = 16;
+        if (nz > 64) nz = 64;
         if (nz < 1) nz = 1;
         const int64_t fit = scratch_bytes / (g.M * g.N * (int64_t)sizeof(T));
         if (nz > fit) nz = (int)(fit > 1 ? fit : 1);
     }
+    // deep K stages for long slices of a small-tile product
+    constexpr int DBK = sizeof(T) == 8 ? 32 : 16;
+    const bool deep = !big && (nz > 1 ? g.K / nz : g.K) >= 256;
+    const int64_t bk = deep ? DBK : GEMM_BK;
     if (nz > 1) {
         int64_t chunk = (g.K + nz - 1) / nz;
-        chunk = (chunk + GEMM_BK - 1) / GEMM_BK * GEMM_BK;
+        chunk = (chunk + bk - 1) / bk * bk;
         nz = (int)((g.K + chunk - 1) / chunk);
         g.kchunk = chunk;
         g.part = scratch;
@@ -318,8 +329,14 @@ static void launch_gemm_t(GemmArgs g, hipStream_t st, void* scratch, int64_t scr
     const bool beta_nz = g.beta.x != 0.0 || g.beta.y != 0.0;
     if (big)
         launch_gemm_cfg<T, BWM, BWN, CA, CB, MA, MB>(g, st, nz);
-    else if (nz == 1 && beta_nz && g.K <= 64)
+    else if (nz == 1 && beta_nz && g.K <= 64 && !thin)
         launch_gemm_cfg<T, 2, 2, CA, CB, MA, MB, true>(g, st, nz);
+    else if (thin && deep)
+        launch_gemm_cfg<T, 1, 4, CA, CB, MA, MB, false, DBK>(g, st, nz);
+    else if (thin)
+        launch_gemm_cfg<T, 1, 4, CA, CB, MA, MB>(g, st, nz);
+    else if (deep)
+        launch_gemm_cfg<T, 2, 2, CA, CB, MA, MB, false, DBK>(g, st, nz);
     else
         launch_gemm_cfg<T, 2, 2, CA, CB, MA, MB>(g, st, nz);
     if (g.part) {

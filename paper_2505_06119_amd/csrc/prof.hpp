@@ -19,7 +19,8 @@ enum {
     PK_UNGQR = 6,     // Q formation
     PK_SPLIT = 7,     // R P^T scatter
     PK_PROPOSE = 8,   // learned proposal: sketch, features, scores, order, gather
-    PK_COUNT = 9
+    PK_WINDOW = 9,    // candidate-window selection, swaps, saves and greedy replay
+    PK_COUNT = 10
 };
 
 struct ProfAcc {

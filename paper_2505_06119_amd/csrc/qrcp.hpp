@@ -43,6 +43,8 @@ enum {
     CTL_PIV = 0,      // pivot position of the current step (written by step A)
     CTL_STOP = 1,     // panel must end: a norm needs recomputing
     CTL_JDONE = 2,    // number of completed steps
+    CTL_TFAIL = 3,    // window panels: first step whose greedy replay fails
+    CTL_TFLAG = 4,    // window panels: first step after which a norm needs recomputing, plus one
     CTL_COUNT = 16
 };
 enum { DSC_NORM2 = 0, DSC_EPS2 = 1, DSC_COUNT = 8 };
@@ -63,6 +65,8 @@ struct QrcpDev {
     double* apart;     // step-A partials, (2 + 2*QR_NBMAX) doubles per block
     double2* hh;       // [0] alpha (written by the block holding row j)
     double2* fsave;    // QR_NBMAX
+    double* pivval;    // QR_NBMAX: downdated norm of each step's pivot at its step
+    int32_t* pivkey;   // QR_NBMAX: its key (original column index)
     ArgBest* cpart;    // argmax partials of the last producer (gate, norms, step C)
     int32_t* cflag;    // per-partial "a norm needs recomputing" flags
     double* npart;     // per-block partial sums of squares
@@ -176,7 +180,11 @@ __global__ __launch_bounds__(256) void k_step_a(QrcpDev<T> d, int64_t j, int64_t
             return;
         }
         if (bb.slot >= j) p = bb.slot;
-        if (blockIdx.x == 0 && tid == 0) d.ctl[CTL_PIV] = (int32_t)p;
+        if (blockIdx.x == 0 && tid == 0) {
+            d.ctl[CTL_PIV] = (int32_t)p;
+            d.pivval[jj] = bb.slot >= j ? bb.val : -1.0;
+            d.pivkey[jj] = bb.key;
+        }
     } else if (stop) {
         return;
     }
@@ -340,51 +348,138 @@ __device__ __forceinline__ void gemv_cols(const QrcpDev<T>& d, int64_t j, int64_
 // ---------------------------------------------------------------------------
 // step C: reflector from step A's partials, GEMV over the trailing block,
 // new F column, pivot row of R, downdate + per-block argmax partial.
-// grid: ceil((cend - j - 1) / QR_CW) blocks (at least one); na = step A blocks.
+// grid: ceil((cend - j - 1) / CW) blocks (at least one); na = step A blocks.
+// CW columns per block: 4 over a full trailing block, 1 over a narrow window
+// (more blocks for the same columns).
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 8 : 4))) void k_step_c(QrcpDev<T> d, int64_t j, int64_t p0, int jj, int64_t cend,
-                                                int na)
+template <typename T, int CW = QR_CW>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CW == 1 ? 1 : (sizeof(T) == 8 ? 8 : 4))))
+void k_step_c(QrcpDev<T> d, int64_t j, int64_t p0, int jj, int64_t cend, int na)
 {
     __shared__ double2 s_aux[QR_NBMAX], s_vj[QR_NBMAX], s_w[QR_NBMAX];
     __shared__ double2 s_par[4];   // beta, tau, scale, alpha
-    __shared__ double red_lds[4 * 2 * QR_CW];
-    __shared__ double red_out[2 * QR_CW];
-    // the stop flag is read now and tested before the first store, so its
-    // latency overlaps the prologue loads (everything before it only reads)
-    const int32_t stop = d.ctl[CTL_STOP];
-
-    const int tid = threadIdx.x;
-    // ---- reflector from step A's partials (identical in every block).  The
-    //      S = 1 + 2*jj values of each step-A block are summed by G = 256/S
-    //      thread groups in parallel, then the G group sums in a fixed order ----
+    __shared__ double red_lds[4 * 2 * CW];
+    __shared__ double red_out[2 * CW];
     __shared__ double s_red[256];
     __shared__ double s_tot[2 * QR_NBMAX + 1];
     __shared__ int s_flag;
-    {
-        const int S = 1 + 2 * jj, G = 256 / S;
-        const int slot = tid % S, grp = tid / S;
-        double acc = 0.0;
-        if (grp < G) {
-            const int off = slot == 0 ? 0 : slot + 1;    // rest at 0, W re/im from 2
-#pragma unroll 4
-            for (int b = grp; b < na; b += G) acc += d.apart[(int64_t)b * APART_STRIDE + off];
+    __shared__ double2 s_f[CW][QR_NBMAX];
+    __shared__ double2 s_arow[CW];
+    __shared__ double s_nu[CW], s_nuref[CW];
+    __shared__ int32_t s_perm[CW];
+
+    // Every load that does not depend on another is issued first: the stop
+    // flag (tested before the first store), step A's partials, this block's
+    // F rows and column scalars, then the GEMV stream.  Only then do the
+    // reductions and the reflector arithmetic wait on them.
+    const int32_t stop = d.ctl[CTL_STOP];
+    const int tid = threadIdx.x;
+    const int64_t p = d.pivoting ? (int64_t)d.ctl[CTL_PIV] : j;
+    const int64_t cbase = j + 1 + (int64_t)blockIdx.x * CW;
+
+    // step A's partials: the S = 1 + 2*jj values of each step-A block are
+    // summed by G = 256/S thread groups (group g takes blocks g, g+G, ...)
+    const int S = 1 + 2 * jj, G = 256 / S;
+    const int slot = tid % S, grp = tid / S;
+    const int off = slot == 0 ? 0 : slot + 1;    // rest at 0, W re/im from 2
+    // (held in registers across the GEMV only by the one-column variant, whose
+    // occupancy does not matter; the wide variant loads them after the GEMV)
+    constexpr int NPV = CW == 1 ? 16 : 0;
+    double pv[NPV > 0 ? NPV : 1];
+    pv[0] = 0.0;
+#pragma unroll
+    for (int u = 0; u < NPV; ++u) {
+        // unconditional loads from clamped indices, masked afterwards
+        const int b = grp + u * G;
+        const int bc = (grp < G && b < na) ? b : 0;
+        pv[u] = d.apart[(int64_t)bc * APART_STRIDE + off];
+    }
+#pragma unroll
+    for (int u = 0; u < NPV; ++u) pv[u] = (grp < G && grp + u * G < na) ? pv[u] : 0.0;
+    const double2 alpha_st = CW == 1 ? d.hh[0] : czero();
+    // staged operands of the per-column work (at most one F entry per thread)
+    double2 f_st = czero();
+    const bool has_f = tid < CW * jj && cbase + tid % CW < cend;
+    if (has_f) {
+        const int u = tid % CW, t = tid / CW;
+        const int64_t c = cbase + u;
+        f_st = (d.pivoting && c == p && p != j) ? d.fsave[t] : to_d(d.F[c + d.ldf * t]);
+    }
+    double2 arow_st = czero(), vj_st = czero();
+    double nu_st = 0.0, nuref_st = 0.0;
+    int32_t perm_st = 0;
+    if (tid < CW && cbase + tid < cend) {
+        const int64_t c = cbase + tid;
+        arow_st = to_d(d.A[j + d.lda * c]);
+        if (d.pivoting) {
+            nu_st = d.nu[c];
+            nuref_st = d.nuref[c];
+            perm_st = d.perm[c];
         }
-        s_red[tid] = acc;
-        if (tid < jj) s_vj[tid] = to_d(d.A[j + d.lda * (p0 + tid)]);
+    }
+    if (tid < jj) vj_st = to_d(d.A[j + d.lda * (p0 + tid)]);
+    // this block's share of the reflector column (stored at the end): rows
+    // [vr0, vr1); the one-column variant fetches its first 256 rows now
+    const int64_t vlen = d.m - j - 1;
+    const int64_t vchunk = (vlen + gridDim.x - 1) / gridDim.x;
+    const int64_t vr0 = j + 1 + (int64_t)blockIdx.x * vchunk;
+    const int64_t vr1 = vr0 + vchunk < d.m ? vr0 + vchunk : d.m;
+    double2 xv_st = czero();
+    if constexpr (CW == 1) {
+        const int64_t i = vr0 + tid < d.m ? vr0 + tid : d.m - 1;   // clamped, masked at the store
+        xv_st = d.xbuf[i];
+    }
+    auto stage = [&]() {
+        if (has_f) s_f[tid % CW][tid / CW] = f_st;
+        if (tid < CW) {
+            s_arow[tid] = arow_st;
+            s_nu[tid] = nu_st;
+            s_nuref[tid] = nuref_st;
+            s_perm[tid] = perm_st;
+        }
+        if (tid < jj) s_vj[tid] = vj_st;
+    };
+    // the wide variant parks the staged values in LDS now (its occupancy
+    // needs the registers during the GEMV); the one-column variant after it
+    if constexpr (CW > 1) stage();
+
+    // ---- GEMV: g_u = sum_{i>j} conj(A[i, c_u]) x_i (independent of the reflector scalars) ----
+    double acc[2 * CW];
+    // one column per block (window panels): many rows in flight per thread instead
+    gemv_cols<T, CW, CW == 1 ? 16 : (sizeof(T) == 8 ? 1 : 4)>(d, j, cbase, cend, acc);
+
+    // ---- reflector from step A's partials (identical in every block) ----
+    {
+        double sacc = 0.0;
+#pragma unroll
+        for (int u = 0; u < NPV; ++u) sacc += pv[u];
+        if (grp < G) {
+            for (int b0 = grp + NPV * G; b0 < na; b0 += 16 * G) {   // the partials not loaded above
+                double v[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int b = b0 + u * G;
+                    v[u] = b < na ? d.apart[(int64_t)b * APART_STRIDE + off] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 16; ++u) sacc += v[u];
+            }
+        }
+        s_red[tid] = grp < G ? sacc : 0.0;
+        if constexpr (CW == 1) stage();
         if (tid == 0) s_flag = 0;
         __syncthreads();
         if (tid < S) {
-            double s = 0.0;
-            for (int g = 0; g < G; ++g) s += s_red[g * S + tid];
-            s_tot[tid] = s;
+            double s2 = 0.0;
+            for (int g = 0; g < G; ++g) s2 += s_red[g * S + tid];
+            s_tot[tid] = s2;
         }
         __syncthreads();
     }
     if (tid < jj) s_w[tid] = make_double2(s_tot[1 + 2 * tid], s_tot[2 + 2 * tid]);
     if (tid == 64) {
         const double rest = s_tot[0];
-        const double2 alpha = d.hh[0];
+        const double2 alpha = CW == 1 ? alpha_st : d.hh[0];
         double2 tau, scale;
         double beta;
         if (rest == 0.0 && alpha.y == 0.0) {
@@ -409,44 +504,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         const double2 rest = csub(s_w[tid], cmul(vjt, s_par[3]));
         s_aux[tid] = cadd(vjt, cmul(s_par[2], rest));
     }
-    __syncthreads();
+    // (the barrier that publishes s_aux is the GEMV reduction's)
     const double beta = s_par[0].x;
     const double2 tau = s_par[1], scale = s_par[2];
-    const int64_t p = d.pivoting ? (int64_t)d.ctl[CTL_PIV] : j;
-    const int64_t cbase = j + 1 + (int64_t)blockIdx.x * QR_CW;
-
-    // ---- stage this block's F rows and column scalars in LDS; the loads
-    //      complete while the GEMV streams the trailing block ----
-    __shared__ double2 s_f[QR_CW][QR_NBMAX];
-    __shared__ double2 s_arow[QR_CW];
-    __shared__ double s_nu[QR_CW], s_nuref[QR_CW];
-    __shared__ int32_t s_perm[QR_CW];
-    for (int q = tid; q < QR_CW * jj; q += 256) {
-        const int u = q % QR_CW, t = q / QR_CW;
-        const int64_t c = cbase + u;
-        if (c < cend) s_f[u][t] = (d.pivoting && c == p && p != j) ? d.fsave[t] : to_d(d.F[c + d.ldf * t]);
-    }
-    if (tid < QR_CW && cbase + tid < cend) {
-        const int64_t c = cbase + tid;
-        s_arow[tid] = to_d(d.A[j + d.lda * c]);
-        if (d.pivoting) {
-            s_nu[tid] = d.nu[c];
-            s_nuref[tid] = d.nuref[c];
-            s_perm[tid] = d.perm[c];
-        }
-    }
-
-    // ---- GEMV: g_u = sum_{i>j} conj(A[i, c_u]) x_i ----
-    double acc[2 * QR_CW];
-    gemv_cols<T, QR_CW>(d, j, cbase, cend, acc);
-    block_sum_rs<2 * QR_CW>(acc, red_lds, red_out);   // ends with a barrier: LDS staging visible
+    block_sum_rs<2 * CW>(acc, red_lds, red_out);
     if (stop) return;
 
     // ---- per-column scalar work: wave 0, 16 lanes per column, each lane
     //      summing the panel terms t = lane % 16 (mod 16), then a 16-lane
     //      shuffle reduction; lane 0 of each group finishes its column ----
-    __shared__ ArgBest s_best[QR_CW];
-    if (tid < 64) {
+    __shared__ ArgBest s_best[CW];
+    if (tid < 16 * CW) {
         const int u = tid >> 4, tq = tid & 15;
         const int64_t c = cbase + u;
         const bool valid = c < cend;
@@ -502,11 +570,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     // ---- the reflector column below the diagonal, split evenly over the
     //      blocks; block 0 also stores R_jj, tau and the progress counter ----
     {
-        const int64_t len = d.m - j - 1;
-        const int64_t chunk = (len + gridDim.x - 1) / gridDim.x;
-        const int64_t r0 = j + 1 + (int64_t)blockIdx.x * chunk;
-        const int64_t r1 = r0 + chunk < d.m ? r0 + chunk : d.m;
-        for (int64_t i = r0 + tid; i < r1; i += 256) d.A[i + d.lda * j] = from_d<T>(cmul(scale, d.xbuf[i]));
+        int64_t i = vr0 + tid;
+        if constexpr (CW == 1) {
+            if (i < vr1) d.A[i + d.lda * j] = from_d<T>(cmul(scale, xv_st));
+            i += 256;
+        }
+        for (; i < vr1; i += 256) d.A[i + d.lda * j] = from_d<T>(cmul(scale, d.xbuf[i]));
     }
     if (blockIdx.x == 0 && tid == 0) {
         d.A[j + d.lda * j] = from_d<T>(make_double2(beta, 0.0));
@@ -518,7 +587,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     __syncthreads();   // publishes s_best and s_flag
     if (tid == 0) {
         ArgBest b = s_best[0];
-        for (int u = 1; u < QR_CW; ++u)
+        for (int u = 1; u < CW; ++u)
             if (arg_better(s_best[u].val, s_best[u].key, b.val, b.key)) b = s_best[u];
         d.cpart[blockIdx.x] = b;
         d.cflag[blockIdx.x] = s_flag;

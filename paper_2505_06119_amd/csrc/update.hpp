@@ -19,6 +19,7 @@
 #include "gemm.hpp"
 #include "prof.hpp"
 #include "qrcp.hpp"
+#include "window.hpp"
 
 struct Gate4 {
     double2 g[16];   // row-major: g[4*(2a'+b') + (2a+b)]
@@ -124,33 +125,37 @@ __global__ __launch_bounds__(256) void k_copy_cols(const T* src, int64_t lds, T*
 
 // T factor of a block reflector (forward, columnwise): H_0..H_{nb-1} = I - V T V^H
 // with T[t,t] = tau_t and T[0:t, t] = -tau_t T[0:t, 0:t] (V^H V)[0:t, t].
-// One block of 64 threads; G = V^H V (nb x nb, ld UNGQR_NB) from a GEMM.
+// One block of 256 threads (four per row of T); G = V^H V (nb x nb, ld
+// UNGQR_NB) from a GEMM.  Writes T[0:nb, 0:nb] (ld UNGQR_NB).
 template <typename T>
-__global__ __launch_bounds__(64) void k_larft(const T* G, const double2* tau, int nb, T* Tout)
+__global__ __launch_bounds__(256) void k_larft(const T* G, const double2* tau, int nb, T* Tout)
 {
     __shared__ double2 Ts[UNGQR_NB][UNGQR_NB + 1];
     __shared__ double2 Gs[UNGQR_NB][UNGQR_NB + 1];
-    const int s = threadIdx.x;
-    for (int q = s; q < UNGQR_NB * UNGQR_NB; q += 64) {
-        const int r = q % UNGQR_NB, c = q / UNGQR_NB;
-        Gs[r][c] = (r < nb && c < nb) ? to_d(G[r + UNGQR_NB * c]) : czero();
+    const int tid = threadIdx.x;
+    for (int q = tid; q < nb * nb; q += 256) {
+        const int r = q % nb, c = q / nb;
+        Gs[r][c] = to_d(G[r + UNGQR_NB * c]);
         Ts[r][c] = czero();
     }
     __syncthreads();
+    const int s = tid >> 2, part = tid & 3;
     for (int t = 0; t < nb; ++t) {
-        const double2 tt = tau[t];
         double2 v = czero();
-        if (s < t) {
-            for (int u = s; u < t; ++u) v = cadd(v, cmul(Ts[s][u], Gs[u][t]));
-            v = cscale(cmul(tt, v), -1.0);
-        }
-        __syncthreads();
-        if (s < t) Ts[s][t] = v;
-        if (s == t) Ts[s][t] = tt;
-        __syncthreads();
+        if (s < t)
+            for (int u = s + part; u < t; u += 4) v = cadd(v, cmul(Ts[s][u], Gs[u][t]));
+        // the four parts of row s sit in adjacent lanes of one wave
+        v.x += __shfl_xor(v.x, 1, MPS_WAVE);
+        v.y += __shfl_xor(v.y, 1, MPS_WAVE);
+        v.x += __shfl_xor(v.x, 2, MPS_WAVE);
+        v.y += __shfl_xor(v.y, 2, MPS_WAVE);
+        const double2 tt = tau[t];
+        if (part == 0 && s < t) Ts[s][t] = cscale(cmul(tt, v), -1.0);
+        if (part == 0 && s == t) Ts[s][t] = tt;
+        __syncthreads();   // column t is read from the next step on
     }
-    for (int q = s; q < UNGQR_NB * UNGQR_NB; q += 64) {
-        const int r = q % UNGQR_NB, c = q / UNGQR_NB;
+    for (int q = tid; q < nb * nb; q += 256) {
+        const int r = q % nb, c = q / nb;
         Tout[r + UNGQR_NB * c] = from_d<T>(Ts[r][c]);
     }
 }
@@ -178,6 +183,13 @@ struct UpdateWs {
     void* gsplit;  // split-K scratch
     int64_t gsplit_bytes;
     int nb;        // QRCP panel width
+    int win;       // candidate-window width of the pivoted panels (0: every panel reads the whole trailing block)
+    int32_t* wplan;          // 1 + 2 * QR_WIN_MAX: swap plan of a window selection
+    T* wsave;                // min(QR_WIN_MAX, n) columns of lda: the window state at the panel start
+    double* wsnu;            // QR_WIN_MAX
+    double* wsnuref;         // QR_WIN_MAX
+    int32_t* wsperm;         // QR_WIN_MAX
+    int32_t* wpart;          // 2 per 256 columns: greedy-replay partials
 };
 
 static inline int64_t rup(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -203,6 +215,8 @@ static bool carve_update_ws(Carver& cv, UpdateWs<T>& w, int64_t m, int64_t n, in
     d.apart = (double*)cv.take(8 * APART_STRIDE * (rup(m, 256) + 1));
     d.hh = (double2*)cv.take(16 * (4 + QR_NBMAX));
     d.fsave = (double2*)cv.take(16 * QR_NBMAX);
+    d.pivval = (double*)cv.take(8 * QR_NBMAX);
+    d.pivkey = (int32_t*)cv.take(4 * QR_NBMAX);
     const int64_t np = rup(n, QR_CW) + rup(n, 2) + 8;
     d.cpart = (ArgBest*)cv.take((int64_t)sizeof(ArgBest) * np);
     d.npart = (double*)cv.take(8 * np);
@@ -218,8 +232,17 @@ static bool carve_update_ws(Carver& cv, UpdateWs<T>& w, int64_t m, int64_t n, in
     const int64_t sk = (int64_t)sizeof(T) * 16 * UNGQR_NB * (wcols > UNGQR_NB ? wcols : UNGQR_NB);
     w.gsplit = cv.take(sk);
     w.gsplit_bytes = sk;
+    const int64_t wmax = n < QR_WIN_MAX ? n : QR_WIN_MAX;
+    w.wplan = (int32_t*)cv.take(4 * (1 + 2 * QR_WIN_MAX));
+    w.wsave = (T*)cv.take((int64_t)sizeof(T) * d.lda * (wmax > 0 ? wmax : 1));
+    w.wsnu = (double*)cv.take(8 * QR_WIN_MAX);
+    w.wsnuref = (double*)cv.take(8 * QR_WIN_MAX);
+    w.wsperm = (int32_t*)cv.take(4 * QR_WIN_MAX);
+    w.wpart = (int32_t*)cv.take(8 * (rup(n, 256) + 1));
+    w.win = 0;
     return d.nu && d.nuref && d.perm && d.F && d.tau && d.diagR && d.xbuf && d.xlo && d.apart && d.hh && d.fsave &&
            d.cpart && d.npart && d.cflag && d.ctl && d.dsc && w.Gbuf && w.Tbuf && w.Wbuf && w.W2buf && w.gsplit &&
+           d.pivval && d.pivkey && w.wplan && w.wsave && w.wsnu && w.wsnuref && w.wsperm && w.wpart &&
            (!theta_in_ws || d.A);
 }
 
@@ -230,6 +253,7 @@ static const double2 C_ZERO = {0.0, 0.0};
 struct QrcpStats {
     int panels = 0;
     int refreshes = 0;
+    int window_misses = 0;   // window panels cut short by the greedy replay
 };
 
 // a4-a10 on d.A; expects nu/nuref/perm/ctl[PIV] set up (pivoting) and the
@@ -272,7 +296,7 @@ static hipError_t run_blocked_fixed(UpdateWs<T>& w, hipStream_t st, QrcpStats* s
         if (!zgemm<T>(st, OP_C, true, OP_N, true, nbe, nbe, rows, C_ONE, V, d.lda, V, d.lda, C_ZERO, w.Gbuf,
                       UNGQR_NB, w.gsplit, w.gsplit_bytes))
             return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_larft<T>), dim3(1), dim3(64), 0, st, w.Gbuf, d.tau + p0, nbe, w.Tbuf);
+        hipLaunchKernelGGL((k_larft<T>), dim3(1), dim3(256), 0, st, w.Gbuf, d.tau + p0, nbe, w.Tbuf);
         if (!zgemm<T>(st, OP_C, true, OP_N, false, nbe, cols, rows, C_ONE, V, d.lda, At, d.lda, C_ZERO, w.Wbuf,
                       UNGQR_NB, w.gsplit, w.gsplit_bytes))
             return hipErrorInvalidValue;
@@ -295,6 +319,179 @@ static hipError_t run_blocked_fixed(UpdateWs<T>& w, hipStream_t st, QrcpStats* s
     return hipGetLastError();
 }
 
+// Pivot steps jc = p0 .. p0+nsteps-1 of one panel; step C covers the columns
+// up to cend (the whole trailing block, or a candidate window with one column
+// per block).  Returns the number of argmax partials of the last step C.
+template <typename T>
+static int run_panel_steps(QrcpDev<T>& d, hipStream_t st, int64_t p0, int64_t nsteps, int64_t cend, bool window,
+                           int nparts)
+{
+    const int64_t m = d.m;
+    const unsigned na = (unsigned)rup(m, 256);
+    for (int64_t jc = p0; jc < p0 + nsteps; ++jc) {
+        const int jj = (int)(jc - p0);
+        hipEvent_t ea = prof_begin(st);
+        launch_step_a<T>(d, na, jc, p0, jj, nparts, st);
+        prof_end(ea, st, PK_STEP_A, (double)sizeof(T) * (double)(m - jc) * (jj + 1), 8.0 * (m - jc) * jj);
+        const int64_t ncol = cend - jc - 1;
+        const int cw = window ? 1 : QR_CW;
+        const unsigned nc = (unsigned)(ncol > 0 ? rup(ncol, cw) : 1);
+        hipEvent_t ec = prof_begin(st, PK_STEP_C);
+        if (window)
+            hipLaunchKernelGGL((k_step_c<T, 1>), dim3(nc), dim3(256), 0, st, d, jc, p0, jj, cend, (int)na);
+        else
+            hipLaunchKernelGGL((k_step_c<T, QR_CW>), dim3(nc), dim3(256), 0, st, d, jc, p0, jj, cend, (int)na);
+        nparts = (int)nc;
+        // algorithmic traffic of one step: one read of the columns it covers
+        prof_end(ec, st, PK_STEP_C, (double)sizeof(T) * (double)(m - jc) * (double)(ncol > 0 ? ncol : 0),
+                 8.0 * (double)(m - jc) * (double)(ncol > 0 ? ncol : 0));
+    }
+    return nparts;
+}
+
+// Host copy of the control block after a stream synchronisation.
+template <typename T>
+static hipError_t read_ctl(const QrcpDev<T>& d, hipStream_t st, int32_t* hctl)
+{
+    hipError_t e = hipMemcpyAsync(hctl, d.ctl, sizeof(int32_t) * CTL_COUNT, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(st);
+    prof_flush();
+    return e;
+}
+
+// Select the window for a panel at p0, bring it to [p0, p0+W) and save that state.
+template <typename T>
+static void window_setup(UpdateWs<T>& w, hipStream_t st, int64_t p0, bool save)
+{
+    QrcpDev<T>& d = w.d;
+    const int W = w.win;
+    hipLaunchKernelGGL((k_window_select<T>), dim3(1), dim3(1024), 0, st, d, p0, W, w.wplan);
+    hipLaunchKernelGGL((k_window_swap<T>), dim3((unsigned)W), dim3(256), 0, st, d, (const int32_t*)w.wplan);
+    if (save) {
+        dim3 grid((unsigned)(rup(d.m, 256) < 64 ? rup(d.m, 256) : 64), (unsigned)W);
+        hipLaunchKernelGGL((k_copy_cols<T>), grid, dim3(256), 0, st, (const T*)(d.A + d.lda * p0), d.lda, w.wsave,
+                           d.lda, d.m);
+        hipLaunchKernelGGL((k_window_meta<T>), dim3((unsigned)rup(W, 256)), dim3(256), 0, st, d, p0, W, w.wsnu,
+                           w.wsnuref, w.wsperm, 0);
+    }
+}
+
+// One candidate-window panel at p0 (see window.hpp).  On return *jend is the
+// first column of the next panel and *nparts the argmax partials for its
+// first step (0 when there are none: the next panel then starts from nu).
+template <typename T>
+static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats, int64_t p0, int64_t* jend_out,
+                               int* nparts)
+{
+    QrcpDev<T>& d = w.d;
+    const int64_t m = d.m, n = d.n, k = d.k;
+    const int W = w.win;
+    const int64_t cend = p0 + W, nout = n - cend;
+    const int64_t nsteps = (p0 + w.nb < k ? p0 + w.nb : k) - p0;
+
+    hipEvent_t ew = prof_begin(st);
+    window_setup<T>(w, st, p0, true);
+    prof_end(ew, st, PK_WINDOW, (double)sizeof(T) * 4.0 * (double)m * W, 0.0);
+    hipLaunchKernelGGL(k_ctl_panel, dim3(1), dim3(64), 0, st, d.ctl, (int32_t)p0);
+    run_panel_steps<T>(d, st, p0, nsteps, cend, true, 1);
+    int32_t hctl[CTL_COUNT];
+    hipError_t e = read_ctl<T>(d, st, hctl);
+    if (e != hipSuccess) return e;
+    int64_t jend = hctl[CTL_JDONE];
+    if (jend <= p0 || jend > p0 + nsteps) return hipErrorUnknown;   // no progress: corrupt state
+    int nbe = (int)(jend - p0);
+    bool refresh = hctl[CTL_STOP] != 0;
+
+    // block reflector of the panel and the R rows of the outside columns
+    const T* V = d.A + p0 + d.lda * p0;
+    const int64_t rows = m - p0;
+    T* Ao = d.A + p0 + d.lda * cend;
+    hipEvent_t et = prof_begin(st);
+    if (!zgemm<T>(st, OP_C, true, OP_N, true, nbe, nbe, rows, C_ONE, V, d.lda, V, d.lda, C_ZERO, w.Gbuf, UNGQR_NB,
+                  w.gsplit, w.gsplit_bytes))
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_larft<T>), dim3(1), dim3(256), 0, st, w.Gbuf, d.tau + p0, nbe, w.Tbuf);
+    if (!zgemm<T>(st, OP_C, true, OP_N, false, nbe, nout, rows, C_ONE, V, d.lda, Ao, d.lda, C_ZERO, w.Wbuf,
+                  UNGQR_NB, w.gsplit, w.gsplit_bytes))
+        return hipErrorInvalidValue;
+    if (!zgemm<T>(st, OP_C, false, OP_N, false, nbe, nout, nbe, C_ONE, w.Tbuf, UNGQR_NB, w.Wbuf, UNGQR_NB, C_ZERO,
+                  w.W2buf, UNGQR_NB, nullptr, 0))
+        return hipErrorInvalidValue;
+    {
+        dim3 grid(1, (unsigned)nout);
+        hipLaunchKernelGGL((k_copy_cols<T>), grid, dim3(256), 0, st, (const T*)Ao, d.lda, w.Wbuf, (int64_t)UNGQR_NB,
+                           (int64_t)nbe);
+    }
+    if (!zgemm<T>(st, OP_N, true, OP_N, false, nbe, nout, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, C_ONE, w.Wbuf,
+                  UNGQR_NB, nullptr, 0))
+        return hipErrorInvalidValue;
+    const double ro = (double)rows * (double)nout;
+    prof_end(et, st, PK_TRAIL, (double)sizeof(T) * ro, 8.0 * nbe * ro);
+
+    // greedy replay of every step against the outside columns
+    hipEvent_t ek = prof_begin(st);
+    const unsigned nchk = (unsigned)rup(nout, 256);
+    hipLaunchKernelGGL((k_window_check<T>), dim3(nchk), dim3(256), 0, st, d, (const T*)w.Wbuf, (int64_t)UNGQR_NB,
+                       cend, nout, nbe, w.wpart);
+    hipLaunchKernelGGL(k_window_reduce, dim3(1), dim3(256), 0, st, (const int32_t*)w.wpart, (int)nchk, d.ctl);
+    prof_end(ek, st, PK_WINDOW, 8.0 * (double)nbe * nout, 0.0);
+    e = read_ctl<T>(d, st, hctl);
+    if (e != hipSuccess) return e;
+    int tstar = nbe;
+    if (hctl[CTL_TFAIL] < tstar) tstar = hctl[CTL_TFAIL];
+    if (hctl[CTL_TFLAG] < tstar) tstar = hctl[CTL_TFLAG];
+    if (tstar < 1) return hipErrorUnknown;   // the window always holds the first pivot
+    if (hctl[CTL_TFLAG] <= tstar) refresh = true;
+    if (tstar < nbe) {
+        // an outside column would have been chosen at step tstar (or the panel
+        // would have ended there): redo exactly tstar steps from the saved state
+        hipEvent_t er = prof_begin(st);
+        dim3 grid((unsigned)(rup(m, 256) < 64 ? rup(m, 256) : 64), (unsigned)W);
+        hipLaunchKernelGGL((k_copy_cols<T>), grid, dim3(256), 0, st, (const T*)w.wsave, d.lda, d.A + d.lda * p0,
+                           d.lda, m);
+        hipLaunchKernelGGL((k_window_meta<T>), dim3((unsigned)rup(W, 256)), dim3(256), 0, st, d, p0, W, w.wsnu,
+                           w.wsnuref, w.wsperm, 1);
+        window_setup<T>(w, st, p0, false);   // same window, no swaps left: restores the first partial
+        prof_end(er, st, PK_WINDOW, (double)sizeof(T) * 2.0 * (double)m * W, 0.0);
+        hipLaunchKernelGGL(k_ctl_panel, dim3(1), dim3(64), 0, st, d.ctl, (int32_t)p0);
+        run_panel_steps<T>(d, st, p0, tstar, cend, true, 1);
+        e = read_ctl<T>(d, st, hctl);
+        if (e != hipSuccess) return e;
+        if (hctl[CTL_JDONE] != p0 + tstar) return hipErrorUnknown;
+        nbe = tstar;
+        jend = p0 + tstar;
+        if (stats) stats->window_misses++;
+    }
+
+    // updates: the window's remaining columns from F, the outside columns from W2
+    hipEvent_t eu = prof_begin(st);
+    if (m > jend && cend > jend) {
+        if (!zgemm<T>(st, OP_N, false, OP_C, false, m - jend, cend - jend, nbe, C_MONE, d.A + jend + d.lda * p0,
+                      d.lda, d.F + jend, d.ldf, C_ONE, d.A + jend + d.lda * jend, d.lda, nullptr, 0))
+            return hipErrorInvalidValue;
+    }
+    if (!zgemm<T>(st, OP_N, true, OP_N, false, rows, nout, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, C_ONE, Ao,
+                  d.lda, nullptr, 0))
+        return hipErrorInvalidValue;
+    const double mn = (double)(m - jend) * (double)(cend - jend) + ro;
+    prof_end(eu, st, PK_TRAIL, 2.0 * sizeof(T) * mn, 8.0 * mn * nbe);
+    if (stats) stats->panels++;
+    if (refresh && jend < k) {
+        const unsigned nblk = (unsigned)rup(n - jend, QR_CW);
+        hipEvent_t en = prof_begin(st);
+        hipLaunchKernelGGL((k_colnorms<T>), dim3(nblk), dim3(256), 0, st, d, jend, jend, 1, 0);
+        prof_end(en, st, PK_NORMS, (double)sizeof(T) * (double)(m - jend) * (double)(n - jend), 0.0);
+        *nparts = (int)nblk;
+        if (stats) stats->refreshes++;
+    } else {
+        hipLaunchKernelGGL((k_window_commit<T>), dim3(nchk), dim3(256), 0, st, d, p0, cend, nout, nbe);
+        *nparts = 0;
+    }
+    *jend_out = jend;
+    return hipSuccess;
+}
+
 // nparts: argmax partials left by the kernel that set up the norms (ignored
 // without pivoting).
 template <typename T>
@@ -304,32 +501,28 @@ static hipError_t run_qrcp(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats, int
     if (!d.pivoting) return run_blocked_fixed<T>(w, st, stats);
     const int64_t m = d.m, n = d.n, k = d.k;
     const int nb = w.nb;
-    const unsigned na = (unsigned)rup(m, 256);
     int64_t j = 0;
     while (j < k) {
         const int64_t p0 = j;
         const int64_t pend = (p0 + nb < k) ? p0 + nb : k;
-        hipLaunchKernelGGL(k_ctl_panel, dim3(1), dim3(64), 0, st, d.ctl, (int32_t)p0);
-        for (int64_t jc = p0; jc < pend; ++jc) {
-            const int jj = (int)(jc - p0);
-            hipEvent_t ea = prof_begin(st);
-            launch_step_a<T>(d, na, jc, p0, jj, nparts, st);
-            prof_end(ea, st, PK_STEP_A, (double)sizeof(T) * (double)(m - jc) * (jj + 1), 8.0 * (m - jc) * jj);
-            int64_t ncol = n - jc - 1;
-            unsigned nc = (unsigned)(ncol > 0 ? rup(ncol, QR_CW) : 1);
-            hipEvent_t ec = prof_begin(st, PK_STEP_C);
-            hipLaunchKernelGGL((k_step_c<T>), dim3(nc), dim3(256), 0, st, d, jc, p0, jj, n, (int)na);
-            nparts = (int)nc;
-            // algorithmic traffic of one step: one read of the trailing block
-            prof_end(ec, st, PK_STEP_C, (double)sizeof(T) * (double)(m - jc) * (double)(ncol > 0 ? ncol : 0),
-                     8.0 * (double)(m - jc) * (double)(ncol > 0 ? ncol : 0));
+        if (w.win > 0 && n - p0 > w.win && n - p0 <= WIN_SORT_MAX) {
+            int64_t jend = p0;
+            hipError_t e = window_panel<T>(w, st, stats, p0, &jend, &nparts);
+            if (e != hipSuccess) return e;
+            j = jend;
+            continue;
         }
+        if (nparts == 0) {
+            // the previous panel left no partials: take them from the norms
+            const unsigned nb2 = (unsigned)rup(n - p0, 256);
+            hipLaunchKernelGGL((k_nu_argmax<T>), dim3(nb2), dim3(256), 0, st, d, p0);
+            nparts = (int)nb2;
+        }
+        hipLaunchKernelGGL(k_ctl_panel, dim3(1), dim3(64), 0, st, d.ctl, (int32_t)p0);
+        nparts = run_panel_steps<T>(d, st, p0, pend - p0, n, false, nparts);
         int32_t hctl[CTL_COUNT];
-        hipError_t e = hipMemcpyAsync(hctl, d.ctl, sizeof(hctl), hipMemcpyDeviceToHost, st);
+        hipError_t e = read_ctl<T>(d, st, hctl);
         if (e != hipSuccess) return e;
-        e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return e;
-        prof_flush();
         const int64_t jend = hctl[CTL_JDONE];
         if (jend <= p0 || jend > pend) return hipErrorUnknown;   // no progress: corrupt state
         const int64_t nbe = jend - p0;
@@ -344,7 +537,7 @@ static hipError_t run_qrcp(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats, int
             prof_end(et, st, PK_TRAIL, 2.0 * sizeof(T) * mn, 8.0 * mn * nbe);
         }
         if (stats) stats->panels++;
-        if (hctl[CTL_STOP] && jend < k && d.pivoting) {
+        if (hctl[CTL_STOP] && jend < k) {
             const unsigned nblk = (unsigned)rup(n - jend, QR_CW);
             hipEvent_t en = prof_begin(st);
             hipLaunchKernelGGL((k_colnorms<T>), dim3(nblk), dim3(256), 0, st, d, jend, jend, 1, 0);
@@ -389,7 +582,7 @@ static hipError_t form_q(UpdateWs<T>& w, T* Q, int64_t ldq, hipStream_t st)
         if (!zgemm<T>(st, OP_C, true, OP_N, true, nbe, nbe, rows, C_ONE, V, d.lda, V, d.lda, C_ZERO, w.Gbuf,
                       UNGQR_NB, w.gsplit, w.gsplit_bytes))
             return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_larft<T>), dim3(1), dim3(64), 0, st, w.Gbuf, d.tau + b0, nbe, w.Tbuf);
+        hipLaunchKernelGGL((k_larft<T>), dim3(1), dim3(256), 0, st, w.Gbuf, d.tau + b0, nbe, w.Tbuf);
         // W = V^H Q[b0:, b0:k]
         if (!zgemm<T>(st, OP_C, true, OP_N, false, nbe, cols, rows, C_ONE, V, d.lda, Q + b0 + ldq * b0, ldq,
                       C_ZERO, w.Wbuf, UNGQR_NB, w.gsplit, w.gsplit_bytes))

@@ -34,7 +34,8 @@ class MpsError(RuntimeError):
 class UpdateInfo(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int64), ("trunc_err_sq", ctypes.c_double), ("norm_sq", ctypes.c_double),
                 ("retained", ctypes.c_double), ("fallback", ctypes.c_int32), ("panels", ctypes.c_int32),
-                ("refreshes", ctypes.c_int32), ("pad", ctypes.c_int32), ("learned_err_sq", ctypes.c_double),
+                ("refreshes", ctypes.c_int32), ("window_misses", ctypes.c_int32),
+                ("learned_err_sq", ctypes.c_double),
                 ("qrcp_err_sq", ctypes.c_double)]
 
     def as_dict(self) -> dict:
@@ -99,6 +100,8 @@ def lib() -> ctypes.CDLL:
     L.pivnet_rank.argtypes = [p, i64, p, p]
     L.mps_set_pivot_network.restype = i32
     L.mps_set_pivot_network.argtypes = [p, ctypes.POINTER(LearnedCfg)]
+    L.mps_set_tuning.restype = i32
+    L.mps_set_tuning.argtypes = [i32, i32]
     L.mps_profile.restype = i32
     L.mps_profile.argtypes = [ctypes.c_int]
     L.mps_profile_read.restype = i32
@@ -192,6 +195,12 @@ def _ptr(t):
 
 
 # --- stateless calls -------------------------------------------------------------------
+
+def set_tuning(panel_width: int = 0, qr_window: int = -1):
+    """Process-wide pivoted-QR tuning (mps_set_tuning): panel width (0 = automatic)
+    and candidate-window width (-1 = automatic, 0 = off)."""
+    _check(lib().mps_set_tuning(panel_width, qr_window))
+
 
 def qrcp_work_bytes(m: int, n: int, k_max: int, prec: int) -> int:
     return int(lib().qrcp_work_bytes(m, n, k_max, prec))

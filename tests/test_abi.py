@@ -96,3 +96,13 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(mps, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         mps.lib()
+
+
+def test_tuning_validation(L):
+    from paper_2505_06119_amd import mps
+    for pw, win in ((12, -1), (32, 48), (32, -2), (0, 513), (128, 0)):
+        assert L.mps_set_tuning(pw, win) == 1, (pw, win)
+        assert "mps_set_tuning" in mps.last_error()
+    for pw, win in ((16, 64), (64, 512), (0, 0), (32, 256)):
+        assert L.mps_set_tuning(pw, win) == 0, (pw, win)
+    assert L.mps_set_tuning(0, -1) == 0

@@ -1,0 +1,94 @@
+"""Candidate-window panels of the pivoted QR against the FP64 oracle and
+against the same library with windows switched off.
+
+A window panel factorises inside the W columns of largest residual norm and
+keeps its steps only as far as a greedy replay against every other column
+confirms them (window.hpp), so the pivots must be those of the full search.
+Narrow windows force replays that cut panels short (window_misses > 0); the
+results must not change.  Tolerances as in test_gpu_qrcp."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2505_06119_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-10, 1: 1e-4}
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2505_06119_amd import mps
+    yield mps
+    mps.set_tuning(0, -1)
+
+
+def _host(t):
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def _qrcp(M, a, k, prec):
+    out = M.qrcp_truncate(M.colmajor(a, prec), k, prec)
+    return {"Q": _host(out["Q"]), "RPt": _host(out["RPt"]), "piv": out["piv"].cpu().numpy().astype(np.int64),
+            "diagR": out["diagR"].cpu().numpy(), "k": out["k"], "err": out["err"]}
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("pw,win", [(32, 256), (16, 64), (64, 128), (32, 64)])
+def test_window_pivots_exact_well_separated(M, prec, pw, win):
+    m, n, k = 1100, 900, 600
+    print(f"case window well_separated m={m} n={n} k={k} pw={pw} win={win} prec={prec}", flush=True)
+    a, p = synth.well_separated(synth.rng(21), m, n)
+    if prec == 1:
+        a = a.astype(np.complex64).astype(np.complex128)
+    M.set_tuning(pw, win)
+    g = _qrcp(M, a, k, prec)
+    M.set_tuning(0, -1)
+    assert list(g["piv"][:k]) == list(p[:k])
+    o = oracle.qrcp(a, k)
+    tol = TOL[prec]
+    scale = np.linalg.norm(a)
+    np.testing.assert_allclose(g["diagR"], o["diagR"], rtol=tol, atol=tol * scale)
+    assert abs(g["err"] - o["err"]) <= tol * 10 * scale
+    assert np.linalg.norm(g["Q"] @ g["RPt"] - o["Q"] @ oracle.r_unpivot(o["R"], o["piv"])) <= tol * 10 * scale
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("win", [64, 128, 0])
+def test_window_matches_full_search(M, prec, win):
+    # a truncated two-site problem: theta 512 x 512 from a chi = 256 canonical pair, k = 256
+    chi = 256
+    print(f"case window update chi={chi} win={win} prec={prec}", flush=True)
+    r = synth.rng(22)
+    a, b = synth.canonical_pair(r, chi, chi, chi, synth.exp_spectrum(chi, 150.0 * chi / 1024.0))
+    g = synth.haar_unitary(r, 4)
+    if prec == 1:
+        a = a.astype(np.complex64).astype(np.complex128)
+        b = b.astype(np.complex64).astype(np.complex128)
+    th = oracle.theta(a, b, g)
+    M.set_tuning(32, win)
+    gw = _qrcp(M, th, chi, prec)
+    out = M.mps_update_bond(M.site_to_device(a, prec), M.site_to_device(b, prec), g, chi, chi, chi, chi, prec,
+                            renormalize=False)
+    M.set_tuning(32, 0)
+    gf = _qrcp(M, th, chi, prec)
+    M.set_tuning(0, -1)
+    info = out["info"]
+    if win == 64:
+        assert info["window_misses"] > 0      # the replay did cut panels short
+    if win == 0:
+        assert info["window_misses"] == 0
+    o = oracle.qrcp(th, chi)
+    tol = TOL[prec]
+    scale = np.linalg.norm(th)
+    if prec == 0:
+        assert list(gw["piv"][:chi]) == list(o["piv"][:chi])
+        assert list(gf["piv"][:chi]) == list(o["piv"][:chi])
+    approx_o = o["Q"] @ oracle.r_unpivot(o["R"], o["piv"])
+    for res in (gw, gf):
+        assert np.linalg.norm(res["Q"] @ res["RPt"] - approx_o) <= tol * 10 * scale
+        assert abs(res["err"] - o["err"]) <= tol * 10 * scale
+    assert abs(info["trunc_err_sq"] - o["err"] ** 2) <= tol * 10 * scale ** 2
