@@ -131,11 +131,12 @@ __global__ __launch_bounds__(256) void k_step_a(QrcpDev<T> d, int64_t j, int64_t
     S vre[JMAX], vim[JMAX];
 #pragma unroll
     for (int t = 0; t < JMAX; ++t) {
+        // entries t >= jj and rows outside [j, m) are never used (the sums
+        // below test t < jj, and x = 0 off those rows)
         const int64_t col = p0 + (t < jj ? t : 0);   // p0 <= j: always a valid column
         const T v = arow[d.lda * col];
-        const bool keep = below && t < jj;
-        vre[t] = keep ? v.x : (S)0;
-        vim[t] = keep ? v.y : (S)0;
+        vre[t] = v.x;
+        vim[t] = v.y;
     }
     const T aj = arow[d.lda * j];
 
@@ -287,17 +288,23 @@ __device__ __forceinline__ void gemv_cols(const QrcpDev<T>& d, int64_t j, int64_
     if constexpr (sizeof(T) == 8) {
         // complex64: pairs of rows (r, r+1), r even, starting at the pair holding row j+1
         const int64_t r0 = (j + 1) & ~(int64_t)1;
+        // loads are unconditional, from clamped rows and columns: a row past m
+        // is masked by lo/hi below, and a column past cend only feeds an
+        // accumulator nobody reads.  (Conditional loads compile to a branch
+        // that waits for each load before the next one issues.)
+        const int64_t rlast = (m - 1) & ~(int64_t)1;   // last pair start; m odd: rows m-1, m < lda
         for (int64_t rb = r0 + 2 * tid; rb < m; rb += 512 * RU) {
             float4 xv[RU], av[RU][CW];
 #pragma unroll
             for (int q = 0; q < RU; ++q) {
                 const int64_t r = rb + 512 * q;
-                const bool ok = r < m;
-                xv[q] = ok ? *(const float4*)(d.xlo + r) : make_float4(0.f, 0.f, 0.f, 0.f);
+                const int64_t rc = r < m ? r : rlast;
+                xv[q] = *(const float4*)(d.xlo + rc);
 #pragma unroll
-                for (int u = 0; u < CW; ++u)
-                    av[q][u] = (ok && u < ncols) ? *(const float4*)(d.A + d.lda * (cbase + u) + r)
-                                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+                for (int u = 0; u < CW; ++u) {
+                    const int64_t cc = cbase + (u < ncols ? u : 0);
+                    av[q][u] = *(const float4*)(d.A + d.lda * cc + rc);
+                }
             }
 #pragma unroll
             for (int q = 0; q < RU; ++q) {
@@ -326,12 +333,24 @@ __device__ __forceinline__ void gemv_cols(const QrcpDev<T>& d, int64_t j, int64_
 #pragma unroll
             for (int q = 0; q < RU; ++q) {
                 const int64_t r = rb + 256 * q;
-                const bool ok = r < m;
-                xv[q] = ok ? to_d(d.xlo[r]) : czero();
+                const int64_t rc = r < m ? r : m - 1;
+                xv[q] = to_d(d.xlo[rc]);
 #pragma unroll
-                for (int u = 0; u < CW; ++u)
-                    av[q][u] = (ok && u < ncols) ? to_d(d.A[d.lda * (cbase + u) + r]) : czero();
+                for (int u = 0; u < CW; ++u) {
+                    const int64_t cc = cbase + (u < ncols ? u : 0);
+                    av[q][u] = to_d(d.A[d.lda * cc + rc]);
+                }
             }
+            // pin the loaded values here so that all loads issue before any is used
+#pragma unroll
+            for (int q = 0; q < RU; ++q) {
+                asm volatile("" : "+v"(xv[q].x), "+v"(xv[q].y));
+#pragma unroll
+                for (int u = 0; u < CW; ++u) asm volatile("" : "+v"(av[q][u].x), "+v"(av[q][u].y));
+            }
+#pragma unroll
+            for (int q = 0; q < RU; ++q)
+                if (rb + 256 * q >= m) xv[q] = czero();   // rows past m contribute nothing
 #pragma unroll
             for (int q = 0; q < RU; ++q) {
 #pragma unroll
@@ -398,26 +417,22 @@ void k_step_c(QrcpDev<T> d, int64_t j, int64_t p0, int jj, int64_t cend, int na)
     for (int u = 0; u < NPV; ++u) pv[u] = (grp < G && grp + u * G < na) ? pv[u] : 0.0;
     const double2 alpha_st = CW == 1 ? d.hh[0] : czero();
     // staged operands of the per-column work (at most one F entry per thread)
-    double2 f_st = czero();
+    // (unconditional loads from clamped in-range indices; a conditional load
+    // would wait for its data before the GEMV stream could be issued)
     const bool has_f = tid < CW * jj && cbase + tid % CW < cend;
-    if (has_f) {
-        const int u = tid % CW, t = tid / CW;
-        const int64_t c = cbase + u;
-        f_st = (d.pivoting && c == p && p != j) ? d.fsave[t] : to_d(d.F[c + d.ldf * t]);
+    double2 f_st;
+    {
+        const int t = has_f ? tid / CW : 0;
+        const int64_t c = has_f ? cbase + tid % CW : cbase;
+        const double2 fs = d.fsave[t];
+        const double2 fr = to_d(d.F[c + d.ldf * t]);
+        f_st = (d.pivoting && c == p && p != j) ? fs : fr;
     }
-    double2 arow_st = czero(), vj_st = czero();
-    double nu_st = 0.0, nuref_st = 0.0;
-    int32_t perm_st = 0;
-    if (tid < CW && cbase + tid < cend) {
-        const int64_t c = cbase + tid;
-        arow_st = to_d(d.A[j + d.lda * c]);
-        if (d.pivoting) {
-            nu_st = d.nu[c];
-            nuref_st = d.nuref[c];
-            perm_st = d.perm[c];
-        }
-    }
-    if (tid < jj) vj_st = to_d(d.A[j + d.lda * (p0 + tid)]);
+    const int64_t cst = cbase + (tid < CW && cbase + tid < cend ? tid : 0);
+    const double2 arow_st = to_d(d.A[j + d.lda * cst]);
+    const double nu_st = d.nu[cst], nuref_st = d.nuref[cst];
+    const int32_t perm_st = d.perm[cst];
+    const double2 vj_st = to_d(d.A[j + d.lda * (p0 + (tid < jj ? tid : 0))]);
     // this block's share of the reflector column (stored at the end): rows
     // [vr0, vr1); the one-column variant fetches its first 256 rows now
     const int64_t vlen = d.m - j - 1;
