@@ -281,7 +281,8 @@ def main():
     if sc["launches"] > 0 and sc["ms"] > 0:
         ach = sc["bytes"] / (sc["ms"] / 1e3) / 1e9
         traffic = measured_traffic() if head == "mixed" and chi == 4096 else None
-        res["roofline"] = {"bound": "hbm", "kernel": "k_step_c (trailing GEMV of one pivot step)",
+        res["roofline"] = {"bound": "hbm", "kernel": "k_step_c (one pivot step: GEMV over the candidate window, "
+                                                     "F column, pivot row, FP64 norm downdate)",
                            "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                            "traffic": traffic, "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + "
                                                                "WRITE_SIZE, copy-calibrated)",
