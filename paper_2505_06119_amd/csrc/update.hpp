@@ -190,6 +190,14 @@ struct UpdateWs {
     double* wsnuref;         // QR_WIN_MAX
     int32_t* wsperm;         // QR_WIN_MAX
     int32_t* wpart;          // 2 per 256 columns: greedy-replay partials
+    ArgBest* wcp;            // 2 * QR_WIN_MAX: argmax partials of the right-looking window steps (double buffer)
+    int32_t* wpiv;           // QR_NBMAX: pivot positions of those steps
+    int32_t* worder;         // QR_WIN_MAX: final column order of the window
+    T* wtmp;                 // like wsave: the window reordered at the panel end
+    T* vbuf;                 // QR_NBMAX columns of lda: beta and v of those steps
+    double* wtnu;            // QR_WIN_MAX
+    double* wtnuref;         // QR_WIN_MAX
+    int32_t* wtperm;         // QR_WIN_MAX
 };
 
 static inline int64_t rup(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -239,10 +247,19 @@ static bool carve_update_ws(Carver& cv, UpdateWs<T>& w, int64_t m, int64_t n, in
     w.wsnuref = (double*)cv.take(8 * QR_WIN_MAX);
     w.wsperm = (int32_t*)cv.take(4 * QR_WIN_MAX);
     w.wpart = (int32_t*)cv.take(8 * (rup(n, 256) + 1));
+    w.wcp = (ArgBest*)cv.take((int64_t)sizeof(ArgBest) * 2 * QR_WIN_MAX);
+    w.wpiv = (int32_t*)cv.take(4 * QR_NBMAX);
+    w.worder = (int32_t*)cv.take(4 * QR_WIN_MAX);
+    w.wtmp = (T*)cv.take((int64_t)sizeof(T) * d.lda * (wmax > 0 ? wmax : 1));
+    w.vbuf = (T*)cv.take((int64_t)sizeof(T) * d.lda * QR_NBMAX);
+    w.wtnu = (double*)cv.take(8 * QR_WIN_MAX);
+    w.wtnuref = (double*)cv.take(8 * QR_WIN_MAX);
+    w.wtperm = (int32_t*)cv.take(4 * QR_WIN_MAX);
     w.win = 0;
     return d.nu && d.nuref && d.perm && d.F && d.tau && d.diagR && d.xbuf && d.xlo && d.apart && d.hh && d.fsave &&
            d.cpart && d.npart && d.cflag && d.ctl && d.dsc && w.Gbuf && w.Tbuf && w.Wbuf && w.W2buf && w.gsplit &&
-           d.pivval && d.pivkey && w.wplan && w.wsave && w.wsnu && w.wsnuref && w.wsperm && w.wpart &&
+           d.pivval && d.pivkey && w.wplan && w.wsave && w.wsnu && w.wsnuref && w.wsperm && w.wpart && w.wcp &&
+           w.wpiv && w.worder && w.wtmp && w.vbuf && w.wtnu && w.wtnuref && w.wtperm &&
            (!theta_in_ws || d.A);
 }
 
@@ -366,7 +383,7 @@ static void window_setup(UpdateWs<T>& w, hipStream_t st, int64_t p0, bool save)
 {
     QrcpDev<T>& d = w.d;
     const int W = w.win;
-    hipLaunchKernelGGL((k_window_select<T>), dim3(1), dim3(1024), 0, st, d, p0, W, w.wplan);
+    hipLaunchKernelGGL((k_window_select<T>), dim3(1), dim3(1024), 0, st, d, p0, W, w.wplan, w.wcp);
     hipLaunchKernelGGL((k_window_swap<T>), dim3((unsigned)W), dim3(256), 0, st, d, (const int32_t*)w.wplan);
     if (save) {
         dim3 grid((unsigned)(rup(d.m, 256) < 64 ? rup(d.m, 256) : 64), (unsigned)W);
@@ -375,6 +392,40 @@ static void window_setup(UpdateWs<T>& w, hipStream_t st, int64_t p0, bool save)
         hipLaunchKernelGGL((k_window_meta<T>), dim3((unsigned)rup(W, 256)), dim3(256), 0, st, d, p0, W, w.wsnu,
                            w.wsnuref, w.wsperm, 0);
     }
+}
+
+// Right-looking pivot steps p0 .. p0+nsteps-1 inside the window (k_window_step),
+// then the window's columns in their final order: pivots first, in step order.
+template <typename T>
+static void run_window_steps(UpdateWs<T>& w, hipStream_t st, int64_t p0, int64_t nsteps)
+{
+    QrcpDev<T>& d = w.d;
+    const int W = w.win;
+    for (int64_t jj = 0; jj < nsteps; ++jj) {
+        const int64_t j = p0 + jj;
+        hipEvent_t ec = prof_begin(st, PK_STEP_C);
+        hipLaunchKernelGGL((k_window_step<T>), dim3((unsigned)W), dim3(1024), 0, st, d, j, p0, (int)jj,
+                           (const ArgBest*)(w.wcp + (jj & 1) * QR_WIN_MAX), w.wcp + ((jj + 1) & 1) * QR_WIN_MAX,
+                           w.wpiv, w.vbuf);
+        // algorithmic traffic of one step: the window right of the pivot read and written once
+        const double cols = (double)(p0 + W - j - 1), rows = (double)(d.m - j);
+        prof_end(ec, st, PK_STEP_C, 2.0 * sizeof(T) * rows * cols, 16.0 * rows * cols);
+    }
+}
+
+template <typename T>
+static void window_reorder(UpdateWs<T>& w, hipStream_t st, int64_t p0, int nbe)
+{
+    QrcpDev<T>& d = w.d;
+    const int W = w.win;
+    hipEvent_t ew = prof_begin(st);
+    hipLaunchKernelGGL(k_window_order, dim3(1), dim3(1024), 0, st, (const int32_t*)w.wpiv, nbe, p0, W, w.worder);
+    dim3 grid((unsigned)(rup(d.m, 256) < 64 ? rup(d.m, 256) : 64), (unsigned)W);
+    hipLaunchKernelGGL((k_window_gather<T>), grid, dim3(256), 0, st, d, (const int32_t*)w.worder, nbe, p0,
+                       (const T*)w.vbuf, w.wtmp, w.wtnu, w.wtnuref, w.wtperm, 0);
+    hipLaunchKernelGGL((k_window_gather<T>), grid, dim3(256), 0, st, d, (const int32_t*)w.worder, nbe, p0,
+                       (const T*)w.vbuf, w.wtmp, w.wtnu, w.wtnuref, w.wtperm, 1);
+    prof_end(ew, st, PK_WINDOW, (double)sizeof(T) * 4.0 * (double)d.m * W, 0.0);
 }
 
 // One candidate-window panel at p0 (see window.hpp).  On return *jend is the
@@ -389,12 +440,16 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
     const int W = w.win;
     const int64_t cend = p0 + W, nout = n - cend;
     const int64_t nsteps = (p0 + w.nb < k ? p0 + w.nb : k) - p0;
+    // right-looking steps keep the window current (one launch per step) while
+    // the rows fit one 1024-thread block; otherwise delayed-update steps
+    const bool right = m - p0 <= 1024 * WSTEP_RPT;
 
     hipEvent_t ew = prof_begin(st);
     window_setup<T>(w, st, p0, true);
     prof_end(ew, st, PK_WINDOW, (double)sizeof(T) * 4.0 * (double)m * W, 0.0);
     hipLaunchKernelGGL(k_ctl_panel, dim3(1), dim3(64), 0, st, d.ctl, (int32_t)p0);
-    run_panel_steps<T>(d, st, p0, nsteps, cend, true, 1);
+    if (right) run_window_steps<T>(w, st, p0, nsteps);
+    else run_panel_steps<T>(d, st, p0, nsteps, cend, true, 1);
     int32_t hctl[CTL_COUNT];
     hipError_t e = read_ctl<T>(d, st, hctl);
     if (e != hipSuccess) return e;
@@ -402,6 +457,7 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
     if (jend <= p0 || jend > p0 + nsteps) return hipErrorUnknown;   // no progress: corrupt state
     int nbe = (int)(jend - p0);
     bool refresh = hctl[CTL_STOP] != 0;
+    if (right) window_reorder<T>(w, st, p0, nbe);
 
     // block reflector of the panel and the R rows of the outside columns
     const T* V = d.A + p0 + d.lda * p0;
@@ -455,18 +511,21 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
         window_setup<T>(w, st, p0, false);   // same window, no swaps left: restores the first partial
         prof_end(er, st, PK_WINDOW, (double)sizeof(T) * 2.0 * (double)m * W, 0.0);
         hipLaunchKernelGGL(k_ctl_panel, dim3(1), dim3(64), 0, st, d.ctl, (int32_t)p0);
-        run_panel_steps<T>(d, st, p0, tstar, cend, true, 1);
+        if (right) run_window_steps<T>(w, st, p0, tstar);
+        else run_panel_steps<T>(d, st, p0, tstar, cend, true, 1);
         e = read_ctl<T>(d, st, hctl);
         if (e != hipSuccess) return e;
         if (hctl[CTL_JDONE] != p0 + tstar) return hipErrorUnknown;
+        if (right) window_reorder<T>(w, st, p0, tstar);
         nbe = tstar;
         jend = p0 + tstar;
         if (stats) stats->window_misses++;
     }
 
-    // updates: the window's remaining columns from F, the outside columns from W2
+    // updates: the window's remaining columns from F (right-looking steps have
+    // kept them current already), the outside columns from W2
     hipEvent_t eu = prof_begin(st);
-    if (m > jend && cend > jend) {
+    if (!right && m > jend && cend > jend) {
         if (!zgemm<T>(st, OP_N, false, OP_C, false, m - jend, cend - jend, nbe, C_MONE, d.A + jend + d.lda * p0,
                       d.lda, d.F + jend, d.ldf, C_ONE, d.A + jend + d.lda * jend, d.lda, nullptr, 0))
             return hipErrorInvalidValue;
@@ -474,7 +533,7 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
     if (!zgemm<T>(st, OP_N, true, OP_N, false, rows, nout, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, C_ONE, Ao,
                   d.lda, nullptr, 0))
         return hipErrorInvalidValue;
-    const double mn = (double)(m - jend) * (double)(cend - jend) + ro;
+    const double mn = (right ? 0.0 : (double)(m - jend) * (double)(cend - jend)) + ro;
     prof_end(eu, st, PK_TRAIL, 2.0 * sizeof(T) * mn, 8.0 * mn * nbe);
     if (stats) stats->panels++;
     if (refresh && jend < k) {

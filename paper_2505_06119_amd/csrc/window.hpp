@@ -65,7 +65,8 @@ __device__ __forceinline__ int block_scan_flags1024(bool flag, int* wsum, int* t
 // post-swap positions goes to cpart[0], cflag[0].
 // Requires W <= 1024, W < n - p0 <= WIN_SORT_MAX.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_window_select(QrcpDev<T> d, int64_t p0, int W, int32_t* plan)
+__global__ __launch_bounds__(1024) void k_window_select(QrcpDev<T> d, int64_t p0, int W, int32_t* plan,
+                                                        ArgBest* wcp)
 {
     __shared__ uint64_t s_b[WIN_SORT_MAX];   // norm bits
     __shared__ int32_t s_key[WIN_SORT_MAX];
@@ -198,12 +199,19 @@ __global__ __launch_bounds__(1024) void k_window_select(QrcpDev<T> d, int64_t p0
     }
     const ArgBest b0 = s_best[0];
     if (tid == 0) plan[0] = nv;
-    // first partial: the argmax, at its post-swap position
-    if (tid < W && qe == b0.slot) {
-        ArgBest b = b0;
-        b.slot = (int32_t)(p0 + (vac ? s_d[iv] : qe));
-        d.cpart[0] = b;
-        d.cflag[0] = 0;
+    // first partial: the argmax, at its post-swap position; and one partial per
+    // window column (post-swap position p0 + b in wcp[b]) for the window steps
+    if (tid < W) {
+        const int64_t pos = p0 + (vac ? s_d[iv] : qe);
+        ArgBest b;
+        b.val = __longlong_as_double((long long)s_b[qe]);
+        b.key = s_key[qe];
+        b.slot = (int32_t)pos;
+        wcp[pos - p0] = b;
+        if (qe == b0.slot) {
+            d.cpart[0] = b;
+            d.cflag[0] = 0;
+        }
     }
 }
 
@@ -357,5 +365,223 @@ __global__ __launch_bounds__(256) void k_nu_argmax(QrcpDev<T> d, int64_t c0)
     if (threadIdx.x == 0) {
         d.cpart[blockIdx.x] = b;
         d.cflag[blockIdx.x] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Right-looking pivot step inside a window (one launch per step).  Block b
+// owns the window column at position p0 + b and keeps it current: every step
+// applies the new reflector to it (H^H a = a - conj(tau) v (v^H a)) and
+// recomputes its residual norm exactly, so no norm is downdated inside the
+// window.  Columns do not move during the panel: the pivots are recorded in
+// wpiv and put in place by k_window_order / k_window_gather at the panel end.
+//   cin[b] / cout[b]: the argmax partial of column p0 + b before / after this
+//   step (slot -1 once it is a pivot); the two buffers alternate between
+//   steps, so no block reads a partial another block of the same launch writes.
+// Every block reads all W partials, finds the pivot, loads the pivot column
+// (rows j..m, shared through L2) and forms the reflector with the same
+// arithmetic as every other block.  The pivot's block stores beta and v in
+// vbuf[:, jj] (column p itself is read by all blocks during the step and is
+// left as it is).  grid: W blocks of 1024 threads; requires
+// m - j <= 1024 * WSTEP_RPT.
+// ---------------------------------------------------------------------------
+#define WSTEP_RPT 8
+
+__device__ __forceinline__ ArgBest e0_dead()
+{
+    ArgBest z;
+    z.val = -1.0;
+    z.key = 0x7fffffff;
+    z.slot = -1;
+    return z;
+}
+
+__device__ __forceinline__ double block_sum1024(double v, double* lds)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < 16; ++w) s += lds[w];
+    return s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_window_step(QrcpDev<T> d, int64_t j, int64_t p0, int jj, const ArgBest* cin,
+                                                      ArgBest* cout, int32_t* wpiv, T* vbuf)
+{
+    __shared__ double s_red[16];
+    __shared__ ArgBest s_arg[16];
+    __shared__ double2 s_alpha;
+    __shared__ int s_dead;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int W = gridDim.x, b = blockIdx.x;
+    const int64_t c = p0 + b;
+    const int m = (int)d.m, j0 = (int)j;   // rows fit 32 bits here (m <= 1024 * WSTEP_RPT)
+    T* colc = d.A + d.lda * c;
+    const int32_t stop = d.ctl[CTL_STOP];
+
+    // independent loads first: all partials, this column's rows j.., its key
+    const ArgBest e = cin[tid < W ? tid : 0];
+    const int32_t key_c = d.perm[c];
+    const double nuref_c = d.nuref[c];
+    T a[WSTEP_RPT];
+#pragma unroll
+    for (int q = 0; q < WSTEP_RPT; ++q) {
+        const int i = j0 + tid + 1024 * q;
+        a[q] = colc[i < m ? i : m - 1];
+    }
+    ArgBest best;
+    best.val = -1.0;
+    best.key = 0x7fffffff;
+    best.slot = -1;
+    if (tid < W && e.slot >= 0) best = e;
+    if (tid == b) s_dead = e.slot < 0 ? 1 : 0;
+    best = wave_argmax(best);
+    if (lane == 0) s_arg[wid] = best;
+    __syncthreads();
+    ArgBest bb = s_arg[0];
+    for (int w = 1; w < 16; ++w)
+        if (arg_better(s_arg[w].val, s_arg[w].key, bb.val, bb.key)) bb = s_arg[w];
+    if (stop || bb.slot < 0) return;   // uniform over the block
+    if (s_dead) {
+        if (tid == 0) cout[b] = e0_dead();
+        return;
+    }
+    const int64_t p = bb.slot;
+
+    // the pivot column and its reflector (identical arithmetic in every block)
+    T x[WSTEP_RPT];   // kept in the storage type, converted at each use
+    const T* colp = d.A + d.lda * p;
+#pragma unroll
+    for (int q = 0; q < WSTEP_RPT; ++q) {
+        const int i = j0 + tid + 1024 * q;
+        x[q] = colp[i < m ? i : m - 1];
+    }
+    double rest = 0.0;
+#pragma unroll
+    for (int q = 0; q < WSTEP_RPT; ++q) {
+        const int i = j0 + tid + 1024 * q;
+        if (i > j0 && i < m) rest += cabs2(to_d(x[q]));
+    }
+    if (tid == 0) s_alpha = to_d(x[0]);
+    rest = block_sum1024(rest, s_red);   // its barriers also publish s_alpha
+    const double2 alpha = s_alpha;
+    double2 tau, scale;
+    double beta;
+    if (rest == 0.0 && alpha.y == 0.0) {
+        tau = czero();
+        scale = czero();
+        beta = alpha.x;
+    } else {
+        const double nrm = sqrt(cabs2(alpha) + rest);
+        beta = alpha.x >= 0.0 ? -nrm : nrm;
+        tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+        scale = cdiv(make_double2(1.0, 0.0), make_double2(alpha.x - beta, alpha.y));
+    }
+
+    if (c == p) {
+        // this column is the pivot: beta and v go to vbuf[j.., jj]
+#pragma unroll
+        for (int q = 0; q < WSTEP_RPT; ++q) {
+            const int i = j0 + tid + 1024 * q;
+            if (i == j0) vbuf[i + d.lda * jj] = from_d<T>(make_double2(beta, 0.0));
+            else if (i < m) vbuf[i + d.lda * jj] = from_d<T>(cmul(scale, to_d(x[q])));
+        }
+        if (tid == 0) {
+            d.tau[j] = tau;
+            d.diagR[j] = beta;
+            d.pivval[jj] = bb.val;
+            d.pivkey[jj] = bb.key;
+            d.ctl[CTL_JDONE] = (int32_t)(j + 1);
+            wpiv[jj] = (int32_t)c;
+            cout[b] = e0_dead();
+        }
+        return;
+    }
+
+    // w = v^H a with v = (1, scale * x_rest)
+    double2 wp = czero();
+#pragma unroll
+    for (int q = 0; q < WSTEP_RPT; ++q) {
+        const int i = j0 + tid + 1024 * q;
+        const double2 ai = to_d(a[q]);
+        if (i == j0) wp = cadd(wp, ai);
+        else if (i < m) wp = cadd(wp, cmulc(cmul(scale, to_d(x[q])), ai));
+    }
+    const double wre = block_sum1024(wp.x, s_red);
+    const double wim = block_sum1024(wp.y, s_red);
+    const double2 coef = cmul(cconj(tau), make_double2(wre, wim));
+    // a -= conj(tau) v (v^H a); exact residual norm of rows > j afterwards
+    double nn = 0.0;
+#pragma unroll
+    for (int q = 0; q < WSTEP_RPT; ++q) {
+        const int i = j0 + tid + 1024 * q;
+        if (i < m) {
+            const double2 vi = i == j0 ? make_double2(1.0, 0.0) : cmul(scale, to_d(x[q]));
+            const T an = from_d<T>(csub(to_d(a[q]), cmul(coef, vi)));
+            colc[i] = an;
+            if (i > j0) nn += cabs2(to_d(an));
+        }
+    }
+    nn = block_sum1024(nn, s_red);
+    if (tid == 0) {
+        d.nu[c] = nn;
+        (void)nuref_c;
+        ArgBest mine;
+        mine.val = nn;
+        mine.key = key_c;
+        mine.slot = (int32_t)c;
+        cout[b] = mine;
+    }
+}
+
+// Panel end of the right-looking window steps: the order of the window's
+// columns, pivots first (in step order), then the others by position.
+// One block of up to 1024 threads (W <= 1024).
+__global__ __launch_bounds__(1024) void k_window_order(const int32_t* wpiv, int nbe, int64_t p0, int W, int32_t* order)
+{
+    __shared__ int32_t s_ispiv[1024];
+    __shared__ int wsum[16];
+    const int tid = threadIdx.x;
+    if (tid < W) s_ispiv[tid] = 0;
+    __syncthreads();
+    if (tid < nbe) s_ispiv[wpiv[tid] - p0] = 1;
+    __syncthreads();
+    const bool rest = tid < W && !s_ispiv[tid];
+    int tot = 0;
+    const int r = block_scan_flags1024(rest, wsum, &tot);
+    if (tid < nbe) order[tid] = wpiv[tid];
+    if (rest) order[nbe + r] = (int32_t)(p0 + tid);
+}
+
+// dir 0: tmp[:, q] = the window column order[q] in its final form (for the
+// q-th pivot, q < nbe: rows above p0 + q from A, beta and v from vbuf[:, q];
+// otherwise all rows from A), and its scalars into snu/snuref/sperm.
+// dir 1: A[:, p0 + q] = tmp[:, q] and the scalars back.  grid: (row chunks, W).
+template <typename T>
+__global__ __launch_bounds__(256) void k_window_gather(QrcpDev<T> d, const int32_t* order, int nbe, int64_t p0,
+                                                       const T* vbuf, T* tmp, double* snu, double* snuref,
+                                                       int32_t* sperm, int dir)
+{
+    const int q = blockIdx.y;
+    const int64_t src = dir == 0 ? order[q] : 0;
+    const int64_t vrow = q < nbe ? p0 + q : d.m;   // first row taken from vbuf
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < d.m; i += (int64_t)gridDim.x * 256) {
+        if (dir == 0) tmp[i + d.lda * q] = i >= vrow ? vbuf[i + d.lda * q] : d.A[i + d.lda * src];
+        else d.A[i + d.lda * (p0 + q)] = tmp[i + d.lda * q];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (dir == 0) {
+            snu[q] = d.nu[src];
+            snuref[q] = d.nuref[src];
+            sperm[q] = d.perm[src];
+        } else {
+            d.nu[p0 + q] = snu[q];
+            d.nuref[p0 + q] = snuref[q];
+            d.perm[p0 + q] = sperm[q];
+        }
     }
 }
