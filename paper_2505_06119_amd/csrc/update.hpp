@@ -404,7 +404,7 @@ static void run_window_steps(UpdateWs<T>& w, hipStream_t st, int64_t p0, int64_t
     for (int64_t jj = 0; jj < nsteps; ++jj) {
         const int64_t j = p0 + jj;
         hipEvent_t ec = prof_begin(st, PK_STEP_C);
-        hipLaunchKernelGGL((k_window_step<T>), dim3((unsigned)W), dim3(1024), 0, st, d, j, p0, (int)jj,
+        hipLaunchKernelGGL((k_window_step<T>), dim3((unsigned)W), dim3(WSTEP_NT), 0, st, d, j, p0, (int)jj,
                            (const ArgBest*)(w.wcp + (jj & 1) * QR_WIN_MAX), w.wcp + ((jj + 1) & 1) * QR_WIN_MAX,
                            w.wpiv, w.vbuf);
         // algorithmic traffic of one step: the window right of the pivot read and written once
@@ -442,7 +442,7 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
     const int64_t nsteps = (p0 + w.nb < k ? p0 + w.nb : k) - p0;
     // right-looking steps keep the window current (one launch per step) while
     // the rows fit one 1024-thread block; otherwise delayed-update steps
-    const bool right = m - p0 <= 1024 * WSTEP_RPT;
+    const bool right = m - p0 <= WSTEP_NT * WSTEP_RPT;
 
     hipEvent_t ew = prof_begin(st);
     window_setup<T>(w, st, p0, true);

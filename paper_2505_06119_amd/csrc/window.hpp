@@ -382,10 +382,12 @@ __global__ __launch_bounds__(256) void k_nu_argmax(QrcpDev<T> d, int64_t c0)
 // (rows j..m, shared through L2) and forms the reflector with the same
 // arithmetic as every other block.  The pivot's block stores beta and v in
 // vbuf[:, jj] (column p itself is read by all blocks during the step and is
-// left as it is).  grid: W blocks of 1024 threads; requires
-// m - j <= 1024 * WSTEP_RPT.
+// left as it is).  grid: W blocks of WSTEP_NT threads; requires
+// m - j <= WSTEP_NT * WSTEP_RPT.
 // ---------------------------------------------------------------------------
-#define WSTEP_RPT 8
+#define WSTEP_NT 512    // threads per block (8 waves)
+#define WSTEP_RPT 16    // rows per thread
+#define WSTEP_NW (WSTEP_NT / 64)
 
 __device__ __forceinline__ ArgBest e0_dead()
 {
@@ -396,7 +398,7 @@ __device__ __forceinline__ ArgBest e0_dead()
     return z;
 }
 
-__device__ __forceinline__ double block_sum1024(double v, double* lds)
+__device__ __forceinline__ double block_sum_ws(double v, double* lds)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     v = wave_sum(v);
@@ -404,33 +406,59 @@ __device__ __forceinline__ double block_sum1024(double v, double* lds)
     if (lane == 0) lds[wid] = v;
     __syncthreads();
     double s = 0.0;
-    for (int w = 0; w < 16; ++w) s += lds[w];
+    for (int w = 0; w < WSTEP_NW; ++w) s += lds[w];
     return s;
 }
 
+// three block sums in one round
+__device__ __forceinline__ void block_sum_ws3(double& a, double& b, double& c, double* lds /* 3 * WSTEP_NW */)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    __syncthreads();
+    if (lane == 0) {
+        lds[wid] = a;
+        lds[WSTEP_NW + wid] = b;
+        lds[2 * WSTEP_NW + wid] = c;
+    }
+    __syncthreads();
+    double sa = 0.0, sb = 0.0, sc = 0.0;
+    for (int w = 0; w < WSTEP_NW; ++w) {
+        sa += lds[w];
+        sb += lds[WSTEP_NW + w];
+        sc += lds[2 * WSTEP_NW + w];
+    }
+    a = sa;
+    b = sb;
+    c = sc;
+}
+
 template <typename T>
-__global__ __launch_bounds__(1024) void k_window_step(QrcpDev<T> d, int64_t j, int64_t p0, int jj, const ArgBest* cin,
+__global__ __launch_bounds__(WSTEP_NT) void k_window_step(QrcpDev<T> d, int64_t j, int64_t p0, int jj, const ArgBest* cin,
                                                       ArgBest* cout, int32_t* wpiv, T* vbuf)
 {
-    __shared__ double s_red[16];
-    __shared__ ArgBest s_arg[16];
-    __shared__ double2 s_alpha;
+    __shared__ double s_red[3 * WSTEP_NW];
+    __shared__ ArgBest s_arg[WSTEP_NW];
+    __shared__ double2 s_alpha, s_aj;
     __shared__ int s_dead;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int W = gridDim.x, b = blockIdx.x;
     const int64_t c = p0 + b;
-    const int m = (int)d.m, j0 = (int)j;   // rows fit 32 bits here (m <= 1024 * WSTEP_RPT)
+    const int m = (int)d.m, j0 = (int)j;   // rows fit 32 bits here
     T* colc = d.A + d.lda * c;
     const int32_t stop = d.ctl[CTL_STOP];
 
     // independent loads first: all partials, this column's rows j.., its key
+    // (W <= QR_WIN_MAX <= WSTEP_NT: one partial per thread)
     const ArgBest e = cin[tid < W ? tid : 0];
     const int32_t key_c = d.perm[c];
     const double nuref_c = d.nuref[c];
     T a[WSTEP_RPT];
 #pragma unroll
     for (int q = 0; q < WSTEP_RPT; ++q) {
-        const int i = j0 + tid + 1024 * q;
+        const int i = j0 + tid + WSTEP_NT * q;
         a[q] = colc[i < m ? i : m - 1];
     }
     ArgBest best;
@@ -443,7 +471,7 @@ __global__ __launch_bounds__(1024) void k_window_step(QrcpDev<T> d, int64_t j, i
     if (lane == 0) s_arg[wid] = best;
     __syncthreads();
     ArgBest bb = s_arg[0];
-    for (int w = 1; w < 16; ++w)
+    for (int w = 1; w < WSTEP_NW; ++w)
         if (arg_better(s_arg[w].val, s_arg[w].key, bb.val, bb.key)) bb = s_arg[w];
     if (stop || bb.slot < 0) return;   // uniform over the block
     if (s_dead) {
@@ -457,17 +485,28 @@ __global__ __launch_bounds__(1024) void k_window_step(QrcpDev<T> d, int64_t j, i
     const T* colp = d.A + d.lda * p;
 #pragma unroll
     for (int q = 0; q < WSTEP_RPT; ++q) {
-        const int i = j0 + tid + 1024 * q;
+        const int i = j0 + tid + WSTEP_NT * q;
         x[q] = colp[i < m ? i : m - 1];
     }
-    double rest = 0.0;
+    // one reduction round for ||x_rest||^2 and g = sum_{i>j} conj(x_i) a_i;
+    // then v^H a = a_j + conj(scale) g with v = (1, scale * x_rest)
+    double rest = 0.0, gre = 0.0, gim = 0.0;
 #pragma unroll
     for (int q = 0; q < WSTEP_RPT; ++q) {
-        const int i = j0 + tid + 1024 * q;
-        if (i > j0 && i < m) rest += cabs2(to_d(x[q]));
+        const int i = j0 + tid + WSTEP_NT * q;
+        if (i > j0 && i < m) {
+            const double2 xi = to_d(x[q]);
+            rest += cabs2(xi);
+            const double2 t = cmulc(xi, to_d(a[q]));
+            gre += t.x;
+            gim += t.y;
+        }
     }
-    if (tid == 0) s_alpha = to_d(x[0]);
-    rest = block_sum1024(rest, s_red);   // its barriers also publish s_alpha
+    if (tid == 0) {
+        s_alpha = to_d(x[0]);
+        s_aj = to_d(a[0]);
+    }
+    block_sum_ws3(rest, gre, gim, s_red);   // its barriers also publish s_alpha, s_aj
     const double2 alpha = s_alpha;
     double2 tau, scale;
     double beta;
@@ -486,7 +525,7 @@ __global__ __launch_bounds__(1024) void k_window_step(QrcpDev<T> d, int64_t j, i
         // this column is the pivot: beta and v go to vbuf[j.., jj]
 #pragma unroll
         for (int q = 0; q < WSTEP_RPT; ++q) {
-            const int i = j0 + tid + 1024 * q;
+            const int i = j0 + tid + WSTEP_NT * q;
             if (i == j0) vbuf[i + d.lda * jj] = from_d<T>(make_double2(beta, 0.0));
             else if (i < m) vbuf[i + d.lda * jj] = from_d<T>(cmul(scale, to_d(x[q])));
         }
@@ -502,23 +541,14 @@ __global__ __launch_bounds__(1024) void k_window_step(QrcpDev<T> d, int64_t j, i
         return;
     }
 
-    // w = v^H a with v = (1, scale * x_rest)
-    double2 wp = czero();
-#pragma unroll
-    for (int q = 0; q < WSTEP_RPT; ++q) {
-        const int i = j0 + tid + 1024 * q;
-        const double2 ai = to_d(a[q]);
-        if (i == j0) wp = cadd(wp, ai);
-        else if (i < m) wp = cadd(wp, cmulc(cmul(scale, to_d(x[q])), ai));
-    }
-    const double wre = block_sum1024(wp.x, s_red);
-    const double wim = block_sum1024(wp.y, s_red);
-    const double2 coef = cmul(cconj(tau), make_double2(wre, wim));
+    // w = v^H a
+    const double2 wv = cadd(s_aj, cmul(cconj(scale), make_double2(gre, gim)));
+    const double2 coef = cmul(cconj(tau), wv);
     // a -= conj(tau) v (v^H a); exact residual norm of rows > j afterwards
     double nn = 0.0;
 #pragma unroll
     for (int q = 0; q < WSTEP_RPT; ++q) {
-        const int i = j0 + tid + 1024 * q;
+        const int i = j0 + tid + WSTEP_NT * q;
         if (i < m) {
             const double2 vi = i == j0 ? make_double2(1.0, 0.0) : cmul(scale, to_d(x[q]));
             const T an = from_d<T>(csub(to_d(a[q]), cmul(coef, vi)));
@@ -526,7 +556,7 @@ __global__ __launch_bounds__(1024) void k_window_step(QrcpDev<T> d, int64_t j, i
             if (i > j0) nn += cabs2(to_d(an));
         }
     }
-    nn = block_sum1024(nn, s_red);
+    nn = block_sum_ws(nn, s_red);
     if (tid == 0) {
         d.nu[c] = nn;
         (void)nuref_c;
