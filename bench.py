@@ -38,7 +38,7 @@ METRIC = "two-site gate updates/sec at χ=4096, mixed vs FP64 QRCP, at 1e-4 fide
 HBM_PEAK_GBS = 8000.0
 PROFILE_SAMPLE = 8   # timed region: events on one k_step_c launch in 8
 KCLASS = ["contract", "gate_norms", "step_a", "step_c", "trail_gemm", "norms", "ungqr", "split", "propose",
-          "window"]
+          "window", "panel"]
 
 
 def log(msg):

@@ -269,14 +269,15 @@ typedef enum {
     MPS_K_CONTRACT = 0, /* theta0 = A_i A_{i+1} (MFMA GEMM)                   */
     MPS_K_GATE = 1,     /* gate + FP64 column norms                           */
     MPS_K_STEP_A = 2,   /* pivot swap, pivot-column bring-up, reflector       */
-    MPS_K_STEP_C = 3,   /* trailing GEMV, F column, pivot row, norm downdate  */
-    MPS_K_TRAIL = 4,    /* panel-end trailing update A -= V F^H (MFMA)        */
+    MPS_K_STEP_C = 3,   /* pivot step: GEMV or window update, pivot row, norms*/
+    MPS_K_TRAIL = 4,    /* panel-end updates A -= V F^H, A -= V W2 (MFMA)     */
     MPS_K_NORMS = 5,    /* exact norm recomputation and ||R22||_F             */
     MPS_K_UNGQR = 6,    /* Q_k formation (MFMA)                               */
     MPS_K_SPLIT = 7,    /* R_k P^T scatter into the right site                */
     MPS_K_PROPOSE = 8,  /* learned proposal: sketch, features, scores, order  */
     MPS_K_WINDOW = 9,   /* candidate-window selection, swaps, greedy replay   */
-    MPS_K_COUNT = 10
+    MPS_K_PANEL = 10,   /* panel block reflector: V^H V, T, V^H A, T^H W      */
+    MPS_K_COUNT = 11
 } mps_kernel_class;
 
 typedef struct {

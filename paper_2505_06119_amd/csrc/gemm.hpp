@@ -221,12 +221,15 @@ __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) cv[j][e] = cpf[i][j][e];
         } else if (use_beta) {
+            // unconditional loads from clamped indices (a conditional load would
+            // wait for its data before the next one issues)
+            const int64_t rc = r < g.M ? r : g.M - 1;
 #pragma unroll
             for (int j = 0; j < WN; ++j)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int64_t c = col0 + wc + 16 * j + MfmaOps<T>::drow(lane, e);
-                    if (r < g.M && c < g.N) cv[j][e] = C[r + g.ldc * c];
+                    cv[j][e] = C[rc + g.ldc * (c < g.N ? c : g.N - 1)];
                 }
         }
 #pragma unroll
@@ -302,9 +305,10 @@ static void launch_gemm_t(GemmArgs g, hipStream_t st, void* scratch, int64_t scr
     const int64_t tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
     int nz = 1;
     if (g.K > 0 && tiles < 256 && g.K >= 512 && scratch) {
-        // enough K slices for ~2048 blocks: a short-M, long-K product streams
-        // its B operand and needs every CU busy with several blocks
-        int64_t want = 2048 / tiles;
+        // enough K slices for ~1024 blocks: a short-M, long-K product streams
+        // its B operand and needs every CU busy with several blocks, while each
+        // slice's partial product costs a write and a read of M x N
+        int64_t want = 1024 / tiles;
         int64_t maxz = g.K / 128;
         nz = (int)(want < maxz ? want : maxz);
         if (nz > 64) nz = 64;

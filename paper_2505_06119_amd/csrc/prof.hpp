@@ -14,13 +14,14 @@ enum {
     PK_GATE = 1,      // gate + FP64 column norms
     PK_STEP_A = 2,    // pivot swap, bring-up, reflector
     PK_STEP_C = 3,    // trailing GEMV, F column, pivot row, downdate
-    PK_TRAIL = 4,     // panel-end MFMA update A -= V F^H
+    PK_TRAIL = 4,     // panel-end MFMA updates A -= V F^H and A -= V W2
     PK_NORMS = 5,     // exact norm recomputation / ||R22||
     PK_UNGQR = 6,     // Q formation
     PK_SPLIT = 7,     // R P^T scatter
     PK_PROPOSE = 8,   // learned proposal: sketch, features, scores, order, gather
     PK_WINDOW = 9,    // candidate-window selection, swaps, saves and greedy replay
-    PK_COUNT = 10
+    PK_PANEL = 10,    // panel block reflector: V^H V, T, V^H A, T^H W and the R rows outside a window
+    PK_COUNT = 11
 };
 
 struct ProfAcc {

@@ -309,6 +309,7 @@ static hipError_t run_blocked_fixed(UpdateWs<T>& w, hipStream_t st, QrcpStats* s
         const T* V = d.A + p0 + d.lda * p0;
         const int64_t rows = m - p0, cols = n - pend;
         T* At = d.A + p0 + d.lda * pend;
+        const double rc = (double)rows * (double)cols;
         hipEvent_t et = prof_begin(st);
         if (!zgemm<T>(st, OP_C, true, OP_N, true, nbe, nbe, rows, C_ONE, V, d.lda, V, d.lda, C_ZERO, w.Gbuf,
                       UNGQR_NB, w.gsplit, w.gsplit_bytes))
@@ -320,11 +321,12 @@ static hipError_t run_blocked_fixed(UpdateWs<T>& w, hipStream_t st, QrcpStats* s
         if (!zgemm<T>(st, OP_C, false, OP_N, false, nbe, cols, nbe, C_ONE, w.Tbuf, UNGQR_NB, w.Wbuf, UNGQR_NB,
                       C_ZERO, w.W2buf, UNGQR_NB, nullptr, 0))
             return hipErrorInvalidValue;
+        prof_end(et, st, PK_PANEL, (double)sizeof(T) * rc, 8.0 * nbe * (rc + (double)nbe * cols));
+        hipEvent_t eu = prof_begin(st);
         if (!zgemm<T>(st, OP_N, true, OP_N, false, rows, cols, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, C_ONE,
                       At, d.lda, nullptr, 0))
             return hipErrorInvalidValue;
-        const double rc = (double)rows * (double)cols;
-        prof_end(et, st, PK_TRAIL, (double)sizeof(T) * 3.0 * rc, 8.0 * nbe * (2.0 * rc + (double)nbe * cols));
+        prof_end(eu, st, PK_TRAIL, 2.0 * (double)sizeof(T) * rc, 8.0 * nbe * rc);
     }
     // a10: ||R22||_F^2 over the final trailing block
     if (m > k && n > k) {
@@ -483,7 +485,7 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
                   UNGQR_NB, nullptr, 0))
         return hipErrorInvalidValue;
     const double ro = (double)rows * (double)nout;
-    prof_end(et, st, PK_TRAIL, (double)sizeof(T) * ro, 8.0 * nbe * ro);
+    prof_end(et, st, PK_PANEL, (double)sizeof(T) * ro, 8.0 * nbe * ro);
 
     // greedy replay of every step against the outside columns
     hipEvent_t ek = prof_begin(st);

@@ -118,19 +118,39 @@ __global__ __launch_bounds__(1024) void k_window_select(QrcpDev<T> d, int64_t p0
             if (q < L && (s_b[q] & mask) == prefix) atomicAdd(&s_hist[(s_b[q] >> shift) & 255], 1u);
         }
         __syncthreads();
-        if (tid == 0) {
-            int cum = 0, dig = 0;
-            for (int bb = 255; bb >= 0; --bb) {
-                const int h = (int)s_hist[bb];
-                if (cum + h >= need) {
-                    dig = bb;
-                    break;
-                }
-                cum += h;
+        if (tid < 64) {
+            // wave 0: lane l holds bins 255-4l .. 252-4l (descending); the bin
+            // where the count from the top reaches `need` is found with one
+            // exclusive scan over the lanes
+            const int lane = tid;
+            int h[4], own = 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                h[u] = (int)s_hist[255 - 4 * lane - u];
+                own += h[u];
             }
-            s_sel[0] = dig;
-            s_sel[1] = need - cum;                               // still needed from this bin
-            s_sel[2] = (int)s_hist[dig] == need - cum ? 1 : 0;   // the whole bin is taken
+            int incl = own;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int t = __shfl_up(incl, off, MPS_WAVE);
+                if (lane >= off) incl += t;
+            }
+            int cum = incl - own;   // count in bins above this lane's
+            const bool here = cum < need && incl >= need;
+            if (here) {
+                int dig = 0, before = cum;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (before + h[u] >= need) {
+                        dig = 255 - 4 * lane - u;
+                        break;
+                    }
+                    before += h[u];
+                }
+                s_sel[0] = dig;
+                s_sel[1] = need - before;                               // still needed from this bin
+                s_sel[2] = (int)s_hist[dig] == need - before ? 1 : 0;   // the whole bin is taken
+            }
         }
         __syncthreads();
         prefix |= (uint64_t)s_sel[0] << shift;
@@ -223,10 +243,25 @@ __global__ __launch_bounds__(256) void k_window_swap(QrcpDev<T> d, const int32_t
     const int q = blockIdx.x;
     if (q >= plan[0]) return;
     const int64_t a = plan[1 + 2 * q], b = plan[2 + 2 * q];
-    for (int64_t i = threadIdx.x; i < d.m; i += 256) {
-        const T x = d.A[i + d.lda * a], y = d.A[i + d.lda * b];
-        d.A[i + d.lda * a] = y;
-        d.A[i + d.lda * b] = x;
+    T* ca = d.A + d.lda * a;
+    T* cb = d.A + d.lda * b;
+    for (int64_t i0 = threadIdx.x; i0 < d.m; i0 += 256 * 8) {
+        T x[8], y[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t i = i0 + 256 * u;
+            const int64_t ic = i < d.m ? i : d.m - 1;
+            x[u] = ca[ic];
+            y[u] = cb[ic];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t i = i0 + 256 * u;
+            if (i < d.m) {
+                ca[i] = y[u];
+                cb[i] = x[u];
+            }
+        }
     }
     if (threadIdx.x == 0) {
         const double t0 = d.nu[a]; d.nu[a] = d.nu[b]; d.nu[b] = t0;
