@@ -125,13 +125,18 @@ __global__ __launch_bounds__(256) void k_copy_cols(const T* src, int64_t lds, T*
 
 // T factor of a block reflector (forward, columnwise): H_0..H_{nb-1} = I - V T V^H
 // with T[t,t] = tau_t and T[0:t, t] = -tau_t T[0:t, 0:t] (V^H V)[0:t, t].
-// One block of 256 threads (four per row of T); G = V^H V (nb x nb, ld
-// UNGQR_NB) from a GEMM.  Writes T[0:nb, 0:nb] (ld UNGQR_NB).
+// Computed by blocks of 16 columns: the diagonal blocks by that recurrence
+// (all four at once, 16 dependent steps), then block column J from the
+// blocks left of it as T[0:J, J] = -T[0:J, 0:J] (V^H V)[0:J, J] T[J, J]
+// (the product rule for two block reflectors).  One block of 256 threads;
+// G = V^H V (nb x nb, ld UNGQR_NB) from a GEMM.  Writes T[0:nb, 0:nb] (ld UNGQR_NB).
+#define LARFT_B 16
 template <typename T>
 __global__ __launch_bounds__(256) void k_larft(const T* G, const double2* tau, int nb, T* Tout)
 {
     __shared__ double2 Ts[UNGQR_NB][UNGQR_NB + 1];
     __shared__ double2 Gs[UNGQR_NB][UNGQR_NB + 1];
+    __shared__ double2 Xs[UNGQR_NB][LARFT_B + 1];
     const int tid = threadIdx.x;
     for (int q = tid; q < nb * nb; q += 256) {
         const int r = q % nb, c = q / nb;
@@ -139,20 +144,46 @@ __global__ __launch_bounds__(256) void k_larft(const T* G, const double2* tau, i
         Ts[r][c] = czero();
     }
     __syncthreads();
-    const int s = tid >> 2, part = tid & 3;
-    for (int t = 0; t < nb; ++t) {
-        double2 v = czero();
-        if (s < t)
-            for (int u = s + part; u < t; u += 4) v = cadd(v, cmul(Ts[s][u], Gs[u][t]));
-        // the four parts of row s sit in adjacent lanes of one wave
-        v.x += __shfl_xor(v.x, 1, MPS_WAVE);
-        v.y += __shfl_xor(v.y, 1, MPS_WAVE);
-        v.x += __shfl_xor(v.x, 2, MPS_WAVE);
-        v.y += __shfl_xor(v.y, 2, MPS_WAVE);
-        const double2 tt = tau[t];
-        if (part == 0 && s < t) Ts[s][t] = cscale(cmul(tt, v), -1.0);
-        if (part == 0 && s == t) Ts[s][t] = tt;
-        __syncthreads();   // column t is read from the next step on
+    // diagonal blocks: thread (blk, row s of the block); step tt fills column
+    // 16 blk + tt of every block at once
+    const int nblk = (nb + LARFT_B - 1) / LARFT_B;
+    {
+        const int blk = tid / LARFT_B, sl = tid % LARFT_B;   // 16 blocks x 16 rows of capacity
+        const int c0 = blk * LARFT_B;
+        for (int tt = 0; tt < LARFT_B; ++tt) {
+            const int t = c0 + tt, s = c0 + sl;
+            if (blk < nblk && t < nb) {
+                const double2 tau_t = tau[t];
+                if (sl < tt) {
+                    double2 v = czero();
+                    for (int u = s; u < t; ++u) v = cadd(v, cmul(Ts[s][u], Gs[u][t]));
+                    Ts[s][t] = cscale(cmul(tau_t, v), -1.0);
+                } else if (sl == tt) {
+                    Ts[s][t] = tau_t;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // block columns 1 .. nblk-1
+    for (int J = 1; J < nblk; ++J) {
+        const int c0 = J * LARFT_B, cw = nb - c0 < LARFT_B ? nb - c0 : LARFT_B;
+        // X = G[0:c0, J] T[J, J]
+        for (int q = tid; q < c0 * cw; q += 256) {
+            const int r = q % c0, cc = q / c0;
+            double2 x = czero();
+            for (int u = 0; u <= cc; ++u) x = cadd(x, cmul(Gs[r][c0 + u], Ts[c0 + u][c0 + cc]));
+            Xs[r][cc] = x;
+        }
+        __syncthreads();
+        // T[0:c0, J] = -T[0:c0, 0:c0] X   (T upper triangular)
+        for (int q = tid; q < c0 * cw; q += 256) {
+            const int r = q % c0, cc = q / c0;
+            double2 y = czero();
+            for (int u = r; u < c0; ++u) y = cadd(y, cmul(Ts[r][u], Xs[u][cc]));
+            Ts[r][c0 + cc] = cscale(y, -1.0);
+        }
+        __syncthreads();
     }
     for (int q = tid; q < nb * nb; q += 256) {
         const int r = q % nb, c = q / nb;
