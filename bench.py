@@ -17,8 +17,9 @@ Three paths run on the same inputs:
 The headline value is the fastest mixed path whose norm fidelity stays within
 1e-4 (relative) of the FP64 QRCP result; the overlap of the truncated states
 is reported beside it.
-The roofline of k_step_c comes from HIP events on the launch stream around one
-k_step_c launch in 8 of the timed steps (mps_profile(8)); the per-kernel table
+The roofline of the pivot-step kernel (k_window_step) comes from HIP events on
+the launch stream around one such launch in 8 of the timed steps
+(mps_profile(8)); the per-kernel table
 from one extra, fully event-timed update after them (mps_profile(1)).  The
 plain FP64 CPU oracle is timed on a bounded sample for cpu_baseline.
 
@@ -36,7 +37,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "two-site gate updates/sec at χ=4096, mixed vs FP64 QRCP, at 1e-4 fidelity"
 HBM_PEAK_GBS = 8000.0
-PROFILE_SAMPLE = 8   # timed region: events on one k_step_c launch in 8
+PROFILE_SAMPLE = 8   # timed region: events on one pivot-step launch in 8
 KCLASS = ["contract", "gate_norms", "step_a", "step_c", "trail_gemm", "norms", "ungqr", "split", "propose",
           "window", "panel"]
 
@@ -75,7 +76,7 @@ def time_path(M, L, torch, name, prec, a, b, g, chi, steps, warmup, learned=None
         t = time.time()
         one()
         log(f"[bench] {name} warmup {w + 1}/{warmup}: {time.time() - t:.3f} s")
-    # timed region: only one k_step_c launch in PROFILE_SAMPLE carries an
+    # timed region: only one pivot-step launch in PROFILE_SAMPLE carries an
     # event pair, so the live roofline costs the timed steps well under 1%
     L.mps_profile(PROFILE_SAMPLE)
     torch.cuda.synchronize()
@@ -137,10 +138,10 @@ def deviation(torch, res, ref, chi):
 
 
 def measured_traffic():
-    """HBM bytes per k_step_c launch from the committed rocprofv3 counter
+    """HBM bytes per pivot-step launch from the committed rocprofv3 counter
     summary, or None when the kernel sources changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_step_c_chi4096_mixed.md")
+    path = os.path.join(ROOT, "profiles", "k_window_step_chi4096_mixed.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -149,7 +150,7 @@ def measured_traffic():
             k, v = line.split(":", 1)
             fields[k] = v.strip()
     h = hashlib.sha256()
-    for f in ("common.hpp", "qrcp.hpp"):
+    for f in ("common.hpp", "qrcp.hpp", "window.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2505_06119_amd", "csrc", f), "rb").read())
     if fields.get("kernel_source_sha256_16") != h.hexdigest()[:16] or "traffic_bytes_per_launch" not in fields:
         return None
@@ -281,12 +282,13 @@ def main():
     if sc["launches"] > 0 and sc["ms"] > 0:
         ach = sc["bytes"] / (sc["ms"] / 1e3) / 1e9
         traffic = measured_traffic() if head == "mixed" and chi == 4096 else None
-        res["roofline"] = {"bound": "hbm", "kernel": "k_step_c (one pivot step: GEMV over the candidate window, "
-                                                     "F column, pivot row, FP64 norm downdate)",
+        res["roofline"] = {"bound": "hbm", "kernel": "k_window_step (one right-looking pivot step over the "
+                                                     "256-column candidate window: reflector, window update, "
+                                                     "exact FP64 norms)",
                            "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                            "traffic": traffic, "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + "
                                                                "WRITE_SIZE, copy-calibrated)",
-                           "timed_launches": sc["launches"], "sampling": f"1 in {PROFILE_SAMPLE} k_step_c "
+                           "timed_launches": sc["launches"], "sampling": f"1 in {PROFILE_SAMPLE} pivot-step "
                                                                              "launches of the timed steps",
                            "avg_us": 1000.0 * sc["ms"] / sc["launches"],
                            "alg_bytes_per_launch": sc["bytes"] / sc["launches"]}
