@@ -39,7 +39,7 @@ METRIC = "two-site gate updates/sec at χ=4096, mixed vs FP64 QRCP, at 1e-4 fide
 HBM_PEAK_GBS = 8000.0
 PROFILE_SAMPLE = 8   # timed region: events on one pivot-step launch in 8
 KCLASS = ["contract", "gate_norms", "step_a", "step_c", "trail_gemm", "norms", "ungqr", "split", "propose",
-          "window", "panel"]
+          "window", "panel", "reflector"]
 
 
 def log(msg):
@@ -292,10 +292,13 @@ def main():
                                                                              "launches of the timed steps",
                            "avg_us": 1000.0 * sc["ms"] / sc["launches"],
                            "alg_bytes_per_launch": sc["bytes"] / sc["launches"]}
-    tg = hr["prof"]["trail_gemm"]
-    if tg["ms"] > 0:
-        res["trailing_update_mfma"] = {"TFLOP/s": tg["flops"] / (tg["ms"] / 1e3) / 1e12, "peak": 157.3,
-                                       "frac": tg["flops"] / (tg["ms"] / 1e3) / 1e12 / 157.3}
+    # trailing-matrix update by block reflectors: W = V^H A (panel) and A -= V W2 (trail_gemm)
+    tg, tw = hr["prof"]["trail_gemm"], hr["prof"]["panel"]
+    if tg["ms"] + tw["ms"] > 0:
+        tf = (tg["flops"] + tw["flops"]) / ((tg["ms"] + tw["ms"]) / 1e3) / 1e12
+        pk = 157.3 if head != "fp64" else 78.6
+        res["trailing_update_mfma"] = {"TFLOP/s": tf, "peak": pk, "frac": tf / pk,
+                                       "gemms": "W = V^H A and A -= V W2 of every panel, event-timed"}
     for k, v in runs.items():
         last = v["infos"][-1]
         res[f"path_{k}"] = {"value": rates[k], "unit": "updates/s", "ms_per_step": 1000.0 * v["seconds"] / args.steps,

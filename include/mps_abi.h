@@ -276,8 +276,9 @@ typedef enum {
     MPS_K_SPLIT = 7,    /* R_k P^T scatter into the right site                */
     MPS_K_PROPOSE = 8,  /* learned proposal: sketch, features, scores, order  */
     MPS_K_WINDOW = 9,   /* candidate-window selection, swaps, greedy replay   */
-    MPS_K_PANEL = 10,   /* panel block reflector: V^H V, T, V^H A, T^H W      */
-    MPS_K_COUNT = 11
+    MPS_K_PANEL = 10,   /* W = V^H A over the trailing columns (MFMA)         */
+    MPS_K_REFL = 11,    /* V^H V, T, T^H W, R rows outside a window           */
+    MPS_K_COUNT = 12
 } mps_kernel_class;
 
 typedef struct {

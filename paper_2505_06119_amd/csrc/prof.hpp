@@ -20,8 +20,9 @@ enum {
     PK_SPLIT = 7,     // R P^T scatter
     PK_PROPOSE = 8,   // learned proposal: sketch, features, scores, order, gather
     PK_WINDOW = 9,    // candidate-window selection, swaps, saves and greedy replay
-    PK_PANEL = 10,    // panel block reflector: V^H V, T, V^H A, T^H W and the R rows outside a window
-    PK_COUNT = 11
+    PK_PANEL = 10,    // W = V^H A over the trailing columns (the first half of the block-reflector update)
+    PK_REFL = 11,     // block reflector bookkeeping: V^H V, T, T^H W, the R rows outside a window
+    PK_COUNT = 12
 };
 
 struct ProfAcc {

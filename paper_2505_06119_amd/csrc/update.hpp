@@ -341,18 +341,22 @@ static hipError_t run_blocked_fixed(UpdateWs<T>& w, hipStream_t st, QrcpStats* s
         const int64_t rows = m - p0, cols = n - pend;
         T* At = d.A + p0 + d.lda * pend;
         const double rc = (double)rows * (double)cols;
-        hipEvent_t et = prof_begin(st);
+        hipEvent_t eg = prof_begin(st);
         if (!zgemm<T>(st, OP_C, true, OP_N, true, nbe, nbe, rows, C_ONE, V, d.lda, V, d.lda, C_ZERO, w.Gbuf,
                       UNGQR_NB, w.gsplit, w.gsplit_bytes))
             return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_larft<T>), dim3(1), dim3(256), 0, st, w.Gbuf, d.tau + p0, nbe, w.Tbuf);
+        prof_end(eg, st, PK_REFL, (double)sizeof(T) * rows * nbe, 8.0 * (double)nbe * nbe * rows);
+        hipEvent_t et = prof_begin(st);
         if (!zgemm<T>(st, OP_C, true, OP_N, false, nbe, cols, rows, C_ONE, V, d.lda, At, d.lda, C_ZERO, w.Wbuf,
                       UNGQR_NB, w.gsplit, w.gsplit_bytes))
             return hipErrorInvalidValue;
+        prof_end(et, st, PK_PANEL, (double)sizeof(T) * rc, 8.0 * nbe * rc);
+        hipEvent_t e2 = prof_begin(st);
         if (!zgemm<T>(st, OP_C, false, OP_N, false, nbe, cols, nbe, C_ONE, w.Tbuf, UNGQR_NB, w.Wbuf, UNGQR_NB,
                       C_ZERO, w.W2buf, UNGQR_NB, nullptr, 0))
             return hipErrorInvalidValue;
-        prof_end(et, st, PK_PANEL, (double)sizeof(T) * rc, 8.0 * nbe * (rc + (double)nbe * cols));
+        prof_end(e2, st, PK_REFL, (double)sizeof(T) * 2.0 * nbe * cols, 8.0 * (double)nbe * nbe * cols);
         hipEvent_t eu = prof_begin(st);
         if (!zgemm<T>(st, OP_N, true, OP_N, false, rows, cols, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, C_ONE,
                       At, d.lda, nullptr, 0))
@@ -496,14 +500,19 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
     const T* V = d.A + p0 + d.lda * p0;
     const int64_t rows = m - p0;
     T* Ao = d.A + p0 + d.lda * cend;
-    hipEvent_t et = prof_begin(st);
+    const double ro = (double)rows * (double)nout;
+    hipEvent_t eg = prof_begin(st);
     if (!zgemm<T>(st, OP_C, true, OP_N, true, nbe, nbe, rows, C_ONE, V, d.lda, V, d.lda, C_ZERO, w.Gbuf, UNGQR_NB,
                   w.gsplit, w.gsplit_bytes))
         return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_larft<T>), dim3(1), dim3(256), 0, st, w.Gbuf, d.tau + p0, nbe, w.Tbuf);
+    prof_end(eg, st, PK_REFL, (double)sizeof(T) * rows * nbe, 8.0 * (double)nbe * nbe * rows);
+    hipEvent_t et = prof_begin(st);
     if (!zgemm<T>(st, OP_C, true, OP_N, false, nbe, nout, rows, C_ONE, V, d.lda, Ao, d.lda, C_ZERO, w.Wbuf,
                   UNGQR_NB, w.gsplit, w.gsplit_bytes))
         return hipErrorInvalidValue;
+    prof_end(et, st, PK_PANEL, (double)sizeof(T) * ro, 8.0 * nbe * ro);
+    hipEvent_t e2 = prof_begin(st);
     if (!zgemm<T>(st, OP_C, false, OP_N, false, nbe, nout, nbe, C_ONE, w.Tbuf, UNGQR_NB, w.Wbuf, UNGQR_NB, C_ZERO,
                   w.W2buf, UNGQR_NB, nullptr, 0))
         return hipErrorInvalidValue;
@@ -515,8 +524,7 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
     if (!zgemm<T>(st, OP_N, true, OP_N, false, nbe, nout, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, C_ONE, w.Wbuf,
                   UNGQR_NB, nullptr, 0))
         return hipErrorInvalidValue;
-    const double ro = (double)rows * (double)nout;
-    prof_end(et, st, PK_PANEL, (double)sizeof(T) * ro, 8.0 * nbe * ro);
+    prof_end(e2, st, PK_REFL, (double)sizeof(T) * 3.0 * nbe * nout, 16.0 * (double)nbe * nbe * nout);
 
     // greedy replay of every step against the outside columns
     hipEvent_t ek = prof_begin(st);
