@@ -92,3 +92,22 @@ def test_window_matches_full_search(M, prec, win):
         assert np.linalg.norm(res["Q"] @ res["RPt"] - approx_o) <= tol * 10 * scale
         assert abs(res["err"] - o["err"]) <= tol * 10 * scale
     assert abs(info["trunc_err_sq"] - o["err"] ** 2) <= tol * 10 * scale ** 2
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_window_tall_delayed_steps(M, prec):
+    # more than 8192 rows: the window panels run the delayed-update steps
+    m, n, k = 8400, 600, 300
+    print(f"case window tall m={m} n={n} k={k} prec={prec}", flush=True)
+    a, p = synth.well_separated(synth.rng(23), m, n)
+    if prec == 1:
+        a = a.astype(np.complex64).astype(np.complex128)
+    g = _qrcp(M, a, k, prec)
+    assert list(g["piv"][:k]) == list(p[:k])
+    o = oracle.qrcp(a, k)
+    tol = TOL[prec]
+    scale = np.linalg.norm(a)
+    np.testing.assert_allclose(g["diagR"], o["diagR"], rtol=tol, atol=tol * scale)
+    assert abs(g["err"] - o["err"]) <= tol * 10 * scale
+    approx_o = o["Q"] @ oracle.r_unpivot(o["R"], o["piv"])
+    assert np.linalg.norm(g["Q"] @ g["RPt"] - approx_o) <= tol * 10 * scale
