@@ -255,6 +255,25 @@ mps_status mps_get_site(mps_ctx* ctx, int32_t j, void* dst, int64_t dst_bytes);
 mps_status mps_set_tuning(int32_t panel_width, int32_t qr_window);
 
 /* ------------------------------------------------------------------------
+ * Small-bond chains, process-wide (not thread-safe; affects later calls).
+ * mps_apply_gate / mps_apply_layer run a gate sequence as the ordered chain
+ * of centre moves (unpivoted QR / LQ, Sec. III-C.1) and two-site updates
+ * (Sec. III-C.3) that sequential application defines.  Every maximal run of
+ * consecutive operations whose bond dimensions are all <= max_dim executes
+ * as ONE kernel launch: a single workgroup performs the run's moves and
+ * updates in order, in FP64 on workspace copies (contraction and gate,
+ * Householder QR with greedy column pivoting on exactly recomputed residual
+ * norms, truncation to k = min(chi_cap, 2 chi_l, 2 chi_r), Q, R P^T and the
+ * renormalisation), reading and writing the sites in the context's storage
+ * precision.  The remaining operations take the multi-kernel path in between.
+ * The bookkept results (bond dimensions, norm fidelity, update info) are those
+ * of the multi-kernel path; panels, refreshes and window_misses read 0 for a
+ * chained update.  Contexts with learned pivots never chain.
+ * max_dim: 0 (off) .. 64; the default is 64.  Other values: MPS_EINVAL.
+ * ------------------------------------------------------------------------ */
+mps_status mps_set_small_bond_limit(int32_t max_dim);
+
+/* ------------------------------------------------------------------------
  * Per-kernel timing.  mps_profile(mode) resets the counters and sets the
  * process-wide timing of the library's launches with HIP events recorded on
  * the caller's stream: mode 0 off; mode 1 every launch of every class; mode

@@ -10,7 +10,7 @@
 #include <vector>
 
 #include "../../include/mps_abi.h"
-#include "update.hpp"
+#include "chain.hpp"
 
 // ---------------------------------------------------------------------------
 // errors

@@ -70,6 +70,10 @@ struct mps_ctx {
     bool poisoned;
     bool has_net;          // pivot network set (learned mode)
     mps_learned_cfg lcfg;
+    ChainOp* chain_ops;    // device: operations of the small-bond chains of one call
+    double* chain_info;    // device: ||theta||^2, eps^2 per chained update
+    int64_t chain_cap;     // capacity of chain_ops (entries)
+    int64_t dmax;          // largest bond dimension the state can reach
 };
 
 static int64_t max_bond(int n, int b, int64_t chi)
@@ -84,8 +88,13 @@ static int64_t max_bond(int n, int b, int64_t chi)
 struct CtxLayout {
     std::vector<int64_t> off;   // site offsets
     std::vector<int64_t> cap;
-    int64_t dmax, ws_off, ws_bytes, tmp_off, rbuf_off, vec_off, total;
+    int64_t dmax, ws_off, ws_bytes, tmp_off, rbuf_off, vec_off, chain_off, chain_cap, total;
 };
+
+// Operations one call can chain: every gate of a layer needs its update and
+// at most n_sites centre moves in all (the centre crosses each bond at most
+// once per direction change, and a layer's bonds are increasing).
+static int64_t chain_capacity(int n_sites) { return 3 * (int64_t)n_sites + 8; }
 
 static bool ctx_layout(const mps_config* cfg, CtxLayout& L)
 {
@@ -118,6 +127,9 @@ static bool ctx_layout(const mps_config* cfg, CtxLayout& L)
     pos += (L.dmax * L.dmax * eb + 255) / 256 * 256;
     L.vec_off = pos;
     pos += 2 * ((L.dmax * 16 + 255) / 256 * 256);
+    L.chain_off = pos;
+    L.chain_cap = chain_capacity(n);
+    pos += (L.chain_cap * (int64_t)sizeof(ChainOp) + 255) / 256 * 256 + (16 * (int64_t)(n + 1) + 255) / 256 * 256;
     L.total = pos + 256;
     return true;
 }
@@ -177,6 +189,10 @@ extern "C" mps_status mps_create(const mps_config* cfg, void* dev_arena, int64_t
     c->rbuf = base + L.rbuf_off;
     c->vec0 = (double2*)(base + L.vec_off);
     c->vec1 = (double2*)(base + L.vec_off + (L.dmax * 16 + 255) / 256 * 256);
+    c->chain_ops = (ChainOp*)(base + L.chain_off);
+    c->chain_cap = L.chain_cap;
+    c->dmax = L.dmax;
+    c->chain_info = (double*)(base + L.chain_off + (L.chain_cap * (int64_t)sizeof(ChainOp) + 255) / 256 * 256);
     c->centre = 0;
     c->log_fid = 0.0;
     c->poisoned = false;
@@ -277,28 +293,190 @@ static mps_status ctx_move_left(mps_ctx* c)
     return MPS_OK;
 }
 
+// Largest bond dimension of an operation that runs in a small-bond chain
+// (mps_set_small_bond_limit; 0: every operation takes the multi-kernel path).
+static int g_chain_dim = CH_DIM_MAX;
+
+// Gates t = 0 .. ng-1 on bonds idx[t] with sequential semantics.  The centre
+// moves and updates are planned first; consecutive operations whose bond
+// dimensions are all <= the chain limit run as one k_chain launch, the others
+// on the multi-kernel path in between.  Norm fidelities are accumulated in
+// gate order after one read-back of the chained updates' norms.
 template <typename T>
-static mps_status ctx_apply_gate(mps_ctx* c, int i, const double* g, mps_update_info* info)
+static mps_status ctx_run_gates(mps_ctx* c, int64_t ng, const int32_t* idx, const double* g, mps_update_info* info)
 {
-    const int target = c->centre <= i ? i : i + 1;
-    while (c->centre < target) {
-        mps_status r = ctx_move_right<T>(c);
-        if (r != MPS_OK) return r;
+    struct Step {
+        int kind, s, t;
+        bool fused;
+    };
+    int lim = c->cfg.pivot == MPS_PIVOT_QRCP ? g_chain_dim : 0;
+    // every bond dimension during the call is <= c->dmax (the structural
+    // bound), and a chained operation's are <= lim: matrices of at most mat rows
+    const int64_t mat = 2 * (c->dmax < lim ? c->dmax : (int64_t)lim);
+    if (lim > 0 && chain_ws_bytes(mat) > c->ws_bytes) lim = 0;
+    const int64_t half = lim > 0 ? mat / 2 : 0;   // = min(dmax, lim)
+    auto small = [&](int64_t a, int64_t b, int64_t d) { return a <= half && b <= half && d <= half; };
+
+    // plan: the operations and the bond dimensions they produce
+    std::vector<int64_t> dims = c->dims;
+    int centre = c->centre;
+    std::vector<Step> steps;
+    std::vector<ChainOp> ops;
+    int nslots = 0;
+    for (int64_t t = 0; t < ng; ++t) {
+        const int i = idx[t];
+        const int target = centre <= i ? i : i + 1;
+        while (centre != target) {
+            ChainOp op = {};
+            const int s = centre;
+            if (centre < target) {
+                op.kind = CH_RIGHT;
+                op.dl = (int32_t)dims[s];
+                op.dr = (int32_t)dims[s + 1];
+                op.dx = (int32_t)dims[s + 2];
+                op.k = (int32_t)(2 * dims[s] < dims[s + 1] ? 2 * dims[s] : dims[s + 1]);
+                op.s0 = c->site[s];
+                op.s1 = c->site[s + 1];
+                dims[s + 1] = op.k;
+                ++centre;
+            } else {
+                op.kind = CH_LEFT;
+                op.dl = (int32_t)dims[s];
+                op.dr = (int32_t)dims[s + 1];
+                op.dx = (int32_t)dims[s - 1];
+                op.k = (int32_t)(2 * dims[s + 1] < dims[s] ? 2 * dims[s + 1] : dims[s]);
+                op.s0 = c->site[s];
+                op.s1 = c->site[s - 1];
+                dims[s] = op.k;
+                --centre;
+            }
+            const bool f = small(op.dl, op.dr, op.dx);
+            steps.push_back({op.kind, s, (int)t, f});
+            if (f) ops.push_back(op);
+        }
+        ChainOp op = {};
+        op.kind = CH_UPDATE;
+        op.dl = (int32_t)dims[i];
+        op.dm = (int32_t)dims[i + 1];
+        op.dr = (int32_t)dims[i + 2];
+        int64_t k = c->chi_max < 2 * dims[i] ? c->chi_max : 2 * dims[i];
+        k = k < 2 * dims[i + 2] ? k : 2 * dims[i + 2];
+        op.k = (int32_t)k;
+        op.s0 = c->site[i];
+        op.s1 = c->site[i + 1];
+        for (int q = 0; q < 16; ++q) op.g[q] = make_double2(g[32 * t + 2 * q], g[32 * t + 2 * q + 1]);
+        const bool f = small(op.dl, op.dm, op.dr);
+        if (f) op.slot = nslots++;
+        steps.push_back({CH_UPDATE, i, (int)t, f});
+        if (f) ops.push_back(op);
+        dims[i + 1] = k;
+        centre = i + 1;
     }
-    while (c->centre > target) {
-        mps_status r = ctx_move_left<T>(c);
+    if ((int64_t)ops.size() > c->chain_cap) return fail(MPS_EINVAL, "gates: too many chained operations");
+    if (!ops.empty())
+        HIPCHK(hipMemcpyAsync(c->chain_ops, ops.data(), sizeof(ChainOp) * ops.size(), hipMemcpyHostToDevice, c->st),
+               "chain upload");
+
+    // execute
+    Carver cv{c->ws, c->ws_bytes, 0};
+    ChainWs cw;
+    cw.M = (double2*)cv.take(16 * mat * mat);
+    cw.Q = (double2*)cv.take(16 * mat * mat);
+    cw.P = (double2*)cv.take(16 * mat * mat);
+    cw.tau = (double2*)cv.take(16 * mat);
+    cw.nu = (double*)cv.take(8 * mat);
+    cw.perm = (int32_t*)cv.take(4 * mat);
+    std::vector<double> retained(ng, 1.0);
+    std::vector<int> slot_of(ng, -1);
+    size_t next_op = 0;
+    for (size_t q = 0; q < steps.size();) {
+        const Step& st = steps[q];
+        if (st.fused) {
+            size_t e = q;
+            while (e < steps.size() && steps[e].fused) ++e;
+            const size_t nops = e - q;
+            hipLaunchKernelGGL((k_chain<T>), dim3(1), dim3(CH_NT), 0, c->st, (const ChainOp*)(c->chain_ops + next_op),
+                               (int)nops, cw, c->chain_info);
+            HIPCHK(hipGetLastError(), "chain launch");
+            for (size_t u = 0; u < nops; ++u) {
+                const ChainOp& op = ops[next_op + u];
+                const Step& su = steps[q + u];
+                if (op.kind == CH_RIGHT) {
+                    c->dims[su.s + 1] = op.k;
+                    c->centre = su.s + 1;
+                } else if (op.kind == CH_LEFT) {
+                    c->dims[su.s] = op.k;
+                    c->centre = su.s - 1;
+                } else {
+                    c->dims[su.s + 1] = op.k;
+                    c->centre = su.s + 1;
+                    slot_of[su.t] = op.slot;
+                }
+            }
+            next_op += nops;
+            q = e;
+            continue;
+        }
+        mps_status r = MPS_OK;
+        if (st.kind == CH_RIGHT) r = ctx_move_right<T>(c);
+        else if (st.kind == CH_LEFT) r = ctx_move_left<T>(c);
+        else {
+            mps_update_info loc;
+            const int i = st.s;
+            const mps_learned_cfg* lc = c->cfg.pivot == MPS_PIVOT_LEARNED ? &c->lcfg : nullptr;
+            r = update_core<T>(c->dims[i], c->dims[i + 1], c->dims[i + 2], c->chi_max, c->prec,
+                               (const T*)c->site[i], (const T*)c->site[i + 1], g + 32 * st.t, (T*)c->site[i],
+                               (T*)c->site[i + 1], 1, lc, &loc, c->ws, c->ws_bytes, c->st);
+            if (r == MPS_OK) {
+                c->dims[i + 1] = loc.k;
+                c->centre = i + 1;
+                retained[st.t] = loc.retained;
+                if (info) info[st.t] = loc;
+            }
+        }
         if (r != MPS_OK) return r;
+        ++q;
     }
-    mps_update_info loc;
-    const mps_learned_cfg* lc = c->cfg.pivot == MPS_PIVOT_LEARNED ? &c->lcfg : nullptr;
-    mps_status r = update_core<T>(c->dims[i], c->dims[i + 1], c->dims[i + 2], c->chi_max, c->prec,
-                                  (const T*)c->site[i], (const T*)c->site[i + 1], g, (T*)c->site[i],
-                                  (T*)c->site[i + 1], 1, lc, &loc, c->ws, c->ws_bytes, c->st);
-    if (r != MPS_OK) return r;
-    c->dims[i + 1] = loc.k;
-    c->centre = i + 1;
-    if (loc.retained > 0) c->log_fid += log(loc.retained);
-    if (info) *info = loc;
+    if (nslots > 0) {
+        std::vector<double> h(2 * (size_t)nslots);
+        HIPCHK(hipMemcpyAsync(h.data(), c->chain_info, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->st),
+               "chain read-back");
+        HIPCHK(hipStreamSynchronize(c->st), "chain sync");
+        bool finite = true;
+        for (int64_t t = 0; t < ng; ++t) {
+            const int sl = slot_of[t];
+            if (sl < 0) continue;
+            const double n2 = h[2 * sl], e2 = h[2 * sl + 1];
+            finite = finite && isfinite(n2) && isfinite(e2);
+            retained[t] = n2 > 0.0 ? 1.0 - e2 / n2 : 1.0;
+            if (info) {
+                mps_update_info& u = info[t];
+                u.k = c->dims[idx[t] + 1];
+                u.trunc_err_sq = e2;
+                u.norm_sq = n2;
+                u.retained = retained[t];
+                u.fallback = 0;
+                u.panels = 0;
+                u.refreshes = 0;
+                u.window_misses = 0;
+                u.learned_err_sq = -1.0;
+                u.qrcp_err_sq = e2;
+            }
+        }
+        if (!finite) return fail(MPS_ENUMERIC, "chained update: non-finite theta");
+    } else {
+        HIPCHK(hipStreamSynchronize(c->st), "gates sync");
+    }
+    for (int64_t t = 0; t < ng; ++t)
+        if (retained[t] > 0) c->log_fid += log(retained[t]);
+    return MPS_OK;
+}
+
+extern "C" mps_status mps_set_small_bond_limit(int32_t max_dim)
+{
+    if (max_dim < 0 || max_dim > CH_DIM_MAX)
+        return fail(MPS_EINVAL, "mps_set_small_bond_limit: %d outside 0..%d", (int)max_dim, CH_DIM_MAX);
+    g_chain_dim = max_dim;
     return MPS_OK;
 }
 
@@ -329,7 +507,9 @@ extern "C" mps_status mps_apply_gate(mps_ctx* ctx, int32_t i, const double* g, m
     if (!gate_finite(g)) return fail(MPS_ENUMERIC, "mps_apply_gate: non-finite gate entry");
     if (ctx->cfg.pivot == MPS_PIVOT_LEARNED && !ctx->has_net)
         return fail(MPS_EINVAL, "mps_apply_gate: learned pivots need mps_set_pivot_network first");
-    s = ctx->prec == MPS_FP64 ? ctx_apply_gate<double2>(ctx, i, g, info) : ctx_apply_gate<float2>(ctx, i, g, info);
+    const int32_t one = i;
+    s = ctx->prec == MPS_FP64 ? ctx_run_gates<double2>(ctx, 1, &one, g, info)
+                              : ctx_run_gates<float2>(ctx, 1, &one, g, info);
     if (s == MPS_EDEVICE) ctx->poisoned = true;
     return s;
 }
@@ -349,15 +529,10 @@ extern "C" mps_status mps_apply_layer(mps_ctx* ctx, int64_t n, const int32_t* id
             return fail(MPS_EINVAL, "mps_apply_layer: bonds must be disjoint and increasing");
         if (!gate_finite(g + 32 * t)) return fail(MPS_ENUMERIC, "mps_apply_layer: non-finite gate entry");
     }
-    for (int64_t t = 0; t < n; ++t) {
-        s = ctx->prec == MPS_FP64 ? ctx_apply_gate<double2>(ctx, idx[t], g + 32 * t, info ? info + t : nullptr)
-                                  : ctx_apply_gate<float2>(ctx, idx[t], g + 32 * t, info ? info + t : nullptr);
-        if (s != MPS_OK) {
-            if (s == MPS_EDEVICE) ctx->poisoned = true;
-            return s;
-        }
-    }
-    return MPS_OK;
+    if (n == 0) return MPS_OK;
+    s = ctx->prec == MPS_FP64 ? ctx_run_gates<double2>(ctx, n, idx, g, info) : ctx_run_gates<float2>(ctx, n, idx, g, info);
+    if (s == MPS_EDEVICE) ctx->poisoned = true;
+    return s;
 }
 
 template <typename T>

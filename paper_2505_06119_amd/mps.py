@@ -102,6 +102,8 @@ def lib() -> ctypes.CDLL:
     L.mps_set_pivot_network.argtypes = [p, ctypes.POINTER(LearnedCfg)]
     L.mps_set_tuning.restype = i32
     L.mps_set_tuning.argtypes = [i32, i32]
+    L.mps_set_small_bond_limit.restype = i32
+    L.mps_set_small_bond_limit.argtypes = [i32]
     L.mps_profile.restype = i32
     L.mps_profile.argtypes = [ctypes.c_int]
     L.mps_profile_read.restype = i32
@@ -200,6 +202,12 @@ def set_tuning(panel_width: int = 0, qr_window: int = -1):
     """Process-wide pivoted-QR tuning (mps_set_tuning): panel width (0 = automatic)
     and candidate-window width (-1 = automatic, 0 = off)."""
     _check(lib().mps_set_tuning(panel_width, qr_window))
+
+
+def set_small_bond_limit(max_dim: int = 64):
+    """Process-wide limit of the one-launch small-bond chains
+    (mps_set_small_bond_limit; 0 = off)."""
+    _check(lib().mps_set_small_bond_limit(max_dim))
 
 
 def qrcp_work_bytes(m: int, n: int, k_max: int, prec: int) -> int:

@@ -98,6 +98,15 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
         mps.lib()
 
 
+def test_small_bond_limit_validation(L):
+    from paper_2505_06119_amd import mps
+    for v in (-1, 65, 1 << 20):
+        assert L.mps_set_small_bond_limit(v) == 1, v
+        assert "mps_set_small_bond_limit" in mps.last_error()
+    for v in (0, 1, 16, 64):
+        assert L.mps_set_small_bond_limit(v) == 0, v
+
+
 def test_tuning_validation(L):
     from paper_2505_06119_amd import mps
     for pw, win in ((12, -1), (32, 48), (32, -2), (0, 513), (128, 0)):
