@@ -31,6 +31,7 @@ static mps_status fail(mps_status s, const char* fmt, ...)
 
 static mps_status hip_fail(hipError_t e, const char* where)
 {
+    if (e == hipErrorUnknown && g_qr_diag[0]) return fail(MPS_EDEVICE, "%s: %s", where, g_qr_diag);
     return fail(MPS_EDEVICE, "%s: %s", where, hipGetErrorString(e));
 }
 

@@ -606,6 +606,10 @@ void k_step_c(QrcpDev<T> d, int64_t j, int64_t p0, int jj, int64_t cend, int na)
             if (arg_better(s_best[u].val, s_best[u].key, b.val, b.key)) b = s_best[u];
         d.cpart[blockIdx.x] = b;
         d.cflag[blockIdx.x] = s_flag;
+        // the panel ends here and the norms are recomputed before the next
+        // one, also when this was the panel's last step (no step A follows
+        // in this panel to turn the flag into the stop)
+        if (s_flag) d.ctl[CTL_STOP] = 1;
     }
 }
 

@@ -20,6 +20,22 @@
 #include "prof.hpp"
 #include "qrcp.hpp"
 #include "window.hpp"
+#include <stdarg.h>
+#include <stdio.h>
+
+// What the last failed pivoted QR found inconsistent (hipErrorUnknown
+// returns of the drivers below); empty when none.  Thread-unsafe, like the
+// rest of the host sequencing.
+static char g_qr_diag[320];
+
+static void qr_diag(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+static void qr_diag(const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_qr_diag, sizeof(g_qr_diag), fmt, ap);
+    va_end(ap);
+}
 
 struct Gate4 {
     double2 g[16];   // row-major: g[4*(2a'+b') + (2a+b)]
@@ -491,7 +507,12 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
     hipError_t e = read_ctl<T>(d, st, hctl);
     if (e != hipSuccess) return e;
     int64_t jend = hctl[CTL_JDONE];
-    if (jend <= p0 || jend > p0 + nsteps) return hipErrorUnknown;   // no progress: corrupt state
+    if (jend <= p0 || jend > p0 + nsteps) {   // no progress: corrupt state
+        qr_diag("window panel p0=%lld: %lld steps done of %lld (right-looking %d, m=%lld n=%lld k=%lld)",
+                (long long)p0, (long long)(jend - p0), (long long)nsteps, (int)right, (long long)m, (long long)n,
+                (long long)k);
+        return hipErrorUnknown;
+    }
     int nbe = (int)(jend - p0);
     bool refresh = hctl[CTL_STOP] != 0;
     if (right) window_reorder<T>(w, st, p0, nbe);
@@ -538,7 +559,12 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
     int tstar = nbe;
     if (hctl[CTL_TFAIL] < tstar) tstar = hctl[CTL_TFAIL];
     if (hctl[CTL_TFLAG] < tstar) tstar = hctl[CTL_TFLAG];
-    if (tstar < 1) return hipErrorUnknown;   // the window always holds the first pivot
+    if (tstar < 1) {   // the window always holds the first pivot
+        qr_diag("window panel p0=%lld: replay accepts no step (nbe=%d, first fail %d, first flag %d; m=%lld n=%lld "
+                "k=%lld)", (long long)p0, nbe, (int)hctl[CTL_TFAIL], (int)hctl[CTL_TFLAG], (long long)m,
+                (long long)n, (long long)k);
+        return hipErrorUnknown;
+    }
     if (hctl[CTL_TFLAG] <= tstar) refresh = true;
     if (tstar < nbe) {
         // an outside column would have been chosen at step tstar (or the panel
@@ -556,7 +582,11 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
         else run_panel_steps<T>(d, st, p0, tstar, cend, true, 1);
         e = read_ctl<T>(d, st, hctl);
         if (e != hipSuccess) return e;
-        if (hctl[CTL_JDONE] != p0 + tstar) return hipErrorUnknown;
+        if (hctl[CTL_JDONE] != p0 + tstar) {
+            qr_diag("window panel p0=%lld: redo of %d steps ended at %d (m=%lld n=%lld k=%lld)", (long long)p0,
+                    tstar, (int)(hctl[CTL_JDONE] - p0), (long long)m, (long long)n, (long long)k);
+            return hipErrorUnknown;
+        }
         if (right) window_reorder<T>(w, st, p0, tstar);
         nbe = tstar;
         jend = p0 + tstar;
@@ -598,6 +628,7 @@ template <typename T>
 static hipError_t run_qrcp(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats, int nparts)
 {
     QrcpDev<T>& d = w.d;
+    g_qr_diag[0] = 0;
     if (!d.pivoting) return run_blocked_fixed<T>(w, st, stats);
     const int64_t m = d.m, n = d.n, k = d.k;
     const int nb = w.nb;
@@ -624,7 +655,11 @@ static hipError_t run_qrcp(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats, int
         hipError_t e = read_ctl<T>(d, st, hctl);
         if (e != hipSuccess) return e;
         const int64_t jend = hctl[CTL_JDONE];
-        if (jend <= p0 || jend > pend) return hipErrorUnknown;   // no progress: corrupt state
+        if (jend <= p0 || jend > pend) {   // no progress: corrupt state
+            qr_diag("panel p0=%lld: %lld steps done of %lld (m=%lld n=%lld k=%lld)", (long long)p0,
+                    (long long)(jend - p0), (long long)(pend - p0), (long long)m, (long long)n, (long long)k);
+            return hipErrorUnknown;
+        }
         const int64_t nbe = jend - p0;
         // trailing update A[jend:, jend:] -= V[jend:, p0:jend] F[jend:, 0:nbe]^H
         if (m > jend && n > jend) {

@@ -118,6 +118,32 @@ def test_rank_deficient(M, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("rank", [8, 15, 16, 17, 32])
+def test_rank_deficient_past_the_rank(M, prec, rank):
+    """k beyond the rank: once it is exhausted every residual norm is rounding
+    noise and falls under the recomputation threshold.  Ranks 16 and 32 put
+    that at the last step of a 16-step panel, which must still lead to a norm
+    recomputation before the next panel (regression)."""
+    print(f"case rank past k rank={rank} prec={prec}", flush=True)
+    r = synth.rng(30 + rank)
+    a = synth.cgauss(r, (48, rank)) @ synth.cgauss(r, (rank, 40))
+    if prec == 1:
+        a = a.astype(np.complex64).astype(np.complex128)
+    M.set_tuning(16, 0)
+    try:
+        g = _run_qrcp(M, a, 40, prec)
+    finally:
+        M.set_tuning(0, -1)
+    tol = TOL[prec]
+    q = g["Q"]
+    assert g["k"] == 40
+    np.testing.assert_allclose(q.conj().T @ q, np.eye(40), atol=tol * 10)
+    assert np.linalg.norm(a - q @ g["RPt"]) <= tol * 100 * np.linalg.norm(a)
+    assert abs(g["diagR"][rank - 1]) >= 1e-6 * abs(g["diagR"][0])
+    assert np.all(np.abs(g["diagR"][rank:]) <= tol * 100 * abs(g["diagR"][0]))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("chl,chm,chr_,cap,seed", [(8, 16, 8, 8, 11), (24, 40, 20, 32, 12), (64, 96, 64, 64, 13),
                                                    (33, 50, 30, 100, 14), (1, 2, 1, 4, 15)])
 def test_update_bond_matches_oracle(M, prec, chl, chm, chr_, cap, seed):
