@@ -181,6 +181,43 @@ def cpu_baseline(chi_sample, chi_target, seed):
                       f"took {dt:.2f} s; scaled by (chi_sample/chi)^3 = {scale:.3e} to chi={chi_target}"}
 
 
+def layer_chains(M, torch, synth):
+    """Circuit layers of small bonds: the same gate sequence with the one-launch
+    small-bond chains on (limit 64) and off (every centre move and update on
+    the multi-kernel path).  Median wall time over 3 runs after a warm-up run,
+    each from the product state."""
+    cases = [("12 qubits, brickwork depth 10, Haar 4x4 gates, chi cap 64 (exact)", 12, 10, 64),
+             ("20 qubits, brickwork depth 8, Haar 4x4 gates, chi cap 256 (bonds up to 256: "
+              "chained runs at the ends, multi-kernel updates in the middle)", 20, 8, 256)]
+    out = []
+    for desc, n, depth, chi in cases:
+        layers = synth.brickwork(synth.rng(100), n, depth)
+        gates = sum(len(layer) for layer in layers)
+        row = {"workload": desc, "gates": gates, "layers": len(layers)}
+        for prec, pname in ((M.MPS_MIXED, "mixed"), (M.MPS_FP64, "fp64")):
+            for lim in (64, 0):
+                M.set_small_bond_limit(lim)
+                times = []
+                for rep in range(4):
+                    st = M.MPS(n, chi, prec)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    st.apply_layers(layers)
+                    torch.cuda.synchronize()
+                    if rep > 0:
+                        times.append(time.perf_counter() - t0)
+                    st.close()
+                dt = sorted(times)[len(times) // 2]
+                key = f"{pname}_{'chained' if lim else 'multikernel'}"
+                row[key] = {"gates_per_s": gates / dt, "ms_per_layer": 1000.0 * dt / len(layers)}
+            row[f"{pname}_speedup"] = row[f"{pname}_chained"]["gates_per_s"] / row[f"{pname}_multikernel"]["gates_per_s"]
+        M.set_small_bond_limit(64)
+        log(f"[bench] layers: {desc}: chained {row['mixed_chained']['gates_per_s']:.0f} gates/s, "
+            f"multi-kernel {row['mixed_multikernel']['gates_per_s']:.0f} gates/s (mixed)")
+        out.append(row)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,6 +229,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-layers", action="store_true", help="skip the small-bond layer measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 512 MiB device copy (reference dispatch for HBM counters)")
     ap.add_argument("--save-inputs", default=None, help="generate the input pair, save it here and exit")
@@ -318,6 +356,9 @@ def main():
         res["speedup_vs_fp64_qrcp"] = rates[head] / rates["fp64"]
     del runs
     torch.cuda.empty_cache()
+    if not args.no_layers:
+        log("[bench] circuit layers with and without small-bond chains")
+        res["layer_chains"] = layer_chains(M, torch, synth)
     if not args.no_cpu_baseline:
         log(f"[bench] timing the CPU oracle on a chi={args.cpu_sample_chi} sample")
         res["cpu_baseline"] = cpu_baseline(args.cpu_sample_chi, chi, args.seed)
