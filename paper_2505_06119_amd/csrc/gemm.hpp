@@ -268,6 +268,178 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(GemmArgs g, int nz)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Rank-K update  C += alpha A B  for K <= KD (32 or 64): the trailing update
+// A_o -= V W2 of a QR panel and the Q update of the blocked Q formation.
+// Memory-bound (16 bytes of C traffic per KD complex MACs), so it is laid out
+// for streaming C rather than for operand reuse:
+//   * each wave keeps its 32 rows of A (the panel's V, read once, masked to
+//     the unit lower trapezoid when MA) in registers as MFMA fragments;
+//   * it walks its block's column range in chunks of 16 columns, loading the
+//     next chunk's C tile and B fragments before the current chunk's MFMAs,
+//     so that HBM traffic overlaps the matrix-core work;
+//   * the contraction index is split so that lane group q (lanes 16q..16q+15)
+//     covers k = q*KD/4 .. (q+1)*KD/4-1: B fragments are then KD/4 contiguous
+//     elements of one B column per lane (16-byte loads).
+// Entries k >= K of A and B are zeroed, so B may hold anything there.  beta
+// is 1.  Grid: (ceil(M / 128), column ranges of cps columns, cps a multiple
+// of 16); 256 threads (four waves stacked in rows).
+// ---------------------------------------------------------------------------
+template <typename T, int KD, bool MA>
+__global__ __launch_bounds__(256) void k_zrank(GemmArgs g, int64_t cps)
+{
+    typedef typename MfmaOps<T>::S S;
+    typedef typename MfmaOps<T>::Acc Acc;
+    constexpr int QK = KD / 4;                 // contraction indices per lane group
+    constexpr int NV = QK * (int)sizeof(T) / 16;   // 16-byte loads per B fragment
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int grp = lane >> 4, l16 = lane & 15;
+    const int64_t M = g.M, N = g.N, K = g.K;
+    const int64_t r0 = (int64_t)blockIdx.x * 128 + wid * 32;
+    const int64_t cbeg = (int64_t)blockIdx.y * cps;
+    const int64_t cend = cbeg + cps < N ? cbeg + cps : N;
+    if (r0 >= M || cbeg >= cend) return;
+    const T* A = (const T*)g.A;
+    const T* B = (const T*)g.B;
+    T* C = (T*)g.C;
+    const S alr = (S)g.alpha.x, ali = (S)g.alpha.y;
+
+    S are[2][QK], aim[2][QK];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int64_t r = r0 + 16 * i + l16;
+        const int64_t rc = r < M ? r : M - 1;
+#pragma unroll
+        for (int q = 0; q < QK; ++q) {
+            const int k = QK * grp + q;
+            const int kc = k < K ? k : 0;
+            T v = A[rc + g.lda * kc];
+            if (MA) {
+                if (r < k) { v.x = 0; v.y = 0; }
+                if (r == k) { v.x = 1; v.y = 0; }
+            }
+            if (k >= K) { v.x = 0; v.y = 0; }
+            are[i][q] = v.x;
+            aim[i][q] = v.y;
+        }
+    }
+    const int64_t ra = r0 + l16, rb = r0 + 16 + l16;
+    const int64_t rca = ra < M ? ra : M - 1, rcb = rb < M ? rb : M - 1;
+    T cv[2][2][4];
+    T bv[2][QK];
+    auto load = [&](int buf, int64_t c0) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t c = c0 + MfmaOps<T>::drow(lane, e);
+            const int64_t cc = c < N ? c : N - 1;
+            cv[buf][0][e] = C[rca + g.ldc * cc];
+            cv[buf][1][e] = C[rcb + g.ldc * cc];
+        }
+        const int64_t c = c0 + l16;
+        const int64_t cc = c < N ? c : N - 1;
+        const float4* bp = (const float4*)(B + QK * grp + g.ldb * cc);
+#pragma unroll
+        for (int h = 0; h < NV; ++h) {
+            const float4 t = bp[h];
+            if constexpr (sizeof(T) == 8) {
+                bv[buf][2 * h] = make_float2(t.x, t.y);
+                bv[buf][2 * h + 1] = make_float2(t.z, t.w);
+            } else {
+                bv[buf][h] = *(const T*)&t;
+            }
+        }
+    };
+    auto compute = [&](int buf, int64_t c0) {
+        S bre[QK], bim[QK], nbi[QK];
+#pragma unroll
+        for (int q = 0; q < QK; ++q) {
+            const bool live = QK * grp + q < K;
+            bre[q] = live ? (S)bv[buf][q].x : (S)0;
+            bim[q] = live ? (S)bv[buf][q].y : (S)0;
+            nbi[q] = -bim[q];
+        }
+        Acc pr[2], pi[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) { pr[i][e] = 0; pi[i][e] = 0; }
+#pragma unroll
+        for (int q = 0; q < QK; ++q)
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                pr[i] = MfmaOps<T>::mma(bre[q], are[i][q], pr[i]);
+                pr[i] = MfmaOps<T>::mma(nbi[q], aim[i][q], pr[i]);
+                pi[i] = MfmaOps<T>::mma(bim[q], are[i][q], pi[i]);
+                pi[i] = MfmaOps<T>::mma(bre[q], aim[i][q], pi[i]);
+            }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int64_t r = i ? rb : ra;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t c = c0 + MfmaOps<T>::drow(lane, e);
+                const S xr = pr[i][e], xi = pi[i][e];
+                T o = cv[buf][i][e];
+                o.x += alr * xr - ali * xi;
+                o.y += alr * xi + ali * xr;
+                if (r < M && c < cend) C[r + g.ldc * c] = o;
+            }
+        }
+    };
+    // two register buffers: chunk c+16 loads while chunk c computes
+    load(0, cbeg);
+    for (int64_t c0 = cbeg;;) {
+        const int64_t c1 = c0 + 16;
+        if (c1 < cend) load(1, c1);
+        compute(0, c0);
+        if (c1 >= cend) break;
+        const int64_t c2 = c1 + 16;
+        if (c2 < cend) load(0, c2);
+        compute(1, c1);
+        if (c2 >= cend) break;
+        c0 = c2;
+    }
+}
+
+// C (M x N) += alpha A B with A M x K (unit lower trapezoidal when mask_a),
+// B K x N (ldb >= 32 for K <= 32, >= 64 otherwise; 16-byte aligned columns),
+// K <= 64.  Complex64 only: the complex128 fragments would need the whole
+// register file (one wave per SIMD), where the LDS-tiled zgemm does better.
+// Returns false for what it does not take (the caller then uses zgemm with
+// beta = 1).
+template <typename T>
+static bool zrank_update(hipStream_t st, bool mask_a, int64_t M, int64_t N, int64_t K, double2 alpha, const T* A,
+                         int64_t lda, const T* B, int64_t ldb, T* C, int64_t ldc)
+{
+    if constexpr (sizeof(T) != 8) {
+        return false;
+    } else {
+    if (M <= 0 || N <= 0 || K <= 0) return true;
+    const int kd = K <= 32 ? 32 : 64;
+    if (K > 64 || ldb < kd || ((uintptr_t)B & 15) != 0 || (ldb * (int64_t)sizeof(T)) % 16 != 0) return false;
+    GemmArgs g;
+    g.M = M; g.N = N; g.K = K;
+    g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+    g.alpha = alpha; g.beta = make_double2(1.0, 0.0);
+    g.kchunk = K; g.part = nullptr;
+    // about 3000 blocks: enough waves in flight per CU to cover HBM latency
+    const int64_t rblk = (M + 127) / 128;
+    int64_t splits = (3072 + rblk - 1) / rblk;
+    int64_t cps = (N + splits - 1) / splits;
+    cps = (cps + 15) / 16 * 16;
+    splits = (N + cps - 1) / cps;
+    dim3 grid((unsigned)rblk, (unsigned)splits);
+    if (kd == 32) {
+        if (mask_a) hipLaunchKernelGGL((k_zrank<T, 32, true>), grid, dim3(256), 0, st, g, cps);
+        else hipLaunchKernelGGL((k_zrank<T, 32, false>), grid, dim3(256), 0, st, g, cps);
+    } else {
+        if (mask_a) hipLaunchKernelGGL((k_zrank<T, 64, true>), grid, dim3(256), 0, st, g, cps);
+        else hipLaunchKernelGGL((k_zrank<T, 64, false>), grid, dim3(256), 0, st, g, cps);
+    }
+    return true;
+    }
+}
+
 enum GemmOp { OP_N = 0, OP_C = 1 };
 
 // Bytes of split-K scratch the launcher may need for an M x N product.

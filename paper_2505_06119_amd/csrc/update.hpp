@@ -601,7 +601,8 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
                       d.lda, d.F + jend, d.ldf, C_ONE, d.A + jend + d.lda * jend, d.lda, nullptr, 0))
             return hipErrorInvalidValue;
     }
-    if (!zgemm<T>(st, OP_N, true, OP_N, false, rows, nout, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, C_ONE, Ao,
+    if (!zrank_update<T>(st, true, rows, nout, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, Ao, d.lda) &&
+        !zgemm<T>(st, OP_N, true, OP_N, false, rows, nout, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, C_ONE, Ao,
                   d.lda, nullptr, 0))
         return hipErrorInvalidValue;
     const double mn = (right ? 0.0 : (double)(m - jend) * (double)(cend - jend)) + ro;
@@ -727,7 +728,8 @@ static hipError_t form_q(UpdateWs<T>& w, T* Q, int64_t ldq, hipStream_t st)
                       C_ZERO, w.W2buf, UNGQR_NB, nullptr, 0))
             return hipErrorInvalidValue;
         // Q[b0:, b0:k] -= V W2
-        if (!zgemm<T>(st, OP_N, true, OP_N, false, rows, cols, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, C_ONE,
+        if (!zrank_update<T>(st, true, rows, cols, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, Q + b0 + ldq * b0, ldq) &&
+            !zgemm<T>(st, OP_N, true, OP_N, false, rows, cols, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, C_ONE,
                       Q + b0 + ldq * b0, ldq, nullptr, 0))
             return hipErrorInvalidValue;
         flops += 8.0 * nbe * ((double)rows * nbe + 2.0 * (double)rows * cols + (double)nbe * cols);
