@@ -239,6 +239,7 @@ struct UpdateWs {
     int32_t* wpart;          // 2 per 256 columns: greedy-replay partials
     ArgBest* wcp;            // 2 * QR_WIN_MAX: argmax partials of the right-looking window steps (double buffer)
     int32_t* wpiv;           // QR_NBMAX: pivot positions of those steps
+    int32_t* wstep;          // QR_WIN_MAX: step at which a window column became the pivot
     int32_t* worder;         // QR_WIN_MAX: final column order of the window
     T* wtmp;                 // like wsave: the window reordered at the panel end
     T* vbuf;                 // QR_NBMAX columns of lda: beta and v of those steps
@@ -296,6 +297,7 @@ static bool carve_update_ws(Carver& cv, UpdateWs<T>& w, int64_t m, int64_t n, in
     w.wpart = (int32_t*)cv.take(8 * (rup(n, 256) + 1));
     w.wcp = (ArgBest*)cv.take((int64_t)sizeof(ArgBest) * 2 * QR_WIN_MAX);
     w.wpiv = (int32_t*)cv.take(4 * QR_NBMAX);
+    w.wstep = (int32_t*)cv.take(4 * QR_WIN_MAX);
     w.worder = (int32_t*)cv.take(4 * QR_WIN_MAX);
     w.wtmp = (T*)cv.take((int64_t)sizeof(T) * d.lda * (wmax > 0 ? wmax : 1));
     w.vbuf = (T*)cv.take((int64_t)sizeof(T) * d.lda * QR_NBMAX);
@@ -306,7 +308,7 @@ static bool carve_update_ws(Carver& cv, UpdateWs<T>& w, int64_t m, int64_t n, in
     return d.nu && d.nuref && d.perm && d.F && d.tau && d.diagR && d.xbuf && d.xlo && d.apart && d.hh && d.fsave &&
            d.cpart && d.npart && d.cflag && d.ctl && d.dsc && w.Gbuf && w.Tbuf && w.Wbuf && w.W2buf && w.gsplit &&
            d.pivval && d.pivkey && w.wplan && w.wsave && w.wsnu && w.wsnuref && w.wsperm && w.wpart && w.wcp &&
-           w.wpiv && w.worder && w.wtmp && w.vbuf && w.wtnu && w.wtnuref && w.wtperm &&
+           w.wpiv && w.wstep && w.worder && w.wtmp && w.vbuf && w.wtnu && w.wtnuref && w.wtperm &&
            (!theta_in_ws || d.A);
 }
 
@@ -459,7 +461,7 @@ static void run_window_steps(UpdateWs<T>& w, hipStream_t st, int64_t p0, int64_t
         hipEvent_t ec = prof_begin(st, PK_STEP_C);
         hipLaunchKernelGGL((k_window_step<T>), dim3((unsigned)W), dim3(WSTEP_NT), 0, st, d, j, p0, (int)jj,
                            (const ArgBest*)(w.wcp + (jj & 1) * QR_WIN_MAX), w.wcp + ((jj + 1) & 1) * QR_WIN_MAX,
-                           w.wpiv, w.vbuf);
+                           w.wpiv, w.vbuf, w.wstep, w.Gbuf, (int)UNGQR_NB);
         // algorithmic traffic of one step: the window right of the pivot read and written once
         const double cols = (double)(p0 + W - j - 1), rows = (double)(d.m - j);
         prof_end(ec, st, PK_STEP_C, 2.0 * sizeof(T) * rows * cols, 16.0 * rows * cols);
@@ -523,11 +525,14 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
     T* Ao = d.A + p0 + d.lda * cend;
     const double ro = (double)rows * (double)nout;
     hipEvent_t eg = prof_begin(st);
-    if (!zgemm<T>(st, OP_C, true, OP_N, true, nbe, nbe, rows, C_ONE, V, d.lda, V, d.lda, C_ZERO, w.Gbuf, UNGQR_NB,
-                  w.gsplit, w.gsplit_bytes))
+    // G = V^H V: the right-looking steps have formed its upper triangle (the
+    // part the T recurrence reads); the delayed-update steps need the GEMM
+    if (!right && !zgemm<T>(st, OP_C, true, OP_N, true, nbe, nbe, rows, C_ONE, V, d.lda, V, d.lda, C_ZERO, w.Gbuf,
+                            UNGQR_NB, w.gsplit, w.gsplit_bytes))
         return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_larft<T>), dim3(1), dim3(256), 0, st, w.Gbuf, d.tau + p0, nbe, w.Tbuf);
-    prof_end(eg, st, PK_REFL, (double)sizeof(T) * rows * nbe, 8.0 * (double)nbe * nbe * rows);
+    prof_end(eg, st, PK_REFL, right ? 0.0 : (double)sizeof(T) * rows * nbe,
+             right ? 0.0 : 8.0 * (double)nbe * nbe * rows);
     hipEvent_t et = prof_begin(st);
     if (!zgemm<T>(st, OP_C, true, OP_N, false, nbe, nout, rows, C_ONE, V, d.lda, Ao, d.lda, C_ZERO, w.Wbuf,
                   UNGQR_NB, w.gsplit, w.gsplit_bytes))

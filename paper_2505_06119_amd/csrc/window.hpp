@@ -472,7 +472,7 @@ __device__ __forceinline__ void block_sum_ws3(double& a, double& b, double& c, d
 
 template <typename T>
 __global__ __launch_bounds__(WSTEP_NT) void k_window_step(QrcpDev<T> d, int64_t j, int64_t p0, int jj, const ArgBest* cin,
-                                                      ArgBest* cout, int32_t* wpiv, T* vbuf)
+                                                      ArgBest* cout, int32_t* wpiv, T* vbuf, int32_t* wstep, T* gbuf, int ldg)
 {
     __shared__ double s_red[3 * WSTEP_NW];
     __shared__ ArgBest s_arg[WSTEP_NW];
@@ -509,10 +509,11 @@ __global__ __launch_bounds__(WSTEP_NT) void k_window_step(QrcpDev<T> d, int64_t 
     for (int w = 1; w < WSTEP_NW; ++w)
         if (arg_better(s_arg[w].val, s_arg[w].key, bb.val, bb.key)) bb = s_arg[w];
     if (stop || bb.slot < 0) return;   // uniform over the block
-    if (s_dead) {
-        if (tid == 0) cout[b] = e0_dead();
-        return;
-    }
+    // a dead block is the pivot of an earlier step i of this panel: it forms
+    // the Gram entry G[i, jj] = v_i^H v_jj of the panel's reflectors instead
+    const int gi = s_dead ? wstep[b] : -1;
+    if (s_dead && tid == 0) cout[b] = e0_dead();
+    if (s_dead && (gi < 0 || gi >= jj)) return;
     const int64_t p = bb.slot;
 
     // the pivot column and its reflector (identical arithmetic in every block)
@@ -523,6 +524,16 @@ __global__ __launch_bounds__(WSTEP_NT) void k_window_step(QrcpDev<T> d, int64_t 
         const int i = j0 + tid + WSTEP_NT * q;
         x[q] = colp[i < m ? i : m - 1];
     }
+    if (gi >= 0) {
+        // dead block: v_i (rows j.. of vbuf column i) takes the place of the
+        // column, and g = sum_{r>j} conj(v_i[r]) x_r is formed below
+        const T* vi = vbuf + d.lda * gi;
+#pragma unroll
+        for (int q = 0; q < WSTEP_RPT; ++q) {
+            const int i = j0 + tid + WSTEP_NT * q;
+            a[q] = vi[i < m ? i : m - 1];
+        }
+    }
     // one reduction round for ||x_rest||^2 and g = sum_{i>j} conj(x_i) a_i;
     // then v^H a = a_j + conj(scale) g with v = (1, scale * x_rest)
     double rest = 0.0, gre = 0.0, gim = 0.0;
@@ -532,7 +543,8 @@ __global__ __launch_bounds__(WSTEP_NT) void k_window_step(QrcpDev<T> d, int64_t 
         if (i > j0 && i < m) {
             const double2 xi = to_d(x[q]);
             rest += cabs2(xi);
-            const double2 t = cmulc(xi, to_d(a[q]));
+            // live: conj(x) a; dead: conj(v_i) x
+            const double2 t = gi >= 0 ? cmulc(to_d(a[q]), xi) : cmulc(xi, to_d(a[q]));
             gre += t.x;
             gim += t.y;
         }
@@ -556,6 +568,12 @@ __global__ __launch_bounds__(WSTEP_NT) void k_window_step(QrcpDev<T> d, int64_t 
         scale = cdiv(make_double2(1.0, 0.0), make_double2(alpha.x - beta, alpha.y));
     }
 
+    if (gi >= 0) {
+        // G[i, jj] = conj(v_i[j]) * 1 + scale * sum_{r>j} conj(v_i[r]) x_r
+        if (tid == 0)
+            gbuf[gi + ldg * jj] = from_d<T>(cadd(cconj(s_aj), cmul(scale, make_double2(gre, gim))));
+        return;
+    }
     if (c == p) {
         // this column is the pivot: beta and v go to vbuf[j.., jj]
 #pragma unroll
@@ -571,6 +589,7 @@ __global__ __launch_bounds__(WSTEP_NT) void k_window_step(QrcpDev<T> d, int64_t 
             d.pivkey[jj] = bb.key;
             d.ctl[CTL_JDONE] = (int32_t)(j + 1);
             wpiv[jj] = (int32_t)c;
+            wstep[b] = jj;
             cout[b] = e0_dead();
         }
         return;
