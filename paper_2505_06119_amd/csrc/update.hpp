@@ -148,7 +148,7 @@ __global__ __launch_bounds__(256) void k_copy_cols(const T* src, int64_t lds, T*
 // G = V^H V (nb x nb, ld UNGQR_NB) from a GEMM.  Writes T[0:nb, 0:nb] (ld UNGQR_NB).
 #define LARFT_B 16
 template <typename T>
-__global__ __launch_bounds__(256) void k_larft(const T* G, const double2* tau, int nb, T* Tout)
+__device__ void larft_block(const T* G, const double2* tau, int nb, T* Tout)
 {
     __shared__ double2 Ts[UNGQR_NB][UNGQR_NB + 1];
     __shared__ double2 Gs[UNGQR_NB][UNGQR_NB + 1];
@@ -207,6 +207,23 @@ __global__ __launch_bounds__(256) void k_larft(const T* G, const double2* tau, i
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_larft(const T* G, const double2* tau, int nb, T* Tout)
+{
+    larft_block<T>(G, tau, nb, Tout);
+}
+
+// The T factors of every UNGQR_NB-column block of k reflectors at once (block b
+// of the launch: G and T at offset b * UNGQR_NB^2, reflectors b*UNGQR_NB ..).
+template <typename T>
+__global__ __launch_bounds__(256) void k_larft_all(const T* G, const double2* tau, int64_t k, T* Tout)
+{
+    const int64_t b0 = (int64_t)blockIdx.x * UNGQR_NB;
+    const int nb = (int)(k - b0 < UNGQR_NB ? k - b0 : UNGQR_NB);
+    const int64_t off = (int64_t)blockIdx.x * UNGQR_NB * UNGQR_NB;
+    larft_block<T>(G + off, tau + b0, nb, Tout + off);
+}
+
 // Scratch carved from a caller-provided workspace.
 struct Carver {
     char* base;
@@ -225,6 +242,8 @@ struct UpdateWs {
     QrcpDev<T> d;
     T* Gbuf;       // UNGQR_NB^2
     T* Tbuf;       // UNGQR_NB^2
+    T* Gall;       // Q formation: V^H V of every UNGQR_NB block (ceil(k / UNGQR_NB) x UNGQR_NB^2)
+    T* Tall;       // and their T factors
     T* Wbuf;       // UNGQR_NB x k
     T* W2buf;      // UNGQR_NB x k
     void* gsplit;  // split-K scratch
@@ -281,6 +300,9 @@ static bool carve_update_ws(Carver& cv, UpdateWs<T>& w, int64_t m, int64_t n, in
     d.dsc = (double*)cv.take(8 * DSC_COUNT);
     w.Gbuf = (T*)cv.take((int64_t)sizeof(T) * UNGQR_NB * UNGQR_NB);
     w.Tbuf = (T*)cv.take((int64_t)sizeof(T) * UNGQR_NB * UNGQR_NB);
+    const int64_t qblocks = (k + UNGQR_NB - 1) / UNGQR_NB > 0 ? (k + UNGQR_NB - 1) / UNGQR_NB : 1;
+    w.Gall = (T*)cv.take((int64_t)sizeof(T) * UNGQR_NB * UNGQR_NB * qblocks);
+    w.Tall = (T*)cv.take((int64_t)sizeof(T) * UNGQR_NB * UNGQR_NB * qblocks);
     // W / W2 hold nb x (columns right of a panel): up to n (blocked QR) or k (UNGQR)
     const int64_t wcols = (n > k ? n : k) + 1;
     w.Wbuf = (T*)cv.take((int64_t)sizeof(T) * UNGQR_NB * wcols);
@@ -306,7 +328,7 @@ static bool carve_update_ws(Carver& cv, UpdateWs<T>& w, int64_t m, int64_t n, in
     w.wtperm = (int32_t*)cv.take(4 * QR_WIN_MAX);
     w.win = 0;
     return d.nu && d.nuref && d.perm && d.F && d.tau && d.diagR && d.xbuf && d.xlo && d.apart && d.hh && d.fsave &&
-           d.cpart && d.npart && d.cflag && d.ctl && d.dsc && w.Gbuf && w.Tbuf && w.Wbuf && w.W2buf && w.gsplit &&
+           d.cpart && d.npart && d.cflag && d.ctl && d.dsc && w.Gbuf && w.Tbuf && w.Gall && w.Tall && w.Wbuf && w.W2buf && w.gsplit &&
            d.pivval && d.pivkey && w.wplan && w.wsave && w.wsnu && w.wsnuref && w.wsperm && w.wpart && w.wcp &&
            w.wpiv && w.wstep && w.worder && w.wtmp && w.vbuf && w.wtnu && w.wtnuref && w.wtperm &&
            (!theta_in_ws || d.A);
@@ -715,22 +737,29 @@ static hipError_t form_q(UpdateWs<T>& w, T* Q, int64_t ldq, hipStream_t st)
     const int64_t last = ((k - 1) / UNGQR_NB) * UNGQR_NB;
     hipEvent_t eq = prof_begin(st);
     double flops = 0.0, bytes = 0.0;
+    // every block's G = V^H V, then all T factors in one launch: none of them
+    // depends on Q, so they stay off the chain of dependent Q updates
+    for (int64_t b0 = 0; b0 <= last; b0 += UNGQR_NB) {
+        const int nbe = (int)((k - b0) < UNGQR_NB ? (k - b0) : UNGQR_NB);
+        const T* V = d.A + b0 + d.lda * b0;
+        if (!zgemm<T>(st, OP_C, true, OP_N, true, nbe, nbe, m - b0, C_ONE, V, d.lda, V, d.lda, C_ZERO,
+                      w.Gall + (b0 / UNGQR_NB) * UNGQR_NB * UNGQR_NB, UNGQR_NB, w.gsplit, w.gsplit_bytes))
+            return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL((k_larft_all<T>), dim3((unsigned)(last / UNGQR_NB + 1)), dim3(256), 0, st, (const T*)w.Gall,
+                       (const double2*)d.tau, k, w.Tall);
     for (int64_t b0 = last; b0 >= 0; b0 -= UNGQR_NB) {
         const int nbe = (int)((k - b0) < UNGQR_NB ? (k - b0) : UNGQR_NB);
         const T* V = d.A + b0 + d.lda * b0;
         const int64_t rows = m - b0, cols = k - b0;
-        // G = V^H V
-        if (!zgemm<T>(st, OP_C, true, OP_N, true, nbe, nbe, rows, C_ONE, V, d.lda, V, d.lda, C_ZERO, w.Gbuf,
-                      UNGQR_NB, w.gsplit, w.gsplit_bytes))
-            return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_larft<T>), dim3(1), dim3(256), 0, st, w.Gbuf, d.tau + b0, nbe, w.Tbuf);
+        const T* Tb = w.Tall + (b0 / UNGQR_NB) * UNGQR_NB * UNGQR_NB;
         // W = V^H Q[b0:, b0:k]
         if (!zgemm<T>(st, OP_C, true, OP_N, false, nbe, cols, rows, C_ONE, V, d.lda, Q + b0 + ldq * b0, ldq,
                       C_ZERO, w.Wbuf, UNGQR_NB, w.gsplit, w.gsplit_bytes))
             return hipErrorInvalidValue;
         // W2 = T W
-        if (!zgemm<T>(st, OP_N, false, OP_N, false, nbe, cols, nbe, C_ONE, w.Tbuf, UNGQR_NB, w.Wbuf, UNGQR_NB,
-                      C_ZERO, w.W2buf, UNGQR_NB, nullptr, 0))
+        if (!zgemm<T>(st, OP_N, false, OP_N, false, nbe, cols, nbe, C_ONE, Tb, UNGQR_NB, w.Wbuf, UNGQR_NB, C_ZERO,
+                      w.W2buf, UNGQR_NB, nullptr, 0))
             return hipErrorInvalidValue;
         // Q[b0:, b0:k] -= V W2
         if (!zrank_update<T>(st, true, rows, cols, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, Q + b0 + ldq * b0, ldq) &&
