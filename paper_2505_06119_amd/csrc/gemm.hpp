@@ -74,7 +74,8 @@ __device__ __forceinline__ T load_masked(const T* base, int64_t ld, int64_t sr, 
 // BK: K depth of one LDS stage.  Long-K slices of small-tile products use 64
 // (complex64) or 32 (complex128), so that each stage streams more of the
 // operands per synchronisation.
-template <typename T, int WM, int WN, bool CA, bool CB, bool MA, bool MB, bool PF = false, int BK = GEMM_BK>
+template <typename T, int WM, int WN, bool CA, bool CB, bool MA, bool MB, bool PF = false, int BK = GEMM_BK,
+          bool G3 = false>
 __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g)
 {
     typedef typename MfmaOps<T>::S S;
@@ -116,13 +117,20 @@ __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g)
         }
     }
 
-    Acc acc_re[WM][WN], acc_im[WM][WN];
+    // G3: three real products per complex one, P1 = Br Ar, P2 = Bi Ai and
+    // P3 = (Br + Bi)(Ar + Ai) in acc_re, acc_im, acc_s (re = P1 - P2,
+    // im = P3 - P1 - P2); otherwise four, straight into re and im
+    Acc acc_re[WM][WN], acc_im[WM][WN], acc_s[G3 ? WM : 1][G3 ? WN : 1];
 #pragma unroll
     for (int i = 0; i < WM; ++i)
 #pragma unroll
         for (int j = 0; j < WN; ++j)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) { acc_re[i][j][e] = 0; acc_im[i][j][e] = 0; }
+            for (int e = 0; e < 4; ++e) {
+                acc_re[i][j][e] = 0;
+                acc_im[i][j][e] = 0;
+                if constexpr (G3) acc_s[i][j][e] = 0;
+            }
 
     // The next K tile is loaded into registers while the current one is
     // multiplied out of LDS.
@@ -196,15 +204,31 @@ __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g)
                 bi[j] = Bs_im[kk][wc + 16 * j + (lane & 15)];
                 nbi[j] = -bi[j];
             }
+            if constexpr (G3) {
+                S as[WM], bs[WN];
 #pragma unroll
-            for (int i = 0; i < WM; ++i)
+                for (int i = 0; i < WM; ++i) as[i] = ar[i] + ai[i];
 #pragma unroll
-                for (int j = 0; j < WN; ++j) {
-                    acc_re[i][j] = MfmaOps<T>::mma(br[j], ar[i], acc_re[i][j]);
-                    acc_re[i][j] = MfmaOps<T>::mma(nbi[j], ai[i], acc_re[i][j]);
-                    acc_im[i][j] = MfmaOps<T>::mma(bi[j], ar[i], acc_im[i][j]);
-                    acc_im[i][j] = MfmaOps<T>::mma(br[j], ai[i], acc_im[i][j]);
-                }
+                for (int j = 0; j < WN; ++j) bs[j] = br[j] + bi[j];
+#pragma unroll
+                for (int i = 0; i < WM; ++i)
+#pragma unroll
+                    for (int j = 0; j < WN; ++j) {
+                        acc_re[i][j] = MfmaOps<T>::mma(br[j], ar[i], acc_re[i][j]);
+                        acc_im[i][j] = MfmaOps<T>::mma(bi[j], ai[i], acc_im[i][j]);
+                        acc_s[i][j] = MfmaOps<T>::mma(bs[j], as[i], acc_s[i][j]);
+                    }
+            } else {
+#pragma unroll
+                for (int i = 0; i < WM; ++i)
+#pragma unroll
+                    for (int j = 0; j < WN; ++j) {
+                        acc_re[i][j] = MfmaOps<T>::mma(br[j], ar[i], acc_re[i][j]);
+                        acc_re[i][j] = MfmaOps<T>::mma(nbi[j], ai[i], acc_re[i][j]);
+                        acc_im[i][j] = MfmaOps<T>::mma(bi[j], ar[i], acc_im[i][j]);
+                        acc_im[i][j] = MfmaOps<T>::mma(br[j], ai[i], acc_im[i][j]);
+                    }
+            }
         }
         __syncthreads();
     }
@@ -239,6 +263,10 @@ __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g)
                 const int64_t c = col0 + wc + 16 * j + MfmaOps<T>::drow(lane, e);
                 if (r >= g.M || c >= g.N) continue;
                 double2 v = make_double2((double)acc_re[i][j][e], (double)acc_im[i][j][e]);
+                if constexpr (G3) {
+                    const double p1 = acc_re[i][j][e], p2 = acc_im[i][j][e], p3 = acc_s[i][j][e];
+                    v = make_double2(p1 - p2, p3 - p1 - p2);
+                }
                 if (P) {
                     P[(int64_t)blockIdx.z * g.M * g.N + r + g.M * c] = from_d<T>(v);
                 } else {
@@ -449,12 +477,13 @@ static inline int64_t gemm_splitk_bytes(int64_t M, int64_t N, int64_t K, int64_t
     return 16 * M * N * elem;   // at most 16 slices
 }
 
-template <typename T, int WM, int WN, bool CA, bool CB, bool MA, bool MB, bool PF = false, int BK = GEMM_BK>
+template <typename T, int WM, int WN, bool CA, bool CB, bool MA, bool MB, bool PF = false, int BK = GEMM_BK,
+          bool G3 = false>
 static void launch_gemm_cfg(GemmArgs g, hipStream_t st, int nz)
 {
     constexpr int BM = 32 * WM, BN = 32 * WN;
     dim3 grid((unsigned)((g.M + BM - 1) / BM), (unsigned)((g.N + BN - 1) / BN), (unsigned)nz);
-    hipLaunchKernelGGL((k_zgemm<T, WM, WN, CA, CB, MA, MB, PF, BK>), grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL((k_zgemm<T, WM, WN, CA, CB, MA, MB, PF, BK, G3>), grid, dim3(256), 0, st, g);
 }
 
 // Tile shapes per storage type: complex64 uses 128 x 128 tiles for large
@@ -503,18 +532,18 @@ static void launch_gemm_t(GemmArgs g, hipStream_t st, void* scratch, int64_t scr
         g.kchunk = g.K;
     }
     const bool beta_nz = g.beta.x != 0.0 || g.beta.y != 0.0;
-    if (big)
-        launch_gemm_cfg<T, BWM, BWN, CA, CB, MA, MB>(g, st, nz);
+    if (big)   // complex128's big tile has no registers left for the third accumulator
+        launch_gemm_cfg<T, BWM, BWN, CA, CB, MA, MB, false, GEMM_BK, sizeof(T) == 8>(g, st, nz);
     else if (nz == 1 && beta_nz && g.K <= 64 && !thin)
         launch_gemm_cfg<T, 2, 2, CA, CB, MA, MB, true>(g, st, nz);
     else if (thin && deep)
-        launch_gemm_cfg<T, 1, 4, CA, CB, MA, MB, false, DBK>(g, st, nz);
+        launch_gemm_cfg<T, 1, 4, CA, CB, MA, MB, false, DBK, true>(g, st, nz);
     else if (thin)
-        launch_gemm_cfg<T, 1, 4, CA, CB, MA, MB>(g, st, nz);
+        launch_gemm_cfg<T, 1, 4, CA, CB, MA, MB, false, GEMM_BK, true>(g, st, nz);
     else if (deep)
-        launch_gemm_cfg<T, 2, 2, CA, CB, MA, MB, false, DBK>(g, st, nz);
+        launch_gemm_cfg<T, 2, 2, CA, CB, MA, MB, false, DBK, true>(g, st, nz);
     else
-        launch_gemm_cfg<T, 2, 2, CA, CB, MA, MB>(g, st, nz);
+        launch_gemm_cfg<T, 2, 2, CA, CB, MA, MB, false, GEMM_BK, true>(g, st, nz);
     if (g.part) {
         int64_t total = g.M * g.N;
         int64_t blocks = (total + 255) / 256;
