@@ -313,7 +313,7 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(GemmArgs g, int nz)
 // is 1.  Grid: (ceil(M / 128), column ranges of cps columns, cps a multiple
 // of 16); 256 threads (four waves stacked in rows).
 // ---------------------------------------------------------------------------
-template <typename T, int KD, bool MA>
+template <typename T, int KD, bool MA, bool G3 = false>
 __global__ __launch_bounds__(256) void k_zrank(GemmArgs g, int64_t cps)
 {
     typedef typename MfmaOps<T>::S S;
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(256) void k_zrank(GemmArgs g, int64_t cps)
     T* C = (T*)g.C;
     const S alr = (S)g.alpha.x, ali = (S)g.alpha.y;
 
-    S are[2][QK], aim[2][QK];
+    S are[2][QK], aim[2][QK], asu[G3 ? 2 : 1][G3 ? QK : 1];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const int64_t r = r0 + 16 * i + l16;
@@ -349,6 +349,7 @@ __global__ __launch_bounds__(256) void k_zrank(GemmArgs g, int64_t cps)
             if (k >= K) { v.x = 0; v.y = 0; }
             are[i][q] = v.x;
             aim[i][q] = v.y;
+            if constexpr (G3) asu[i][q] = v.x + v.y;
         }
     }
     const int64_t ra = r0 + l16, rb = r0 + 16 + l16;
@@ -386,19 +387,31 @@ __global__ __launch_bounds__(256) void k_zrank(GemmArgs g, int64_t cps)
             bim[q] = live ? (S)bv[buf][q].y : (S)0;
             nbi[q] = -bim[q];
         }
-        Acc pr[2], pi[2];
+        // G3: P1 = Br Ar, P2 = Bi Ai, P3 = (Br + Bi)(Ar + Ai) in pr, pi, ps;
+        // otherwise the real and imaginary parts directly in pr, pi
+        Acc pr[2], pi[2], ps[G3 ? 2 : 1];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) { pr[i][e] = 0; pi[i][e] = 0; }
+            for (int e = 0; e < 4; ++e) {
+                pr[i][e] = 0;
+                pi[i][e] = 0;
+                if constexpr (G3) ps[i][e] = 0;
+            }
 #pragma unroll
         for (int q = 0; q < QK; ++q)
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                pr[i] = MfmaOps<T>::mma(bre[q], are[i][q], pr[i]);
-                pr[i] = MfmaOps<T>::mma(nbi[q], aim[i][q], pr[i]);
-                pi[i] = MfmaOps<T>::mma(bim[q], are[i][q], pi[i]);
-                pi[i] = MfmaOps<T>::mma(bre[q], aim[i][q], pi[i]);
+                if constexpr (G3) {
+                    pr[i] = MfmaOps<T>::mma(bre[q], are[i][q], pr[i]);
+                    pi[i] = MfmaOps<T>::mma(bim[q], aim[i][q], pi[i]);
+                    ps[i] = MfmaOps<T>::mma(bre[q] + bim[q], asu[i][q], ps[i]);
+                } else {
+                    pr[i] = MfmaOps<T>::mma(bre[q], are[i][q], pr[i]);
+                    pr[i] = MfmaOps<T>::mma(nbi[q], aim[i][q], pr[i]);
+                    pi[i] = MfmaOps<T>::mma(bim[q], are[i][q], pi[i]);
+                    pi[i] = MfmaOps<T>::mma(bre[q], aim[i][q], pi[i]);
+                }
             }
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
@@ -406,7 +419,11 @@ __global__ __launch_bounds__(256) void k_zrank(GemmArgs g, int64_t cps)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int64_t c = c0 + MfmaOps<T>::drow(lane, e);
-                const S xr = pr[i][e], xi = pi[i][e];
+                S xr = pr[i][e], xi = pi[i][e];
+                if constexpr (G3) {
+                    xr = pr[i][e] - pi[i][e];
+                    xi = ps[i][e] - pr[i][e] - pi[i][e];
+                }
                 T o = cv[buf][i][e];
                 o.x += alr * xr - ali * xi;
                 o.y += alr * xi + ali * xr;
@@ -457,9 +474,9 @@ static bool zrank_update(hipStream_t st, bool mask_a, int64_t M, int64_t N, int6
     cps = (cps + 15) / 16 * 16;
     splits = (N + cps - 1) / cps;
     dim3 grid((unsigned)rblk, (unsigned)splits);
-    if (kd == 32) {
-        if (mask_a) hipLaunchKernelGGL((k_zrank<T, 32, true>), grid, dim3(256), 0, st, g, cps);
-        else hipLaunchKernelGGL((k_zrank<T, 32, false>), grid, dim3(256), 0, st, g, cps);
+    if (kd == 32) {   // three products per complex one (the rank-64 form has no registers for it)
+        if (mask_a) hipLaunchKernelGGL((k_zrank<T, 32, true, true>), grid, dim3(256), 0, st, g, cps);
+        else hipLaunchKernelGGL((k_zrank<T, 32, false, true>), grid, dim3(256), 0, st, g, cps);
     } else {
         if (mask_a) hipLaunchKernelGGL((k_zrank<T, 64, true>), grid, dim3(256), 0, st, g, cps);
         else hipLaunchKernelGGL((k_zrank<T, 64, false>), grid, dim3(256), 0, st, g, cps);
@@ -493,7 +510,7 @@ template <> struct GemmTile<float2> { static constexpr int WM = 4, WN = 4; };
 template <> struct GemmTile<double2> { static constexpr int WM = 4, WN = 2; };
 
 template <typename T, bool CA, bool CB, bool MA, bool MB>
-static void launch_gemm_t(GemmArgs g, hipStream_t st, void* scratch, int64_t scratch_bytes)
+static void launch_gemm_t(GemmArgs g, hipStream_t st, void* scratch, int64_t scratch_bytes, int* nz_out)
 {
     if (g.M <= 0 || g.N <= 0) return;
     constexpr int BWM = GemmTile<T>::WM, BWN = GemmTile<T>::WN;
@@ -544,7 +561,8 @@ static void launch_gemm_t(GemmArgs g, hipStream_t st, void* scratch, int64_t scr
         launch_gemm_cfg<T, 2, 2, CA, CB, MA, MB, false, DBK, true>(g, st, nz);
     else
         launch_gemm_cfg<T, 2, 2, CA, CB, MA, MB, false, GEMM_BK, true>(g, st, nz);
-    if (g.part) {
+    if (nz_out) *nz_out = g.part ? nz : 1;
+    if (g.part && !nz_out) {
         int64_t total = g.M * g.N;
         int64_t blocks = (total + 255) / 256;
         if (blocks > 4096) blocks = 4096;
@@ -553,12 +571,15 @@ static void launch_gemm_t(GemmArgs g, hipStream_t st, void* scratch, int64_t scr
 }
 
 // Runtime dispatch over the operand forms used by the library.  Returns false
-// for a combination that has no instantiation.
+// for a combination that has no instantiation.  With nz_out, a product split
+// along K leaves its *nz_out partial products unreduced in scratch (slice z at
+// scratch + z M N, ld M; alpha and beta not applied) for the caller to reduce;
+// *nz_out = 1 means C holds the product.
 template <typename T>
 static bool zgemm(hipStream_t st, GemmOp opa, bool maska, GemmOp opb, bool maskb,
                   int64_t M, int64_t N, int64_t K, double2 alpha,
                   const T* A, int64_t lda, const T* B, int64_t ldb, double2 beta, T* C, int64_t ldc,
-                  void* scratch, int64_t scratch_bytes)
+                  void* scratch, int64_t scratch_bytes, int* nz_out = nullptr)
 {
     GemmArgs g;
     g.M = M; g.N = N; g.K = K;
@@ -567,13 +588,13 @@ static bool zgemm(hipStream_t st, GemmOp opa, bool maska, GemmOp opb, bool maskb
     g.kchunk = K; g.part = nullptr;
     const int key = (opa == OP_C ? 8 : 0) | (opb == OP_C ? 4 : 0) | (maska ? 2 : 0) | (maskb ? 1 : 0);
     switch (key) {
-    case 0:  launch_gemm_t<T, false, false, false, false>(g, st, scratch, scratch_bytes); return true;
-    case 4:  launch_gemm_t<T, false, true, false, false>(g, st, scratch, scratch_bytes); return true;
-    case 8:  launch_gemm_t<T, true, false, false, false>(g, st, scratch, scratch_bytes); return true;
-    case 2:  launch_gemm_t<T, false, false, true, false>(g, st, scratch, scratch_bytes); return true;
-    case 10: launch_gemm_t<T, true, false, true, false>(g, st, scratch, scratch_bytes); return true;
-    case 11: launch_gemm_t<T, true, false, true, true>(g, st, scratch, scratch_bytes); return true;
-    case 12: launch_gemm_t<T, true, true, false, false>(g, st, scratch, scratch_bytes); return true;
+    case 0:  launch_gemm_t<T, false, false, false, false>(g, st, scratch, scratch_bytes, nz_out); return true;
+    case 4:  launch_gemm_t<T, false, true, false, false>(g, st, scratch, scratch_bytes, nz_out); return true;
+    case 8:  launch_gemm_t<T, true, false, false, false>(g, st, scratch, scratch_bytes, nz_out); return true;
+    case 2:  launch_gemm_t<T, false, false, true, false>(g, st, scratch, scratch_bytes, nz_out); return true;
+    case 10: launch_gemm_t<T, true, false, true, false>(g, st, scratch, scratch_bytes, nz_out); return true;
+    case 11: launch_gemm_t<T, true, false, true, true>(g, st, scratch, scratch_bytes, nz_out); return true;
+    case 12: launch_gemm_t<T, true, true, false, false>(g, st, scratch, scratch_bytes, nz_out); return true;
     default: return false;
     }
 }

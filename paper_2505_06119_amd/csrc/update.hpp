@@ -224,6 +224,51 @@ __global__ __launch_bounds__(256) void k_larft_all(const T* G, const double2* ta
     larft_block<T>(G + off, tau + b0, nb, Tout + off);
 }
 
+// The R rows of a panel for the columns outside its window, from the split-K
+// partial products of W = V^H A_o (nz slices, slice z at P + z*zs, ld ldp):
+//   w = sum_z P_z[:, c]            (FP64, fixed order)
+//   W2[:, c] = T^H w               (T: the panel's T factor, ld UNGQR_NB)
+//   R12[:, c] = A_o[0:nbe, c] - V_top W2[:, c]   (V_top unit lower triangular)
+// W2 and R12 have leading dimension UNGQR_NB.  nbe <= 32.  Each half
+// wavefront (lane r = row r) takes one column at a time; T and V_top sit in LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_panel_rows(const T* P, int64_t ldp, int64_t zs, int nz, const T* Tm,
+                                                    const T* V, int64_t lda, const T* Ao, int64_t nout, int nbe,
+                                                    T* W2, T* R12)
+{
+    __shared__ double2 Ts[32][33], Vs[32][33];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    for (int q = tid; q < 32 * 32; q += 256) {
+        const int r = q % 32, c = q / 32;
+        const bool in = r < nbe && c < nbe;
+        Ts[r][c] = in ? to_d(Tm[r + UNGQR_NB * c]) : czero();
+        // V_top: entries below the diagonal from storage, 1 on it, 0 above
+        Vs[r][c] = in && r > c ? to_d(V[r + lda * c]) : (in && r == c ? make_double2(1.0, 0.0) : czero());
+    }
+    __syncthreads();
+    const int r = lane & 31, hb = lane & 32;
+    const bool live = r < nbe;
+    for (int64_t c = ((int64_t)blockIdx.x * 4 + wid) * 2 + (lane >> 5); c < nout; c += (int64_t)gridDim.x * 8) {
+        double2 w = czero();
+        if (live)
+            for (int z = 0; z < nz; ++z) w = cadd(w, to_d(P[z * zs + r + ldp * c]));
+        double2 w2 = czero();
+        for (int rr = 0; rr < nbe; ++rr) {
+            const double2 wr = make_double2(__shfl(w.x, hb + rr, MPS_WAVE), __shfl(w.y, hb + rr, MPS_WAVE));
+            w2 = cadd(w2, cmulc(Ts[rr][r], wr));   // (T^H)[r, rr] = conj(T[rr, r])
+        }
+        double2 vw = czero();
+        for (int rr = 0; rr < nbe; ++rr) {
+            const double2 x = make_double2(__shfl(w2.x, hb + rr, MPS_WAVE), __shfl(w2.y, hb + rr, MPS_WAVE));
+            vw = cadd(vw, cmul(Vs[r][rr], x));
+        }
+        if (live) {
+            W2[r + UNGQR_NB * c] = from_d<T>(w2);
+            R12[r + UNGQR_NB * c] = from_d<T>(csub(to_d(Ao[r + lda * c]), vw));
+        }
+    }
+}
+
 // Scratch carved from a caller-provided workspace.
 struct Carver {
     char* base;
@@ -556,23 +601,35 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
     prof_end(eg, st, PK_REFL, right ? 0.0 : (double)sizeof(T) * rows * nbe,
              right ? 0.0 : 8.0 * (double)nbe * nbe * rows);
     hipEvent_t et = prof_begin(st);
+    // nbe <= 32: the split-K partials stay unreduced for k_panel_rows
+    const bool fused = nbe <= 32;
+    int nzw = 1;
     if (!zgemm<T>(st, OP_C, true, OP_N, false, nbe, nout, rows, C_ONE, V, d.lda, Ao, d.lda, C_ZERO, w.Wbuf,
-                  UNGQR_NB, w.gsplit, w.gsplit_bytes))
+                  UNGQR_NB, w.gsplit, w.gsplit_bytes, fused ? &nzw : nullptr))
         return hipErrorInvalidValue;
     prof_end(et, st, PK_PANEL, (double)sizeof(T) * ro, 8.0 * nbe * ro);
+    // W2 = T^H W and R12 = A_o[p0:p0+nbe] - V_top W2
     hipEvent_t e2 = prof_begin(st);
-    if (!zgemm<T>(st, OP_C, false, OP_N, false, nbe, nout, nbe, C_ONE, w.Tbuf, UNGQR_NB, w.Wbuf, UNGQR_NB, C_ZERO,
-                  w.W2buf, UNGQR_NB, nullptr, 0))
-        return hipErrorInvalidValue;
-    {
+    if (fused) {
+        const bool split = nzw > 1;
+        const T* P = split ? (const T*)w.gsplit : (const T*)w.Wbuf;
+        const int64_t ldp = split ? nbe : UNGQR_NB, zs = (int64_t)nbe * nout;
+        int64_t blocks = (nout + 7) / 8;
+        if (blocks > 1024) blocks = 1024;
+        hipLaunchKernelGGL((k_panel_rows<T>), dim3((unsigned)blocks), dim3(256), 0, st, P, ldp, zs, nzw,
+                           (const T*)w.Tbuf, V, d.lda, (const T*)Ao, nout, nbe, w.W2buf, w.Wbuf);
+    } else {
+        if (!zgemm<T>(st, OP_C, false, OP_N, false, nbe, nout, nbe, C_ONE, w.Tbuf, UNGQR_NB, w.Wbuf, UNGQR_NB,
+                      C_ZERO, w.W2buf, UNGQR_NB, nullptr, 0))
+            return hipErrorInvalidValue;
         dim3 grid(1, (unsigned)nout);
         hipLaunchKernelGGL((k_copy_cols<T>), grid, dim3(256), 0, st, (const T*)Ao, d.lda, w.Wbuf, (int64_t)UNGQR_NB,
                            (int64_t)nbe);
+        if (!zgemm<T>(st, OP_N, true, OP_N, false, nbe, nout, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, C_ONE,
+                      w.Wbuf, UNGQR_NB, nullptr, 0))
+            return hipErrorInvalidValue;
     }
-    if (!zgemm<T>(st, OP_N, true, OP_N, false, nbe, nout, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, C_ONE, w.Wbuf,
-                  UNGQR_NB, nullptr, 0))
-        return hipErrorInvalidValue;
-    prof_end(e2, st, PK_REFL, (double)sizeof(T) * 3.0 * nbe * nout, 16.0 * (double)nbe * nbe * nout);
+    prof_end(e2, st, PK_REFL, (double)sizeof(T) * ((double)nzw + 3.0) * nbe * nout, 16.0 * (double)nbe * nbe * nout);
 
     // greedy replay of every step against the outside columns
     hipEvent_t ek = prof_begin(st);
