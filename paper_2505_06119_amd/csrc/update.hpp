@@ -249,9 +249,19 @@ __global__ __launch_bounds__(256) void k_panel_rows(const T* P, int64_t ldp, int
     const int r = lane & 31, hb = lane & 32;
     const bool live = r < nbe;
     for (int64_t c = ((int64_t)blockIdx.x * 4 + wid) * 2 + (lane >> 5); c < nout; c += (int64_t)gridDim.x * 8) {
+        // the partials in slice order, eight loads in flight at a time
         double2 w = czero();
-        if (live)
-            for (int z = 0; z < nz; ++z) w = cadd(w, to_d(P[z * zs + r + ldp * c]));
+        const T* pc = P + (live ? r : 0) + ldp * c;
+        int z = 0;
+        for (; z + 8 <= nz; z += 8) {
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = pc[(int64_t)(z + u) * zs];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) w = cadd(w, to_d(v[u]));
+        }
+        for (; z < nz; ++z) w = cadd(w, to_d(pc[(int64_t)z * zs]));
+        if (!live) w = czero();
         double2 w2 = czero();
         for (int rr = 0; rr < nbe; ++rr) {
             const double2 wr = make_double2(__shfl(w.x, hb + rr, MPS_WAVE), __shfl(w.y, hb + rr, MPS_WAVE));
