@@ -467,9 +467,11 @@ static bool zrank_update(hipStream_t st, bool mask_a, int64_t M, int64_t N, int6
     g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
     g.alpha = alpha; g.beta = make_double2(1.0, 0.0);
     g.kchunk = K; g.part = nullptr;
-    // about 3000 blocks: enough waves in flight per CU to cover HBM latency
+    // rank <= 32: about 1500 blocks (six per CU) measured best, the longer
+    // column ranges amortising the V fragment loads; rank 64: about 3000
     const int64_t rblk = (M + 127) / 128;
-    int64_t splits = (3072 + rblk - 1) / rblk;
+    const int64_t target = kd == 32 ? 1536 : 3072;
+    int64_t splits = (target + rblk - 1) / rblk;
     int64_t cps = (N + splits - 1) / splits;
     cps = (cps + 15) / 16 * 16;
     splits = (N + cps - 1) / cps;
