@@ -82,8 +82,11 @@ def time_path(M, L, torch, name, prec, a, b, g, chi, steps, warmup, learned=None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
+    per_step = []   # each update ends with a host synchronisation (its info read-back)
     for s in range(steps):
+        ts = time.perf_counter()
         one()
+        per_step.append(time.perf_counter() - ts)
         infos.append(info.as_dict())
         log(f"[bench] {name} step {s + 1}/{steps}: k={info.k} retained={info.retained:.6f} "
             f"panels={info.panels} refreshes={info.refreshes} fallback={info.fallback}")
@@ -101,7 +104,19 @@ def time_path(M, L, torch, name, prec, a, b, g, chi, steps, warmup, learned=None
     L.mps_profile(0)
     del work
     return {"seconds": t1 - t0, "infos": infos, "sampled": sampled, "prof": prof, "prof_seconds": t3 - t2,
-            "A_out": A_out, "B_out": B_out}
+            "per_step": per_step, "A_out": A_out, "B_out": B_out}
+
+
+def step_stats(per_step):
+    """Median, interquartile range and extremes of the per-update wall times (ms)."""
+    v = sorted(1000.0 * x for x in per_step)
+
+    def q(f):
+        pos = f * (len(v) - 1)
+        lo = int(pos)
+        hi = min(lo + 1, len(v) - 1)
+        return v[lo] + (v[hi] - v[lo]) * (pos - lo)
+    return {"median": q(0.5), "q25": q(0.25), "q75": q(0.75), "min": v[0], "max": v[-1], "n": len(v)}
 
 
 def state_fidelity(torch, r1, r2, chi):
@@ -306,6 +321,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "within_fidelity_bar": res_within,
+        "step_ms": step_stats(hr["per_step"]),
         "dtype": "c64",
         "data": "synthetic",
         "config": {"workload": f"two-site update chi_l=chi_m=chi_r={chi} (theta {2 * chi}x{2 * chi}), "
@@ -340,6 +356,7 @@ def main():
     for k, v in runs.items():
         last = v["infos"][-1]
         res[f"path_{k}"] = {"value": rates[k], "unit": "updates/s", "ms_per_step": 1000.0 * v["seconds"] / args.steps,
+                            "step_ms": step_stats(v["per_step"]),
                             "retained": last["retained"], "panels": last["panels"],
                             "refreshes": last["refreshes"], "window_misses": last["window_misses"],
                             "fallback_rate": sum(i["fallback"] for i in v["infos"]) / len(v["infos"]),
