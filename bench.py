@@ -37,7 +37,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "two-site gate updates/sec at χ=4096, mixed vs FP64 QRCP, at 1e-4 fidelity"
 HBM_PEAK_GBS = 8000.0
-PROFILE_SAMPLE = 8   # timed region: events on one pivot-step launch in 8
+PROFILE_SAMPLE = 32  # timed region: events on one pivot-step launch in 32 (each marker pair costs a few us)
 KCLASS = ["contract", "gate_norms", "step_a", "step_c", "trail_gemm", "norms", "ungqr", "split", "propose",
           "window", "panel", "reflector"]
 

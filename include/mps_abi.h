@@ -277,7 +277,7 @@ mps_status mps_set_small_bond_limit(int32_t max_dim);
  * Per-kernel timing.  mps_profile(mode) resets the counters and sets the
  * process-wide timing of the library's launches with HIP events recorded on
  * the caller's stream: mode 0 off; mode 1 every launch of every class; mode
- * s >= 2 only one pivot-step GEMV launch (MPS_K_STEP_C) in s, a sample that
+ * s >= 2 only one pivot-step launch (MPS_K_STEP_C) in s, a sample that
  * leaves the measured run nearly undisturbed (each event marker costs a few
  * microseconds of stream time).  A negative mode is MPS_EINVAL.
  * mps_profile_read fills up to n entries, indexed by mps_kernel_class, with

@@ -1,7 +1,8 @@
 // Optional per-kernel timing with HIP events on the launch stream.  In mode 1
 // (mps_profile(1)) every timed launch is bracketed by an event pair; in a
-// sampled mode s >= 2 only one pivot-step GEMV launch (k_step_c) in s is, so
-// that the event markers barely perturb the run they measure.  The pairs are
+// sampled mode s >= 2 only one pivot-step launch (class PK_STEP_C: k_step_c
+// or k_window_step) in s is, so that the event markers barely perturb the run
+// they measure.  The pairs are
 // resolved at the next host synchronisation point of the library and
 // accumulated per kernel class together with the algorithmic bytes and flops
 // of each launch.  Process-global; meant for single-threaded use.
