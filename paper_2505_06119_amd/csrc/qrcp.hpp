@@ -683,5 +683,7 @@ __global__ void k_ctl_panel(int32_t* ctl, int32_t jdone)
     if (threadIdx.x == 0) {
         ctl[CTL_STOP] = 0;
         ctl[CTL_JDONE] = jdone;
+        ctl[CTL_TFAIL] = 0x7fffffff;   // atomic minima of a window panel's replay
+        ctl[CTL_TFLAG] = 0x7fffffff;
     }
 }

@@ -310,7 +310,6 @@ struct UpdateWs {
     double* wsnu;            // QR_WIN_MAX
     double* wsnuref;         // QR_WIN_MAX
     int32_t* wsperm;         // QR_WIN_MAX
-    int32_t* wpart;          // 2 per 256 columns: greedy-replay partials
     ArgBest* wcp;            // 2 * QR_WIN_MAX: argmax partials of the right-looking window steps (double buffer)
     int32_t* wpiv;           // QR_NBMAX: pivot positions of those steps
     int32_t* wstep;          // QR_WIN_MAX: step at which a window column became the pivot
@@ -366,12 +365,11 @@ static bool carve_update_ws(Carver& cv, UpdateWs<T>& w, int64_t m, int64_t n, in
     w.gsplit = cv.take(sk);
     w.gsplit_bytes = sk;
     const int64_t wmax = n < QR_WIN_MAX ? n : QR_WIN_MAX;
-    w.wplan = (int32_t*)cv.take(4 * (1 + 2 * QR_WIN_MAX));
+    w.wplan = (int32_t*)cv.take(4 * (1 + 3 * QR_WIN_MAX));
     w.wsave = (T*)cv.take((int64_t)sizeof(T) * d.lda * (wmax > 0 ? wmax : 1));
     w.wsnu = (double*)cv.take(8 * QR_WIN_MAX);
     w.wsnuref = (double*)cv.take(8 * QR_WIN_MAX);
     w.wsperm = (int32_t*)cv.take(4 * QR_WIN_MAX);
-    w.wpart = (int32_t*)cv.take(8 * (rup(n, 256) + 1));
     w.wcp = (ArgBest*)cv.take((int64_t)sizeof(ArgBest) * 2 * QR_WIN_MAX);
     w.wpiv = (int32_t*)cv.take(4 * QR_NBMAX);
     w.wstep = (int32_t*)cv.take(4 * QR_WIN_MAX);
@@ -384,7 +382,7 @@ static bool carve_update_ws(Carver& cv, UpdateWs<T>& w, int64_t m, int64_t n, in
     w.win = 0;
     return d.nu && d.nuref && d.perm && d.F && d.tau && d.diagR && d.xbuf && d.xlo && d.apart && d.hh && d.fsave &&
            d.cpart && d.npart && d.cflag && d.ctl && d.dsc && w.Gbuf && w.Tbuf && w.Gall && w.Tall && w.Wbuf && w.W2buf && w.gsplit &&
-           d.pivval && d.pivkey && w.wplan && w.wsave && w.wsnu && w.wsnuref && w.wsperm && w.wpart && w.wcp &&
+           d.pivval && d.pivkey && w.wplan && w.wsave && w.wsnu && w.wsnuref && w.wsperm && w.wcp &&
            w.wpiv && w.wstep && w.worder && w.wtmp && w.vbuf && w.wtnu && w.wtnuref && w.wtperm &&
            (!theta_in_ws || d.A);
 }
@@ -516,14 +514,8 @@ static void window_setup(UpdateWs<T>& w, hipStream_t st, int64_t p0, bool save)
     QrcpDev<T>& d = w.d;
     const int W = w.win;
     hipLaunchKernelGGL((k_window_select<T>), dim3(1), dim3(1024), 0, st, d, p0, W, w.wplan, w.wcp);
-    hipLaunchKernelGGL((k_window_swap<T>), dim3((unsigned)W), dim3(256), 0, st, d, (const int32_t*)w.wplan);
-    if (save) {
-        dim3 grid((unsigned)(rup(d.m, 256) < 64 ? rup(d.m, 256) : 64), (unsigned)W);
-        hipLaunchKernelGGL((k_copy_cols<T>), grid, dim3(256), 0, st, (const T*)(d.A + d.lda * p0), d.lda, w.wsave,
-                           d.lda, d.m);
-        hipLaunchKernelGGL((k_window_meta<T>), dim3((unsigned)rup(W, 256)), dim3(256), 0, st, d, p0, W, w.wsnu,
-                           w.wsnuref, w.wsperm, 0);
-    }
+    hipLaunchKernelGGL((k_window_place<T>), dim3((unsigned)W), dim3(256), 0, st, d, p0, W, (const int32_t*)w.wplan,
+                       w.wsave, d.lda, w.wsnu, w.wsnuref, w.wsperm, save ? 1 : 0);
 }
 
 // Right-looking pivot steps p0 .. p0+nsteps-1 inside the window (k_window_step),
@@ -645,8 +637,7 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
     hipEvent_t ek = prof_begin(st);
     const unsigned nchk = (unsigned)rup(nout, 256);
     hipLaunchKernelGGL((k_window_check<T>), dim3(nchk), dim3(256), 0, st, d, (const T*)w.Wbuf, (int64_t)UNGQR_NB,
-                       cend, nout, nbe, w.wpart);
-    hipLaunchKernelGGL(k_window_reduce, dim3(1), dim3(256), 0, st, (const int32_t*)w.wpart, (int)nchk, d.ctl);
+                       cend, nout, nbe);
     prof_end(ek, st, PK_WINDOW, 8.0 * (double)nbe * nout, 0.0);
     e = read_ctl<T>(d, st, hctl);
     if (e != hipSuccess) return e;

@@ -60,7 +60,8 @@ __device__ __forceinline__ int block_scan_flags1024(bool flag, int* wsum, int* t
 // on the norms' bit patterns (non-negative doubles order like their bits),
 // equal norms at the threshold taken in column order -- and write the swap
 // plan that brings them to [p0, p0+W): plan[0] = number of pairs, then pairs
-// (a, b) of column positions to exchange.  The first pivot (largest norm,
+// (a, b) of column positions to exchange, then from plan[1 + 2W] one entry
+// per window slot: the position of the column that moves into it, or -1.  The first pivot (largest norm,
 // smallest key on ties) is always in the window; its argmax partial for the
 // post-swap positions goes to cpart[0], cflag[0].
 // Requires W <= 1024, W < n - p0 <= WIN_SORT_MAX.
@@ -216,7 +217,9 @@ __global__ __launch_bounds__(1024) void k_window_select(QrcpDev<T> d, int64_t p0
     if (vac) {
         plan[1 + 2 * iv] = (int32_t)(p0 + s_d[iv]);
         plan[2 + 2 * iv] = (int32_t)(p0 + qe);
+        plan[1 + 2 * W + s_d[iv]] = (int32_t)(p0 + qe);   // the slot's incoming column
     }
+    if (tid < W && !disp) plan[1 + 2 * W + tid] = -1;      // slot already holds a window column
     const ArgBest b0 = s_best[0];
     if (tid == 0) plan[0] = nv;
     // first partial: the argmax, at its post-swap position; and one partial per
@@ -235,16 +238,21 @@ __global__ __launch_bounds__(1024) void k_window_select(QrcpDev<T> d, int64_t p0
     }
 }
 
-// Step 1b: exchange the planned column pairs (all m rows, norms, keys).
-// grid: W blocks (one pair each; blocks past plan[0] return).
+// Step 1b (block q = window slot p0 + q): carry out the plan -- a slot with an
+// incoming column b exchanges all m rows, norm, reference norm and key with
+// it -- and, with save, keep a copy of the slot's new column (wsave[:, q], ld
+// lds) and of its norms and key (snu, snuref, sperm).  grid: W blocks.
 template <typename T>
-__global__ __launch_bounds__(256) void k_window_swap(QrcpDev<T> d, const int32_t* plan)
+__global__ __launch_bounds__(256) void k_window_place(QrcpDev<T> d, int64_t p0, int W, const int32_t* plan, T* wsave,
+                                                      int64_t lds, double* snu, double* snuref, int32_t* sperm,
+                                                      int save)
 {
     const int q = blockIdx.x;
-    if (q >= plan[0]) return;
-    const int64_t a = plan[1 + 2 * q], b = plan[2 + 2 * q];
+    const int64_t a = p0 + q, b = plan[1 + 2 * W + q];
+    if (b < 0 && !save) return;   // nothing moves into this slot
     T* ca = d.A + d.lda * a;
-    T* cb = d.A + d.lda * b;
+    T* cb = d.A + d.lda * (b >= 0 ? b : a);
+    T* cs = wsave + lds * q;
     for (int64_t i0 = threadIdx.x; i0 < d.m; i0 += 256 * 8) {
         T x[8], y[8];
 #pragma unroll
@@ -258,15 +266,25 @@ __global__ __launch_bounds__(256) void k_window_swap(QrcpDev<T> d, const int32_t
         for (int u = 0; u < 8; ++u) {
             const int64_t i = i0 + 256 * u;
             if (i < d.m) {
-                ca[i] = y[u];
-                cb[i] = x[u];
+                if (b >= 0) {
+                    ca[i] = y[u];
+                    cb[i] = x[u];
+                }
+                if (save) cs[i] = b >= 0 ? y[u] : x[u];
             }
         }
     }
     if (threadIdx.x == 0) {
-        const double t0 = d.nu[a]; d.nu[a] = d.nu[b]; d.nu[b] = t0;
-        const double t1 = d.nuref[a]; d.nuref[a] = d.nuref[b]; d.nuref[b] = t1;
-        const int32_t t2 = d.perm[a]; d.perm[a] = d.perm[b]; d.perm[b] = t2;
+        if (b >= 0) {
+            const double t0 = d.nu[a]; d.nu[a] = d.nu[b]; d.nu[b] = t0;
+            const double t1 = d.nuref[a]; d.nuref[a] = d.nuref[b]; d.nuref[b] = t1;
+            const int32_t t2 = d.perm[a]; d.perm[a] = d.perm[b]; d.perm[b] = t2;
+        }
+        if (save) {
+            snu[q] = d.nu[a];
+            snuref[q] = d.nuref[a];
+            sperm[q] = d.perm[a];
+        }
     }
 }
 
@@ -290,12 +308,13 @@ __global__ __launch_bounds__(256) void k_window_meta(QrcpDev<T> d, int64_t p0, i
 
 // Step 3: greedy replay for the columns [c0, c0 + nout) outside the window.
 // R12 (nbe x nout, leading dimension ldr) holds their R rows of the panel.
-// Per block: wpart[2b] = first failing step, wpart[2b+1] = first step after
-// which a norm falls under the recomputation threshold, plus one (both nbe+1
-// when none).  One thread per column.
+// ctl[CTL_TFAIL] = first failing step, ctl[CTL_TFLAG] = first step after which
+// a norm falls under the recomputation threshold, plus one (nbe+1 when none):
+// minima over the columns, per block by shuffles, across blocks by atomic
+// minimum on values k_ctl_panel set to INT_MAX.  One thread per column.
 template <typename T>
 __global__ __launch_bounds__(256) void k_window_check(QrcpDev<T> d, const T* R12, int64_t ldr, int64_t c0,
-                                                      int64_t nout, int nbe, int32_t* wpart)
+                                                      int64_t nout, int nbe)
 {
     __shared__ int s_min[2][4];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -332,34 +351,8 @@ __global__ __launch_bounds__(256) void k_window_check(QrcpDev<T> d, const T* R12
     }
     __syncthreads();
     if (tid == 0) {
-        wpart[2 * blockIdx.x] = min(min(s_min[0][0], s_min[0][1]), min(s_min[0][2], s_min[0][3]));
-        wpart[2 * blockIdx.x + 1] = min(min(s_min[1][0], s_min[1][1]), min(s_min[1][2], s_min[1][3]));
-    }
-}
-
-// Minimum over the check partials into ctl[CTL_TFAIL], ctl[CTL_TFLAG].
-__global__ __launch_bounds__(256) void k_window_reduce(const int32_t* wpart, int nparts, int32_t* ctl)
-{
-    __shared__ int s_min[2][4];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    int a = 0x7fffffff, b = 0x7fffffff;
-    for (int q = tid; q < nparts; q += 256) {
-        a = min(a, wpart[2 * q]);
-        b = min(b, wpart[2 * q + 1]);
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        a = min(a, __shfl_xor(a, off, MPS_WAVE));
-        b = min(b, __shfl_xor(b, off, MPS_WAVE));
-    }
-    if (lane == 0) {
-        s_min[0][wid] = a;
-        s_min[1][wid] = b;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        ctl[CTL_TFAIL] = min(min(s_min[0][0], s_min[0][1]), min(s_min[0][2], s_min[0][3]));
-        ctl[CTL_TFLAG] = min(min(s_min[1][0], s_min[1][1]), min(s_min[1][2], s_min[1][3]));
+        atomicMin(d.ctl + CTL_TFAIL, min(min(s_min[0][0], s_min[0][1]), min(s_min[0][2], s_min[0][3])));
+        atomicMin(d.ctl + CTL_TFLAG, min(min(s_min[1][0], s_min[1][1]), min(s_min[1][2], s_min[1][3])));
     }
 }
 
