@@ -313,7 +313,7 @@ struct UpdateWs {
     ArgBest* wcp;            // 2 * QR_WIN_MAX: argmax partials of the right-looking window steps (double buffer)
     int32_t* wpiv;           // QR_NBMAX: pivot positions of those steps
     int32_t* wstep;          // QR_WIN_MAX: step at which a window column became the pivot
-    int32_t* worder;         // QR_WIN_MAX: final column order of the window
+    int32_t* worder;         // 1 + 3 QR_WIN_MAX: the panel-end column moves of the window
     T* wtmp;                 // like wsave: the window reordered at the panel end
     T* vbuf;                 // QR_NBMAX columns of lda: beta and v of those steps
     double* wtnu;            // QR_WIN_MAX
@@ -373,7 +373,7 @@ static bool carve_update_ws(Carver& cv, UpdateWs<T>& w, int64_t m, int64_t n, in
     w.wcp = (ArgBest*)cv.take((int64_t)sizeof(ArgBest) * 2 * QR_WIN_MAX);
     w.wpiv = (int32_t*)cv.take(4 * QR_NBMAX);
     w.wstep = (int32_t*)cv.take(4 * QR_WIN_MAX);
-    w.worder = (int32_t*)cv.take(4 * QR_WIN_MAX);
+    w.worder = (int32_t*)cv.take(4 * (1 + 3 * QR_WIN_MAX));
     w.wtmp = (T*)cv.take((int64_t)sizeof(T) * d.lda * (wmax > 0 ? wmax : 1));
     w.vbuf = (T*)cv.take((int64_t)sizeof(T) * d.lda * QR_NBMAX);
     w.wtnu = (double*)cv.take(8 * QR_WIN_MAX);
@@ -544,12 +544,13 @@ static void window_reorder(UpdateWs<T>& w, hipStream_t st, int64_t p0, int nbe)
     const int W = w.win;
     hipEvent_t ew = prof_begin(st);
     hipLaunchKernelGGL(k_window_order, dim3(1), dim3(1024), 0, st, (const int32_t*)w.wpiv, nbe, p0, W, w.worder);
-    dim3 grid((unsigned)(rup(d.m, 256) < 64 ? rup(d.m, 256) : 64), (unsigned)W);
-    hipLaunchKernelGGL((k_window_gather<T>), grid, dim3(256), 0, st, d, (const int32_t*)w.worder, nbe, p0,
+    // at most 2 nbe columns move
+    dim3 grid((unsigned)(rup(d.m, 256) < 64 ? rup(d.m, 256) : 64), (unsigned)(2 * nbe < W ? 2 * nbe : W));
+    hipLaunchKernelGGL((k_window_gather<T>), grid, dim3(256), 0, st, d, (const int32_t*)w.worder, p0,
                        (const T*)w.vbuf, w.wtmp, w.wtnu, w.wtnuref, w.wtperm, 0);
-    hipLaunchKernelGGL((k_window_gather<T>), grid, dim3(256), 0, st, d, (const int32_t*)w.worder, nbe, p0,
+    hipLaunchKernelGGL((k_window_gather<T>), grid, dim3(256), 0, st, d, (const int32_t*)w.worder, p0,
                        (const T*)w.vbuf, w.wtmp, w.wtnu, w.wtnuref, w.wtperm, 1);
-    prof_end(ew, st, PK_WINDOW, (double)sizeof(T) * 4.0 * (double)d.m * W, 0.0);
+    prof_end(ew, st, PK_WINDOW, (double)sizeof(T) * 8.0 * (double)d.m * nbe, 0.0);
 }
 
 // One candidate-window panel at p0 (see window.hpp).  On return *jend is the

@@ -615,50 +615,72 @@ __global__ __launch_bounds__(WSTEP_NT) void k_window_step(QrcpDev<T> d, int64_t 
     }
 }
 
-// Panel end of the right-looking window steps: the order of the window's
-// columns, pivots first (in step order), then the others by position.
-// One block of up to 1024 threads (W <= 1024).
-__global__ __launch_bounds__(1024) void k_window_order(const int32_t* wpiv, int nbe, int64_t p0, int W, int32_t* order)
+// Panel end of the right-looking window steps: the moves that put the pivots
+// first (in step order).  Pivot q goes to slot q; a non-pivot column sitting
+// in one of the slots 0..nbe-1 goes to a slot a pivot vacated (both taken in
+// slot order); every other column stays, so at most 2 nbe columns move (the
+// order of the non-pivot columns does not matter: the next panel reselects
+// its window by norm, ties by key).  mv[0] = number of moves; move t is
+// (mv[1+3t], mv[2+3t], mv[3+3t]) = (target slot, source column, pivot step or
+// -1).  One block of up to 1024 threads (W <= 1024).
+__global__ __launch_bounds__(1024) void k_window_order(const int32_t* wpiv, int nbe, int64_t p0, int W, int32_t* mv)
 {
     __shared__ int32_t s_ispiv[1024];
+    __shared__ int32_t s_d[1024];
     __shared__ int wsum[16];
     const int tid = threadIdx.x;
     if (tid < W) s_ispiv[tid] = 0;
     __syncthreads();
     if (tid < nbe) s_ispiv[wpiv[tid] - p0] = 1;
     __syncthreads();
-    const bool rest = tid < W && !s_ispiv[tid];
-    int tot = 0;
-    const int r = block_scan_flags1024(rest, wsum, &tot);
-    if (tid < nbe) order[tid] = wpiv[tid];
-    if (rest) order[nbe + r] = (int32_t)(p0 + tid);
+    // non-pivot slots below nbe (sources) and pivot slots from nbe on (targets)
+    const bool src = tid < nbe && !s_ispiv[tid];
+    int nd = 0, ne = 0;
+    const int rd = block_scan_flags1024(src, wsum, &nd);
+    if (src) s_d[rd] = tid;
+    const bool dst = tid >= nbe && tid < W && s_ispiv[tid];
+    const int re = block_scan_flags1024(dst, wsum, &ne);
+    __syncthreads();
+    if (tid < nbe) {
+        mv[1 + 3 * tid] = tid;
+        mv[2 + 3 * tid] = wpiv[tid];
+        mv[3 + 3 * tid] = tid;
+    }
+    if (dst) {
+        const int t = nbe + re;
+        mv[1 + 3 * t] = tid;
+        mv[2 + 3 * t] = (int32_t)(p0 + s_d[re]);
+        mv[3 + 3 * t] = -1;
+    }
+    if (tid == 0) mv[0] = nbe + ne;
 }
 
-// dir 0: tmp[:, q] = the window column order[q] in its final form (for the
-// q-th pivot, q < nbe: rows above p0 + q from A, beta and v from vbuf[:, q];
-// otherwise all rows from A), and its scalars into snu/snuref/sperm.
-// dir 1: A[:, p0 + q] = tmp[:, q] and the scalars back.  grid: (row chunks, W).
+// dir 0: tmp[:, t] = the final form of move t's column (for pivot step q:
+// rows above p0 + q from A, beta and v from vbuf[:, q]; otherwise all rows
+// from A), and its scalars into snu/snuref/sperm.  dir 1: the target slot
+// receives tmp[:, t] and the scalars.  grid: (row chunks, >= mv[0]).
 template <typename T>
-__global__ __launch_bounds__(256) void k_window_gather(QrcpDev<T> d, const int32_t* order, int nbe, int64_t p0,
-                                                       const T* vbuf, T* tmp, double* snu, double* snuref,
-                                                       int32_t* sperm, int dir)
+__global__ __launch_bounds__(256) void k_window_gather(QrcpDev<T> d, const int32_t* mv, int64_t p0, const T* vbuf,
+                                                       T* tmp, double* snu, double* snuref, int32_t* sperm, int dir)
 {
-    const int q = blockIdx.y;
-    const int64_t src = dir == 0 ? order[q] : 0;
-    const int64_t vrow = q < nbe ? p0 + q : d.m;   // first row taken from vbuf
+    const int t = blockIdx.y;
+    if (t >= mv[0]) return;
+    const int64_t tgt = p0 + mv[1 + 3 * t], src = mv[2 + 3 * t];
+    const int q = mv[3 + 3 * t];
+    const int64_t vrow = q >= 0 ? p0 + q : d.m;   // first row taken from vbuf
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < d.m; i += (int64_t)gridDim.x * 256) {
-        if (dir == 0) tmp[i + d.lda * q] = i >= vrow ? vbuf[i + d.lda * q] : d.A[i + d.lda * src];
-        else d.A[i + d.lda * (p0 + q)] = tmp[i + d.lda * q];
+        if (dir == 0) tmp[i + d.lda * t] = i >= vrow ? vbuf[i + d.lda * q] : d.A[i + d.lda * src];
+        else d.A[i + d.lda * tgt] = tmp[i + d.lda * t];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (dir == 0) {
-            snu[q] = d.nu[src];
-            snuref[q] = d.nuref[src];
-            sperm[q] = d.perm[src];
+            snu[t] = d.nu[src];
+            snuref[t] = d.nuref[src];
+            sperm[t] = d.perm[src];
         } else {
-            d.nu[p0 + q] = snu[q];
-            d.nuref[p0 + q] = snuref[q];
-            d.perm[p0 + q] = sperm[q];
+            d.nu[tgt] = snu[t];
+            d.nuref[tgt] = snuref[t];
+            d.perm[tgt] = sperm[t];
         }
     }
 }
