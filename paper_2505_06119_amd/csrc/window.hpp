@@ -55,6 +55,29 @@ __device__ __forceinline__ int block_scan_flags1024(bool flag, int* wsum, int* t
     return off + inwave;
 }
 
+// Exclusive prefix sum of v over the threads of a 1024-thread block; *total
+// receives the block total.  `wsum` is LDS scratch of 16 ints.
+__device__ __forceinline__ int block_scan_counts1024(int v, int* wsum, int* total)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(incl, off, MPS_WAVE);
+        if (lane >= off) incl += t;
+    }
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+        if (w < wid) off += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + incl - v;
+}
+
 // Step 1a (one block of 1024 threads): choose the window among the remaining
 // columns [p0, n) -- the W largest residual norms, found by a radix select
 // on the norms' bit patterns (non-negative doubles order like their bits),
@@ -162,20 +185,29 @@ __global__ __launch_bounds__(1024) void k_window_select(QrcpDev<T> d, int64_t p0
         if (all_in) break;
     }
     // membership: above the threshold prefix, or at it (all of them when the
-    // bin was taken whole, else the first `need` in column order)
-    int taken_eq = 0;
-    for (int u = 0; u < PER; ++u) {
-        const int q0 = 1024 * u;
-        const int q = tid + q0;
-        const bool valid = q < L;
-        const uint64_t hb = valid ? (s_b[q] & mask) : 0;
-        const bool above = valid && hb > prefix;
-        const bool at = valid && hb == prefix;
+    // bin was taken whole, else the first `need` in column order).  Here each
+    // thread owns PER consecutive columns, so one block scan of the per-thread
+    // counts ranks every column at the threshold in column order.
+    {
+        int cnt = 0;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int q = PER * tid + u;
+            cnt += (q < L && (s_b[q] & mask) == prefix) ? 1 : 0;
+        }
         int tot = 0;
-        const int rank = block_scan_flags1024(at, wsum, &tot);
-        const bool take = above || (at && (all_in || taken_eq + rank < need));
-        if (take) s_in[q] = 1;
-        taken_eq += tot;
+        int rank = block_scan_counts1024(cnt, wsum, &tot);
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int q = PER * tid + u;
+            const bool valid = q < L;
+            const uint64_t hb = valid ? (s_b[q] & mask) : 0;
+            const bool above = valid && hb > prefix;
+            const bool at = valid && hb == prefix;
+            const bool take = above || (at && (all_in || rank < need));
+            rank += at ? 1 : 0;
+            if (take) s_in[q] = 1;
+        }
     }
     __syncthreads();
     // the global argmax must be in the window (it is, unless ties at the threshold left it out)
@@ -187,15 +219,24 @@ __global__ __launch_bounds__(1024) void k_window_select(QrcpDev<T> d, int64_t p0
         s_sel[3] = s_in[b.slot] ? -1 : b.slot;
     }
     __syncthreads();
-    // compact the window in column order
-    int base = 0;
-    for (int u = 0; u < PER; ++u) {
-        const int q = tid + 1024 * u;
-        const bool f = q < L && s_in[q];
+    // compact the window in column order (one scan of per-thread member counts)
+    {
+        int cnt = 0;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int q = PER * tid + u;
+            cnt += (q < L && s_in[q]) ? 1 : 0;
+        }
         int tot = 0;
-        const int r = block_scan_flags1024(f, wsum, &tot);
-        if (f && base + r < W) s_win[base + r] = q;
-        base += tot;
+        int base = block_scan_counts1024(cnt, wsum, &tot);
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int q = PER * tid + u;
+            if (q < L && s_in[q]) {
+                if (base < W) s_win[base] = q;
+                ++base;
+            }
+        }
     }
     __syncthreads();
     if (tid == 0 && s_sel[3] >= 0) {
