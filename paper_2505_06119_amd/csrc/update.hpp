@@ -702,7 +702,8 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
         *nparts = (int)nblk;
         if (stats) stats->refreshes++;
     } else {
-        hipLaunchKernelGGL((k_window_commit<T>), dim3(nchk), dim3(256), 0, st, d, p0, cend, nout, nbe);
+        hipLaunchKernelGGL((k_window_commit<T>), dim3(nchk), dim3(256), 0, st, d, (const T*)w.Wbuf,
+                           (int64_t)UNGQR_NB, cend, nout, nbe);
         *nparts = 0;
     }
     *jend_out = jend;

@@ -366,19 +366,33 @@ __global__ __launch_bounds__(256) void k_window_check(QrcpDev<T> d, const T* R12
         double s = d.nu[c];
         const double lim = d.tol * d.nuref[c];
         const int32_t key = d.perm[c];
-        for (int t = 0; t < nbe; ++t) {
-            const double pv = d.pivval[t];
-            if (s > pv || (s == pv && key < d.pivkey[t])) {
-                tfail = t;
-                break;
+        // rows in chunks of 8 loaded ahead (clamped, unconditional), so the
+        // early exits do not serialise one load per step
+        const T* rq = R12 + ldr * q;
+        bool done = false;
+        for (int t0 = 0; t0 < nbe && !done; t0 += 8) {
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = rq[t0 + u < nbe ? t0 + u : nbe - 1];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int t = t0 + u;
+                if (done || t >= nbe) break;
+                const double pv = d.pivval[t];
+                if (s > pv || (s == pv && key < d.pivkey[t])) {
+                    tfail = t;
+                    done = true;
+                    break;
+                }
+                double nn = s - cabs2(to_d(v[u]));
+                if (nn < 0.0) nn = 0.0;
+                if (nn <= lim) {
+                    tflag = t + 1;
+                    done = true;
+                    break;
+                }
+                s = nn;
             }
-            double nn = s - cabs2(to_d(R12[t + ldr * q]));
-            if (nn < 0.0) nn = 0.0;
-            if (nn <= lim) {
-                tflag = t + 1;
-                break;
-            }
-            s = nn;
         }
     }
 #pragma unroll
@@ -398,17 +412,30 @@ __global__ __launch_bounds__(256) void k_window_check(QrcpDev<T> d, const T* R12
 }
 
 // Step 4 (no recomputation pending): downdate the outside columns' norms by
-// their R rows r0 .. r0+nbe-1, now stored in A, with the per-step clamp of
-// the step kernel.  One thread per column.
+// their R rows 0 .. nbe-1 in R12 (the values the replay used), with the
+// per-step clamp of the step kernel.  One thread per column.
 template <typename T>
-__global__ __launch_bounds__(256) void k_window_commit(QrcpDev<T> d, int64_t r0, int64_t c0, int64_t nout, int nbe)
+__global__ __launch_bounds__(256) void k_window_commit(QrcpDev<T> d, const T* R12, int64_t ldr, int64_t c0,
+                                                       int64_t nout, int nbe)
 {
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (q >= nout) return;
     const int64_t c = c0 + q;
+    const T* rq = R12 + ldr * q;
     double s = d.nu[c];
-    for (int t = 0; t < nbe; ++t) {
-        const double nn = s - cabs2(to_d(d.A[r0 + t + d.lda * c]));
+    int t = 0;
+    for (; t + 8 <= nbe; t += 8) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = rq[t + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double nn = s - cabs2(to_d(v[u]));
+            s = nn < 0.0 ? 0.0 : nn;
+        }
+    }
+    for (; t < nbe; ++t) {
+        const double nn = s - cabs2(to_d(rq[t]));
         s = nn < 0.0 ? 0.0 : nn;
     }
     d.nu[c] = s;
