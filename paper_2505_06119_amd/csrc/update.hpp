@@ -23,8 +23,8 @@
 #include <stdarg.h>
 #include <stdio.h>
 
-// What the last failed pivoted QR found inconsistent (hipErrorUnknown
-// returns of the drivers below); empty when none.  Thread-unsafe, like the
+// What the last failed pivoted QR found inconsistent (the hipErrorUnknown
+// returns of run_qrcp and window_panel below); empty when none.  Thread-unsafe, like the
 // rest of the host sequencing.
 static char g_qr_diag[320];
 
