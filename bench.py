@@ -18,8 +18,9 @@ The headline value is the fastest mixed path whose norm fidelity stays within
 1e-4 (relative) of the FP64 QRCP result; the overlap of the truncated states
 is reported beside it.
 The roofline of the pivot-step kernel (k_window_step) comes from HIP events on
-the launch stream around one such launch in 8 of the timed steps
-(mps_profile(8)); the per-kernel table
+the launch stream of the timed steps: one event pair around one panel's run of
+back-to-back step launches in 8 (mps_profile(8)), so the figure is the kernel's
+duration plus the dispatch gap between dependent launches; the per-kernel table
 from one extra, fully event-timed update after them (mps_profile(1)).  The
 plain FP64 CPU oracle is timed on a bounded sample for cpu_baseline.
 
@@ -37,7 +38,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "two-site gate updates/sec at χ=4096, mixed vs FP64 QRCP, at 1e-4 fidelity"
 HBM_PEAK_GBS = 8000.0
-PROFILE_SAMPLE = 32  # timed region: events on one pivot-step launch in 32 (each marker pair costs a few us)
+PROFILE_SAMPLE = 8  # timed region: one run of window-step launches (a panel's pivot steps) in 8 carries an event pair
 KCLASS = ["contract", "gate_norms", "step_a", "step_c", "trail_gemm", "norms", "ungqr", "split", "propose",
           "window", "panel", "reflector"]
 
@@ -76,8 +77,9 @@ def time_path(M, L, torch, name, prec, a, b, g, chi, steps, warmup, learned=None
         t = time.time()
         one()
         log(f"[bench] {name} warmup {w + 1}/{warmup}: {time.time() - t:.3f} s")
-    # timed region: only one pivot-step launch in PROFILE_SAMPLE carries an
-    # event pair, so the live roofline costs the timed steps well under 1%
+    # timed region: only one run of pivot-step launches in PROFILE_SAMPLE
+    # carries an event pair, so the live roofline costs the timed steps well
+    # under 1%
     L.mps_profile(PROFILE_SAMPLE)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -342,7 +344,8 @@ def main():
                            "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                            "traffic": traffic, "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + "
                                                                "WRITE_SIZE, copy-calibrated)",
-                           "timed_launches": sc["launches"], "sampling": f"1 in {PROFILE_SAMPLE} pivot-step "
+                           "timed_launches": sc["launches"], "sampling": f"one event pair around 1 in {PROFILE_SAMPLE} "
+                                                                             "panel runs of back-to-back step "
                                                                              "launches of the timed steps",
                            "avg_us": 1000.0 * sc["ms"] / sc["launches"],
                            "alg_bytes_per_launch": sc["bytes"] / sc["launches"]}

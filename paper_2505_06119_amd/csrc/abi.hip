@@ -187,6 +187,11 @@ extern "C" mps_status mps_profile(int mode)
     g_prof.on = mode != 0;
     g_prof.stride = mode > 1 ? mode : 1;
     g_prof.counter = 0;
+    g_prof.runs = 0;
+    for (auto& r : g_prof.pending) {
+        g_prof.pool.push_back(r.a);
+        g_prof.pool.push_back(r.b);
+    }
     g_prof.pending.clear();
     for (int c = 0; c < PK_COUNT; ++c) g_prof.acc[c] = ProfAcc{0, 0.0, 0.0, 0.0};
     return MPS_OK;
