@@ -398,7 +398,7 @@ struct QrcpStats {
 };
 
 // a4-a10 on d.A; expects nu/nuref/perm/ctl[PIV] set up (pivoting) and the
-// control block reset.  Synchronises the stream once per panel.
+// control block reset.  Waits for the stream once per panel (read_ctl).
 // Householder QR of d.A with the columns in their given order (a centre move,
 // or pivoted QR with a pivot order known in advance).  Only the panel's own
 // columns go through the per-column steps; the trailing columns receive the
