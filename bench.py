@@ -238,8 +238,8 @@ def layer_chains(M, torch, synth):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--chi", type=int, default=4096)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-sample-chi", type=int, default=1024)
