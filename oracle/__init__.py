@@ -13,7 +13,9 @@ Pieces and the passages they follow (arXiv 2505.06119):
 * ``qrcp``              -- Table III, QR with pivoting M = Q R P^T; the greedy
   definition with exact residual norms, in plain C (``qrcp_oracle.c``).
 * ``two_site_update``   -- Sec. III-C.2: contract, truncated pivoted-QR
-  decomposition, split back into two sites.
+  decomposition, split back into two sites; with ``truncation="svd"`` the
+  truncated decomposition is the SVD of Table III (M = U S V^dagger), the
+  Schmidt decomposition of Sec. II-B, keeping the k largest singular values.
 * ``MPS``               -- Sec. III-C.1 canonicalisation (QR / LQ moves of the
   orthogonality centre) and Sec. III-C.2 application of two-site gates; the
   state is kept unnormalised so that ``norm_fidelity`` is the paper's
@@ -122,13 +124,33 @@ def theta(a: np.ndarray, b: np.ndarray, g: np.ndarray) -> np.ndarray:
     return t.reshape(2 * chi_l, 2 * chi_r)
 
 
-def two_site_update(a: np.ndarray, b: np.ndarray, g: np.ndarray, chi_cap: int) -> dict:
+def svd_truncate(th: np.ndarray, kmax: int) -> dict:
+    """Truncated SVD (Table III, M = U S V^dagger): the k = min(kmax, m, n)
+    largest singular values.  Left factor U_k (orthonormal columns), right
+    factor S_k V_k^dagger, err = (sum of the discarded s_i^2)^(1/2)."""
+    m, n = th.shape
+    k = min(int(kmax), m, n)
+    u, sv, vh = np.linalg.svd(th, full_matrices=False)
+    return {"U": u[:, :k], "SVh": sv[:k, None] * vh[:k], "s": sv, "k": k,
+            "err": float(np.sqrt(np.sum(sv[k:] ** 2)))}
+
+
+def two_site_update(a: np.ndarray, b: np.ndarray, g: np.ndarray, chi_cap: int, truncation: str = "qrcp") -> dict:
     """Contract, factorise by truncated pivoted QR, split (Sec. III-C.2).
 
     The new left site is Q_k reshaped (chi_l, 2, k); the new right site is
-    R_k P^T reshaped (k, 2, chi_r).  Nothing is renormalised."""
+    R_k P^T reshaped (k, 2, chi_r).  With truncation="svd" they are U_k and
+    S_k V_k^dagger.  Nothing is renormalised."""
     chi_l, chi_r = a.shape[0], b.shape[2]
     th = theta(a, b, g)
+    if truncation == "svd":
+        f = svd_truncate(th, chi_cap)
+        k = f["k"]
+        return {"A": np.ascontiguousarray(f["U"].reshape(chi_l, 2, k)),
+                "B": np.ascontiguousarray(f["SVh"].reshape(k, 2, chi_r)), "k": k, "err": f["err"],
+                "norm2": float(np.vdot(th, th).real), "theta": th, "s": f["s"]}
+    if truncation != "qrcp":
+        raise ValueError(f"unknown truncation {truncation!r}")
     f = qrcp(th, chi_cap, pivoting=True)
     k = f["k"]
     a2 = f["Q"].reshape(chi_l, 2, k)
@@ -142,10 +164,11 @@ def two_site_update(a: np.ndarray, b: np.ndarray, g: np.ndarray, chi_cap: int) -
 class MPS:
     """Matrix product state with sites [l, s, r] (Eq. (2)), kept unnormalised."""
 
-    def __init__(self, sites, chi_cap: int, centre: int = 0):
+    def __init__(self, sites, chi_cap: int, centre: int = 0, truncation: str = "qrcp"):
         self.sites = [np.array(s, dtype=np.complex128) for s in sites]
         self.chi_cap = int(chi_cap)
         self.centre = int(centre)
+        self.truncation = truncation
         self.history = []
 
     @property
@@ -183,7 +206,7 @@ class MPS:
     def apply_gate(self, i: int, g: np.ndarray, chi_cap: int | None = None) -> dict:
         self.move_centre(i if self.centre <= i else i + 1)
         cap = self.chi_cap if chi_cap is None else int(chi_cap)
-        u = two_site_update(self.sites[i], self.sites[i + 1], g, cap)
+        u = two_site_update(self.sites[i], self.sites[i + 1], g, cap, self.truncation)
         self.sites[i], self.sites[i + 1] = u["A"], u["B"]
         self.centre = i + 1
         rec = {"i": i, "k": u["k"], "err": u["err"], "norm2": u["norm2"]}
