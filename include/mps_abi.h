@@ -274,12 +274,35 @@ mps_status mps_set_tuning(int32_t panel_width, int32_t qr_window);
 mps_status mps_set_small_bond_limit(int32_t max_dim);
 
 /* ------------------------------------------------------------------------
+ * Truncation of a context's two-site updates (Table III: pivoted QR
+ * M = Q R P^T, or SVD M = U S V^dagger; Sec. III-C.2 applies either).
+ *   MPS_TRUNC_QRCP (default): truncated pivoted QR, site i <- Q_k,
+ *                  site i+1 <- R_k P^T.
+ *   MPS_TRUNC_SVD:  truncated SVD keeping the k = min(chi_cap, 2 chi_l,
+ *                  2 chi_r) largest singular values (ties: the smaller
+ *                  row of theta^H's Jacobi order), site i <- U_k,
+ *                  site i+1 <- S_k V_k^dagger; eps^2 = the sum of the
+ *                  discarded squared singular values.  Computed by one-sided
+ *                  Jacobi in FP64 inside the small-bond chains only: a call
+ *                  with an update whose bond dimensions exceed the chain
+ *                  limit (mps_set_small_bond_limit) returns MPS_EINVAL before
+ *                  anything changes.  Needs pivot = MPS_PIVOT_QRCP.
+ * The renormalisation, norm-fidelity bookkeeping and update info are those
+ * of the QR updates (qrcp_err_sq reads -1 for an SVD update).  Returns
+ * MPS_EINVAL for a NULL context, an unknown mode or SVD with learned pivots.
+ * ------------------------------------------------------------------------ */
+typedef enum { MPS_TRUNC_QRCP = 0, MPS_TRUNC_SVD = 1 } mps_truncation;
+mps_status mps_set_truncation(mps_ctx* ctx, int32_t mode);
+
+/* ------------------------------------------------------------------------
  * Per-kernel timing.  mps_profile(mode) resets the counters and sets the
  * process-wide timing of the library's launches with HIP events recorded on
  * the caller's stream: mode 0 off; mode 1 every launch of every class; mode
- * s >= 2 only one pivot-step launch (MPS_K_STEP_C) in s, a sample that
- * leaves the measured run nearly undisturbed (each event marker costs a few
- * microseconds of stream time).  A negative mode is MPS_EINVAL.
+ * s >= 2 only the pivot steps (MPS_K_STEP_C), sampled: one run of a panel's
+ * back-to-back window-step launches in s is bracketed by a single event pair
+ * and counted as that many launches (outside a window, one step launch in
+ * s), which leaves the measured run nearly undisturbed (each event marker
+ * costs a few microseconds of stream time).  A negative mode is MPS_EINVAL.
  * mps_profile_read fills up to n entries, indexed by mps_kernel_class, with
  * the timed launch count, their summed event time and their algorithmic
  * bytes and flops.  Not thread-safe.

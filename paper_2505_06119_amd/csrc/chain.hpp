@@ -28,7 +28,7 @@
 #define CH_NT 256          // threads of the chain workgroup
 #define CH_DIM_MAX 64      // largest bond dimension a chain operation may touch
 
-enum { CH_RIGHT = 0, CH_LEFT = 1, CH_UPDATE = 2 };
+enum { CH_RIGHT = 0, CH_LEFT = 1, CH_UPDATE = 2, CH_UPDATE_SVD = 3 };
 
 // One operation of a chain (host-built, read by the kernel).
 //   CH_RIGHT  centre s -> s+1.  s0 = site s (2 dl x dr), s1 = site s+1
@@ -39,6 +39,8 @@ enum { CH_RIGHT = 0, CH_LEFT = 1, CH_UPDATE = 2 };
 //   CH_UPDATE bond (i, i+1).  s0 = site i (2 dl x dm), s1 = site i+1
 //             (dm x 2 dr).  Site i <- Q (2 dl x k), site i+1 <- R P^T
 //             renormalised; info[2 slot] = ||theta||^2, info[2 slot + 1] = eps^2.
+//   CH_UPDATE_SVD  as CH_UPDATE with the truncated SVD instead of pivoted QR:
+//             site i <- U_k, site i+1 <- S_k V_k^H renormalised.
 struct ChainOp {
     int32_t kind;
     int32_t slot;
@@ -128,6 +130,7 @@ __device__ void ch_reflect(const double2* V, int len, double2 coef, double2* X, 
 struct ChLds {
     double red[4];
     ArgBest arg[4];
+    int flag;
 };
 
 // Householder QR of M (m x n, ld m) in place, k steps: R on and above the
@@ -283,6 +286,141 @@ __device__ void ch_update(const ChainOp* op, const ChainWs& w, double* info, ChL
     }
 }
 
+// One-sided (Hestenes) Jacobi on the columns of X (rx x cols, ld rx): pairs of
+// columns are rotated until every pair is orthogonal to working precision,
+// |x_p^H x_q| <= CH_JTOL ||x_p|| ||x_q||; the same unitary rotations are
+// applied to the columns of V (rv x cols, ld rv).  A column with
+// ||x||^2 <= floor2 counts as numerically zero and is not rotated (with more
+// columns than rows, or a rank-deficient X, such columns hold only rounding
+// noise, whose angles never settle).  A sweep visits every pair once in
+// round-robin order (cols/2 disjoint pairs per round, one group of lanes per
+// pair); at most CH_JSWEEPS sweeps.  Returns with a barrier.
+#define CH_JTOL 1e-14
+#define CH_JSWEEPS 60
+__device__ void ch_jacobi(double2* X, int rx, int cols, double2* V, int rv, double floor2, ChLds& L)
+{
+    if (cols < 2) return;
+    const int cp = cols + (cols & 1), npairs = cp / 2;
+    const int G = ch_group(npairs), gl = threadIdx.x % G, pi = threadIdx.x / G;
+    for (int sweep = 0; sweep < CH_JSWEEPS; ++sweep) {
+        if (threadIdx.x == 0) L.flag = 0;
+        __syncthreads();
+        for (int r = 0; r < cp - 1; ++r) {
+            int p = cp - 1, q = r;
+            if (pi > 0) {
+                p = (r + pi) % (cp - 1);
+                q = (r - pi + cp - 1) % (cp - 1);
+            }
+            if (p > q) {
+                const int t = p;
+                p = q;
+                q = t;
+            }
+            if (pi < npairs && q < cols) {
+                double2* xp = X + (int64_t)rx * p;
+                double2* xq = X + (int64_t)rx * q;
+                double a = 0.0, b = 0.0, gr = 0.0, gi = 0.0;
+                for (int i = gl; i < rx; i += G) {
+                    const double2 u = xp[i], v = xq[i];
+                    a += cabs2(u);
+                    b += cabs2(v);
+                    const double2 t = cmulc(u, v);   // conj(u) v
+                    gr += t.x;
+                    gi += t.y;
+                }
+                a = ch_group_sum(a, G);
+                b = ch_group_sum(b, G);
+                gr = ch_group_sum(gr, G);
+                gi = ch_group_sum(gi, G);
+                const double g = sqrt(gr * gr + gi * gi);
+                if (a > floor2 && b > floor2 && g > CH_JTOL * sqrt(a * b)) {
+                    // [x_p, x_q] <- [x_p, x_q] J, J = [[c, s e], [-s conj(e), c]],
+                    // e = gamma / |gamma|, t = s / c the smaller root of
+                    // t^2 + 2 zeta t - 1 = 0, zeta = (b - a) / (2 |gamma|)
+                    const double zeta = (b - a) / (2.0 * g);
+                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+                    const double2 e = make_double2(gr / g, gi / g);
+                    const double2 se = cscale(e, sn), sec = cscale(cconj(e), sn);
+                    for (int i = gl; i < rx; i += G) {
+                        const double2 u = xp[i], v = xq[i];
+                        xp[i] = csub(cscale(u, c), cmul(sec, v));
+                        xq[i] = cadd(cmul(se, u), cscale(v, c));
+                    }
+                    double2* vp = V + (int64_t)rv * p;
+                    double2* vq = V + (int64_t)rv * q;
+                    for (int i = gl; i < rv; i += G) {
+                        const double2 u = vp[i], v = vq[i];
+                        vp[i] = csub(cscale(u, c), cmul(sec, v));
+                        vq[i] = cadd(cmul(se, u), cscale(v, c));
+                    }
+                    if (gl == 0) L.flag = 1;
+                }
+            }
+            __syncthreads();
+        }
+        const int rotated = L.flag;
+        __syncthreads();   // every lane has read the flag before it is reset
+        if (!rotated) break;
+    }
+}
+
+// Truncated SVD update.  With X = theta^H (n x m) and V = I (m x m), Jacobi
+// gives X V = W with orthogonal columns, so theta = V W^H and the singular
+// values are the column norms of W.  The k largest (ties: the smaller
+// column) are kept: site i <- their columns of V (orthonormal whatever the
+// rank), site i+1 <- the matching rows of W^H scaled by 1/sqrt(kept);
+// eps^2 = the sum of the discarded squared column norms.
+template <typename T>
+__device__ void ch_update_svd(const ChainOp* op, const ChainWs& w, double* info, ChLds& L)
+{
+    const int dl = op->dl, dm = op->dm, dr = op->dr, k = op->k;
+    const int m = 2 * dl, n = 2 * dr;
+    T* A = (T*)op->s0;
+    T* B = (T*)op->s1;
+    ch_theta<T>(A, B, dl, dm, dr, op->g, w.M);
+    __syncthreads();
+    double s_all = 0.0;
+    for (int idx = threadIdx.x; idx < m * n; idx += CH_NT) s_all += cabs2(w.M[idx]);
+    s_all = block_sum256(s_all, L.red);
+    double2* X = w.P;   // n x m, ld n
+    for (int idx = threadIdx.x; idx < n * m; idx += CH_NT) {
+        const int i = idx % n, c = idx / n;
+        X[idx] = cconj(w.M[c + (int64_t)m * i]);
+    }
+    for (int idx = threadIdx.x; idx < m * m; idx += CH_NT)
+        w.Q[idx] = (idx % m == idx / m) ? make_double2(1.0, 0.0) : czero();
+    __syncthreads();
+    // columns below 1e-14 of ||theta||_F are numerically zero
+    ch_jacobi(X, n, m, w.Q, m, 1e-28 * s_all, L);
+    ch_colnorms(X, n, n, 0, m, w.nu);
+    __syncthreads();
+    for (int j = threadIdx.x; j < m; j += CH_NT) {
+        const double v = w.nu[j];
+        int rank = 0;
+        for (int i = 0; i < m; ++i) rank += (w.nu[i] > v || (w.nu[i] == v && i < j)) ? 1 : 0;
+        w.perm[rank] = j;
+    }
+    __syncthreads();
+    double s_eps = 0.0;
+    for (int r = k + (int)threadIdx.x; r < m; r += CH_NT) s_eps += w.nu[w.perm[r]];
+    s_eps = block_sum256(s_eps, L.red);
+    const double kept = s_all - s_eps;
+    const double sc = kept > 0.0 ? 1.0 / sqrt(kept) : 1.0;
+    for (int idx = threadIdx.x; idx < m * k; idx += CH_NT) {
+        const int i = idx % m, t = idx / m;
+        A[idx] = from_d<T>(w.Q[i + (int64_t)m * w.perm[t]]);
+    }
+    for (int idx = threadIdx.x; idx < k * n; idx += CH_NT) {
+        const int t = idx % k, c = idx / k;
+        B[idx] = from_d<T>(cscale(cconj(X[c + (int64_t)n * w.perm[t]]), sc));
+    }
+    if (threadIdx.x == 0) {
+        info[2 * op->slot] = s_all;
+        info[2 * op->slot + 1] = s_eps;
+    }
+}
+
 template <typename T>
 __device__ void ch_move_right(const ChainOp* op, const ChainWs& w, ChLds& L)
 {
@@ -344,6 +482,7 @@ __global__ __launch_bounds__(CH_NT) void k_chain(const ChainOp* ops, int nops, C
         const ChainOp* op = ops + o;
         const int kind = op->kind;
         if (kind == CH_UPDATE) ch_update<T>(op, w, info, L);
+        else if (kind == CH_UPDATE_SVD) ch_update_svd<T>(op, w, info, L);
         else if (kind == CH_RIGHT) ch_move_right<T>(op, w, L);
         else ch_move_left<T>(op, w, L);
         __syncthreads();

@@ -74,6 +74,7 @@ struct mps_ctx {
     double* chain_info;    // device: ||theta||^2, eps^2 per chained update
     int64_t chain_cap;     // capacity of chain_ops (entries)
     int64_t dmax;          // largest bond dimension the state can reach
+    int32_t trunc;         // mps_truncation of the two-site updates
 };
 
 static int64_t max_bond(int n, int b, int64_t chi)
@@ -197,6 +198,7 @@ extern "C" mps_status mps_create(const mps_config* cfg, void* dev_arena, int64_t
     c->log_fid = 0.0;
     c->poisoned = false;
     c->has_net = false;
+    c->trunc = MPS_TRUNC_QRCP;
     mps_status s = c->prec == MPS_FP64 ? ctx_init_sites<double2>(c) : ctx_init_sites<float2>(c);
     if (s != MPS_OK) {
         delete c;
@@ -355,7 +357,7 @@ static mps_status ctx_run_gates(mps_ctx* c, int64_t ng, const int32_t* idx, cons
             if (f) ops.push_back(op);
         }
         ChainOp op = {};
-        op.kind = CH_UPDATE;
+        op.kind = c->trunc == MPS_TRUNC_SVD ? CH_UPDATE_SVD : CH_UPDATE;
         op.dl = (int32_t)dims[i];
         op.dm = (int32_t)dims[i + 1];
         op.dr = (int32_t)dims[i + 2];
@@ -373,6 +375,13 @@ static mps_status ctx_run_gates(mps_ctx* c, int64_t ng, const int32_t* idx, cons
         centre = i + 1;
     }
     if ((int64_t)ops.size() > c->chain_cap) return fail(MPS_EINVAL, "gates: too many chained operations");
+    if (c->trunc == MPS_TRUNC_SVD)
+        for (const Step& st : steps)
+            if (st.kind == CH_UPDATE && !st.fused)
+                return fail(MPS_EINVAL,
+                            "gates: SVD truncation runs only inside small-bond chains (gate %d on bond %d exceeds "
+                            "bond dimension %lld)",
+                            st.t, st.s, (long long)half);
     if (!ops.empty())
         HIPCHK(hipMemcpyAsync(c->chain_ops, ops.data(), sizeof(ChainOp) * ops.size(), hipMemcpyHostToDevice, c->st),
                "chain upload");
@@ -460,7 +469,7 @@ static mps_status ctx_run_gates(mps_ctx* c, int64_t ng, const int32_t* idx, cons
                 u.refreshes = 0;
                 u.window_misses = 0;
                 u.learned_err_sq = -1.0;
-                u.qrcp_err_sq = e2;
+                u.qrcp_err_sq = c->trunc == MPS_TRUNC_SVD ? -1.0 : e2;
             }
         }
         if (!finite) return fail(MPS_ENUMERIC, "chained update: non-finite theta");
@@ -469,6 +478,17 @@ static mps_status ctx_run_gates(mps_ctx* c, int64_t ng, const int32_t* idx, cons
     }
     for (int64_t t = 0; t < ng; ++t)
         if (retained[t] > 0) c->log_fid += log(retained[t]);
+    return MPS_OK;
+}
+
+extern "C" mps_status mps_set_truncation(mps_ctx* ctx, int32_t mode)
+{
+    if (!ctx) return fail(MPS_EINVAL, "mps_set_truncation: NULL context");
+    if (mode != MPS_TRUNC_QRCP && mode != MPS_TRUNC_SVD)
+        return fail(MPS_EINVAL, "mps_set_truncation: unknown mode %d", (int)mode);
+    if (mode == MPS_TRUNC_SVD && ctx->cfg.pivot != MPS_PIVOT_QRCP)
+        return fail(MPS_EINVAL, "mps_set_truncation: SVD truncation needs pivot = MPS_PIVOT_QRCP");
+    ctx->trunc = mode;
     return MPS_OK;
 }
 

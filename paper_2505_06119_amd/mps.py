@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libmpsgpu.so")
 
 MPS_FP64, MPS_MIXED = 0, 1
 MPS_PIVOT_QRCP, MPS_PIVOT_LEARNED = 0, 1
+MPS_TRUNC_QRCP, MPS_TRUNC_SVD = 0, 1
 STATUS = {0: "MPS_OK", 1: "MPS_EINVAL", 2: "MPS_ENOMEM", 3: "MPS_EDEVICE", 4: "MPS_ENUMERIC", 5: "MPS_ESTATE"}
 
 
@@ -104,6 +105,8 @@ def lib() -> ctypes.CDLL:
     L.mps_set_tuning.argtypes = [i32, i32]
     L.mps_set_small_bond_limit.restype = i32
     L.mps_set_small_bond_limit.argtypes = [i32]
+    L.mps_set_truncation.restype = i32
+    L.mps_set_truncation.argtypes = [ctypes.c_void_p, i32]
     L.mps_profile.restype = i32
     L.mps_profile.argtypes = [ctypes.c_int]
     L.mps_profile_read.restype = i32
@@ -368,6 +371,10 @@ class MPS:
             self.close()
         except Exception:
             pass
+
+    def set_truncation(self, mode: int):
+        """MPS_TRUNC_QRCP or MPS_TRUNC_SVD for the later updates (mps_set_truncation)."""
+        _check(lib().mps_set_truncation(self._h, mode))
 
     def set_pivot_network(self, cfg: LearnedCfg):
         self._lcfg = cfg

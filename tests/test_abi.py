@@ -107,6 +107,13 @@ def test_small_bond_limit_validation(L):
         assert L.mps_set_small_bond_limit(v) == 0, v
 
 
+def test_set_truncation_null_context(L):
+    from paper_2505_06119_amd import mps
+    for mode in (0, 1, 2):
+        assert L.mps_set_truncation(None, mode) == 1, mode
+        assert "mps_set_truncation" in mps.last_error()
+
+
 def test_tuning_validation(L):
     from paper_2505_06119_amd import mps
     for pw, win in ((12, -1), (32, 48), (32, -2), (0, 513), (128, 0)):
