@@ -33,6 +33,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -235,6 +237,69 @@ def layer_chains(M, torch, synth):
     return out
 
 
+def _statevector_gpu(torch, n, layers):
+    """Exact statevector of a gate sequence from |0...0> (complex128, on the
+    GPU; site 0 is the most significant qubit)."""
+    psi = torch.zeros((2,) * n, dtype=torch.complex128, device="cuda")
+    psi[(0,) * n] = 1.0
+    for layer in layers:
+        for i, g in layer:
+            g4 = torch.as_tensor(np.asarray(g, dtype=np.complex128).reshape(2, 2, 2, 2), device="cuda")
+            psi = torch.tensordot(g4, psi, dims=([2, 3], [i, i + 1]))
+            psi = torch.movedim(psi, (0, 1), (i, i + 1))
+    return psi.reshape(-1)
+
+
+def _mps_statevector(torch, sites):
+    t = torch.as_tensor(sites[0], device="cuda")
+    for s in sites[1:]:
+        t = torch.tensordot(t, torch.as_tensor(s, device="cuda"), dims=([t.dim() - 1], [0]))
+    return t.reshape(-1)
+
+
+def truncation_compare(M, torch, synth):
+    """Pivoted-QR against SVD truncation (Table III) on the same truncating
+    circuits, every operation inside the small-bond chains in FP64: gates/s
+    (median of 3 runs after a warm-up run), the norm fidelity Fbar the
+    library bookkeeps, the overlap fidelity F with the exact statevector and
+    their difference Fbar - F (Sec. III-E)."""
+    cases = [("12 qubits, brickwork depth 12, Haar 4x4 gates, chi cap 16 (truncating)", 12, 12, 16),
+             ("16 qubits, brickwork depth 12, Haar 4x4 gates, chi cap 32 (truncating)", 16, 12, 32)]
+    out = []
+    M.set_small_bond_limit(64)
+    for desc, n, depth, chi in cases:
+        layers = synth.brickwork(synth.rng(400), n, depth)
+        gates = sum(len(layer) for layer in layers)
+        exact = _statevector_gpu(torch, n, layers)
+        row = {"workload": desc, "gates": gates}
+        for mode, name in ((M.MPS_TRUNC_QRCP, "qrcp"), (M.MPS_TRUNC_SVD, "svd")):
+            times = []
+            for rep in range(4):
+                st = M.MPS(n, chi, M.MPS_FP64)
+                st.set_truncation(mode)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st.apply_layers(layers)
+                torch.cuda.synchronize()
+                if rep > 0:
+                    times.append(time.perf_counter() - t0)
+                if rep < 3:
+                    st.close()
+            dt = sorted(times)[len(times) // 2]
+            fbar = float(np.exp(st.log_norm_fidelity()))
+            sv = _mps_statevector(torch, st.sites())
+            f = float((torch.abs(torch.vdot(exact, sv)) ** 2 / torch.vdot(sv, sv).real).item())
+            st.close()
+            row[name] = {"gates_per_s": gates / dt, "norm_fidelity": fbar, "overlap_fidelity": f,
+                         "fbar_minus_f": fbar - f}
+        row["svd_time_over_qrcp"] = row["qrcp"]["gates_per_s"] / row["svd"]["gates_per_s"]
+        log(f"[bench] truncation: {desc}: QR {row['qrcp']['gates_per_s']:.0f} gates/s F={row['qrcp']['overlap_fidelity']:.4f}"
+            f" Fbar-F={row['qrcp']['fbar_minus_f']:+.2e}; SVD {row['svd']['gates_per_s']:.0f} gates/s"
+            f" F={row['svd']['overlap_fidelity']:.4f} Fbar-F={row['svd']['fbar_minus_f']:+.2e}")
+        out.append(row)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -379,6 +444,8 @@ def main():
     if not args.no_layers:
         log("[bench] circuit layers with and without small-bond chains")
         res["layer_chains"] = layer_chains(M, torch, synth)
+        log("[bench] pivoted QR against SVD truncation on small-bond circuits")
+        res["truncation_compare"] = truncation_compare(M, torch, synth)
     if not args.no_cpu_baseline:
         log(f"[bench] timing the CPU oracle on a chi={args.cpu_sample_chi} sample")
         res["cpu_baseline"] = cpu_baseline(args.cpu_sample_chi, chi, args.seed)
