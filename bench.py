@@ -300,6 +300,37 @@ def truncation_compare(M, torch, synth):
     return out
 
 
+def routed_grid(M, torch, synth):
+    """A grid random circuit embedded in the chain (5x8 qubits, 14 cycles of
+    single-qubit gates and fSim couplers, ABCDCDAB, re-embedded between the
+    row and column snakes by SWAP networks), mixed precision, chi cap 128:
+    the circuit as generated against the same circuit with consecutive
+    same-bond operations fused (routing.fuse_layers).  Wall time of one run
+    from the product state (the library is warm by then), and the norm
+    fidelity."""
+    from paper_2505_06119_amd import routing
+    rows, cols, cycles, chi = 5, 8, 14, 128
+    layers, _ = synth.grid_rcs(synth.rng(500), rows, cols, cycles)
+    out = {"workload": f"{rows}x{cols} grid random circuit, {cycles} cycles (ABCDCDAB, fSim), chain re-embedded "
+                       f"by SWAP networks, chi cap {chi}, mixed"}
+    for name, ls in (("as_generated", layers), ("fused", routing.fuse_layers(layers))):
+        st = M.MPS(rows * cols, chi, M.MPS_MIXED)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.apply_layers(ls)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        fbar = float(np.exp(st.log_norm_fidelity()))
+        st.close()
+        n_up = sum(len(layer) for layer in ls)
+        out[name] = {"updates": n_up, "seconds": dt, "updates_per_s": n_up / dt, "norm_fidelity": fbar}
+    out["fused_speedup"] = out["as_generated"]["seconds"] / out["fused"]["seconds"]
+    log(f"[bench] routed grid: {out['as_generated']['updates']} updates in {out['as_generated']['seconds']:.2f} s "
+        f"(Fbar {out['as_generated']['norm_fidelity']:.3e}); fused {out['fused']['updates']} in "
+        f"{out['fused']['seconds']:.2f} s (Fbar {out['fused']['norm_fidelity']:.3e})")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -446,6 +477,8 @@ def main():
         res["layer_chains"] = layer_chains(M, torch, synth)
         log("[bench] pivoted QR against SVD truncation on small-bond circuits")
         res["truncation_compare"] = truncation_compare(M, torch, synth)
+        log("[bench] grid random circuit with and without same-bond fusion")
+        res["routed_grid"] = routed_grid(M, torch, synth)
     if not args.no_cpu_baseline:
         log(f"[bench] timing the CPU oracle on a chi={args.cpu_sample_chi} sample")
         res["cpu_baseline"] = cpu_baseline(args.cpu_sample_chi, chi, args.seed)

@@ -17,7 +17,9 @@
 //     column norms recomputed exactly after every step (ties: the smaller
 //     original column index);
 //   * Q is accumulated backwards from the reflectors; R P^T is scattered into
-//     the right site and scaled by 1/sqrt(||theta||^2 - eps^2).
+//     the right site and scaled by 1/sqrt(||theta||^2 - eps^2);
+//   * with SVD truncation (Table III) the update instead runs one-sided
+//     Jacobi on theta^H and keeps the k largest singular values (below).
 //
 // The bond dimension every operation produces follows from the shapes alone
 // (k = min(chi_cap, m, n) for an update, min(rows, cols) for a centre move),

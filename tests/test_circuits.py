@@ -85,6 +85,36 @@ def test_grid_rcs_gpu_truncated_vs_oracle(prec):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("prec", [0, 1])
+def test_grid_rcs_gpu_fused_vs_oracle(prec):
+    """The same circuit with consecutive same-bond operations fused
+    (routing.fuse_layers): chi cap 64 equals brute force of the unfused
+    circuit; chi cap 16 follows the oracle MPS run on the fused circuit."""
+    from paper_2505_06119_amd import mps, routing
+    print(f"case grid rcs fused prec={prec}", flush=True)
+    layers, _ = synth.grid_rcs(synth.rng(6), 3, 4, 8)
+    fused = routing.fuse_layers(layers)
+    tol = 1e-10 if prec == 0 else 1e-4
+    st = mps.MPS(12, 64, prec)
+    st.apply_layers(fused)
+    ref = oracle.brute_force(12, layers)
+    sv = oracle.statevector(st.sites()) * np.sqrt(np.exp(st.log_norm_fidelity()))
+    assert np.max(np.abs(sv - ref)) <= tol * 10 * np.max(np.abs(ref))
+    st = mps.MPS(12, 16, prec)
+    st.apply_layers(fused)
+    om = oracle.MPS(synth.product_state_sites(12), chi_cap=16)
+    om.apply_layers(fused)
+    f_o = oracle.norm_fidelity(om.sites)
+    f_g = np.exp(st.log_norm_fidelity())
+    assert f_o < 0.9999
+    assert abs(f_g - f_o) <= tol * 10 * f_o
+    sv_o = oracle.statevector(om.sites)
+    sv_g = oracle.statevector(st.sites()) * np.sqrt(f_g)
+    fid = abs(np.vdot(sv_o, sv_g)) ** 2 / (np.vdot(sv_o, sv_o).real * np.vdot(sv_g, sv_g).real)
+    assert 1 - fid <= tol * 10
+
+
+@pytest.mark.gpu
 def test_qpe_gpu_exact_phase():
     from paper_2505_06119_amd import mps
     print("case qpe", flush=True)
