@@ -23,8 +23,9 @@ Pieces and the passages they follow (arXiv 2505.06119):
 * ``amplitude``         -- Eq. (2): product of the site matrices selected by
   the bits.
 * ``overlap``           -- Sec. III-E overlap fidelity, by transfer matrices.
-* ``statevector`` / ``brute_force`` -- Sec. II-A statevector and gates, for
-  exact comparison on small registers.
+* ``statevector`` / ``brute_force`` / ``brute_force_ops`` -- Sec. II-A
+  statevector and gates (on neighbouring chain sites, or on any pair of
+  logical qubits), for exact comparison on small registers.
 
 Where the paper is silent the oracle takes these readings: site 0 is the most
 significant qubit; the gate's row index is 2a'+b' with a on the lower site;
@@ -258,6 +259,23 @@ def statevector(sites) -> np.ndarray:
     for s in sites[1:]:
         t = np.tensordot(t, s, axes=(t.ndim - 1, 0))
     return t.reshape(-1)
+
+
+def brute_force_ops(n: int, ops) -> np.ndarray:
+    """Apply a circuit on logical qubits to |0...0> (Sec. II-A): ops are
+    ("1q", q, U 2x2) or ("2q", a, b, U 4x4) with row index 2 a' + b'; qubit 0
+    is the most significant bit."""
+    psi = np.zeros((2,) * n, dtype=np.complex128)
+    psi[(0,) * n] = 1.0
+    for op in ops:
+        if op[0] == "1q":
+            _, q, u = op
+            psi = np.moveaxis(np.tensordot(np.asarray(u, dtype=np.complex128), psi, axes=([1], [q])), 0, q)
+        else:
+            _, a, b, u = op
+            g4 = np.asarray(u, dtype=np.complex128).reshape(2, 2, 2, 2)
+            psi = np.moveaxis(np.tensordot(g4, psi, axes=([2, 3], [a, b])), [0, 1], [a, b])
+    return psi.reshape(-1)
 
 
 def brute_force(n: int, layers, bits=None) -> np.ndarray:

@@ -1,4 +1,5 @@
-"""Fusion of consecutive two-site operations on the same bond (host side).
+"""Routing of circuits onto the MPS chain and fusion of same-bond operations
+(host side).
 
 A routed circuit on an MPS chain (Sec. III-C, gates applied to neighbouring
 sites; Sec. III-D.2, 2D circuits embedded in the chain and re-embedded by
@@ -11,6 +12,13 @@ no operation has touched sites b or b+1 in between: the 4x4 matrices
 multiply (later one on the left) and one update replaces two.  Without
 truncation the state is unchanged; with truncation there are fewer
 truncations, at different points of the circuit.
+
+route_lazy places a circuit on logical qubits onto the chain on demand
+instead of re-embedding the whole register between fixed orders: a
+two-qubit gate on qubits at distance d moves one of them d - 1 sites by SWAP
+updates and leaves it there, and single-qubit gates wait on their qubit and
+join its next two-qubit gate (the approach the paper's state-of-the-art
+comparison, Sec. IV, credits to quimb as the more robust one).
 """
 from __future__ import annotations
 
@@ -57,3 +65,44 @@ def pack_layers(ops):
 def fuse_layers(layers):
     """fuse() over the layers' sequential order, packed back into layers."""
     return pack_layers(fuse(flatten(layers)))
+
+
+_SWAP = np.array([[1, 0, 0, 0], [0, 0, 1, 0], [0, 1, 0, 0], [0, 0, 0, 1]], dtype=np.complex128)
+_I2 = np.eye(2, dtype=np.complex128)
+
+
+def route_lazy(n: int, ops, order):
+    """Place ("1q", q, U) / ("2q", a, b, U) operations on logical qubits onto
+    an n-site chain whose position p holds qubit order[p].
+
+    A two-qubit gate whose qubits are not neighbours first moves b towards a
+    by SWAP updates; b stays where it arrives.  The gate, with the pending
+    single-qubit gates of a and b folded in (U kron(u_a, u_b)) and re-oriented
+    when b sits left of a (SWAP U SWAP), is one update on their bond.  Pending
+    single-qubit gates left at the end become updates with a neighbour.
+    Returns the sequential (bond, 4x4) list and the final order."""
+    order = list(order)
+    pos = {q: p for p, q in enumerate(order)}
+    pend = {}
+    out = []
+    for op in ops:
+        if op[0] == "1q":
+            _, q, u = op
+            pend[q] = np.asarray(u, dtype=np.complex128) @ pend.get(q, _I2)
+            continue
+        _, a, b, u = op
+        while abs(pos[a] - pos[b]) > 1:
+            pb = pos[b]
+            pn = pb - 1 if pos[a] < pb else pb + 1
+            qn = order[pn]
+            out.append((min(pb, pn), _SWAP))
+            order[pb], order[pn] = qn, b
+            pos[qn], pos[b] = pb, pn
+        g = np.asarray(u, dtype=np.complex128) @ np.kron(pend.pop(a, _I2), pend.pop(b, _I2))
+        if pos[a] > pos[b]:
+            g = _SWAP @ g @ _SWAP
+        out.append((min(pos[a], pos[b]), g))
+    for q in sorted(pend):
+        p = pos[q]
+        out.append((p, np.kron(pend[q], _I2)) if p + 1 < n else (p - 1, np.kron(_I2, pend[q])))
+    return out, order

@@ -348,6 +348,23 @@ def grid_rcs(r: np.random.Generator, rows: int, cols: int, cycles: int, patterns
     return layers, order
 
 
+def grid_rcs_logical(r: np.random.Generator, rows: int, cols: int, cycles: int, patterns: str = "ABCDCDAB"):
+    """The circuit of grid_rcs on logical qubits (row-major labels), before
+    any embedding: ("1q", q, U) and ("2q", a, b, fSim) operations.  Draws the
+    same random numbers as grid_rcs, so both describe the same circuit."""
+    n = rows * cols
+    singles = [gate_sqrt_x(), gate_sqrt_y(), gate_sqrt_w()]
+    ops = []
+    for c in range(cycles):
+        pat = patterns[c % len(patterns)]
+        choice = r.integers(0, 3, size=n)
+        for q in range(n):
+            ops.append(("1q", q, singles[choice[q]]))
+        for a, b in grid_couplers(rows, cols, pat):
+            ops.append(("2q", a, b, gate_fsim()))
+    return ops
+
+
 def qpe_circuit(t: int, alphas, target_init: str = "plus"):
     """Quantum phase estimation on a chain: t counting qubits (positions
     0..t-1, position 0 the most significant) and one target qubit per angle

@@ -60,3 +60,54 @@ def test_fused_oracle_mps_exact():
     m = oracle.MPS(synth.product_state_sites(12), chi_cap=64)
     m.apply_layers(fused)
     np.testing.assert_allclose(oracle.statevector(m.sites), oracle.brute_force(12, layers), atol=1e-12)
+
+
+def _to_logical(psi_chain, order):
+    n = len(order)
+    pos = {q: p for p, q in enumerate(order)}
+    return np.transpose(psi_chain.reshape((2,) * n), [pos[q] for q in range(n)]).reshape(-1)
+
+
+@pytest.mark.parametrize("rows,cols,cycles,seed", [(3, 4, 8, 1), (2, 5, 10, 2)])
+def test_grid_rcs_logical_is_the_embedded_circuit(rows, cols, cycles, seed):
+    """grid_rcs (chain positions, SWAP re-embedding) and grid_rcs_logical
+    (logical qubits) describe the same circuit."""
+    layers, order = synth.grid_rcs(synth.rng(seed), rows, cols, cycles)
+    ops = synth.grid_rcs_logical(synth.rng(seed), rows, cols, cycles)
+    n = rows * cols
+    np.testing.assert_allclose(_to_logical(oracle.brute_force(n, layers), order), oracle.brute_force_ops(n, ops),
+                               atol=1e-12)
+
+
+@pytest.mark.parametrize("rows,cols,cycles,seed", [(3, 4, 8, 1), (2, 5, 10, 2), (3, 3, 12, 3)])
+def test_lazy_routing_same_state(rows, cols, cycles, seed):
+    ops = synth.grid_rcs_logical(synth.rng(seed), rows, cols, cycles)
+    n = rows * cols
+    row_order, _ = synth.grid_snakes(rows, cols)
+    chain, order = routing.route_lazy(n, ops, row_order)
+    assert sorted(order) == list(range(n))
+    layers = routing.pack_layers(routing.fuse(chain))
+    np.testing.assert_allclose(_to_logical(oracle.brute_force(n, layers), order), oracle.brute_force_ops(n, ops),
+                               atol=1e-12)
+
+
+def test_lazy_routing_reorients_gates():
+    """A non-symmetric gate on (a, b) with b left of a is conjugated by SWAP."""
+    r = synth.rng(8)
+    g = synth.haar_unitary(r, 4)
+    u = synth.haar_unitary(r, 2)
+    ops = [("1q", 2, u), ("2q", 2, 0, g), ("2q", 3, 0, g)]
+    chain, order = routing.route_lazy(4, ops, [0, 1, 2, 3])
+    layers = routing.pack_layers(chain)
+    np.testing.assert_allclose(_to_logical(oracle.brute_force(4, layers), order), oracle.brute_force_ops(4, ops),
+                               atol=1e-12)
+
+
+def test_lazy_routing_oracle_mps_exact():
+    ops = synth.grid_rcs_logical(synth.rng(9), 3, 4, 8)
+    row_order, _ = synth.grid_snakes(3, 4)
+    chain, order = routing.route_lazy(12, ops, row_order)
+    m = oracle.MPS(synth.product_state_sites(12), chi_cap=64)
+    m.apply_layers(routing.pack_layers(routing.fuse(chain)))
+    np.testing.assert_allclose(_to_logical(oracle.statevector(m.sites), order), oracle.brute_force_ops(12, ops),
+                               atol=1e-12)
