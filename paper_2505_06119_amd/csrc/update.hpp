@@ -581,10 +581,9 @@ static void window_setup(UpdateWs<T>& w, hipStream_t st, int64_t p0, bool save)
 // Right-looking pivot steps p0 .. p0+nsteps-1 inside the window (k_window_step),
 // then the window's columns in their final order: pivots first, in step order.
 template <typename T>
-static void run_window_steps(UpdateWs<T>& w, hipStream_t st, int64_t p0, int64_t nsteps)
+static void run_window_steps(UpdateWs<T>& w, hipStream_t st, int64_t p0, int64_t nsteps, int W, int fixed = 0)
 {
     QrcpDev<T>& d = w.d;
-    const int W = w.win;
     // sampled profiling times the whole run with one event pair
     hipEvent_t er = prof_begin_run(st);
     double rbytes = 0.0, rflops = 0.0;
@@ -593,7 +592,7 @@ static void run_window_steps(UpdateWs<T>& w, hipStream_t st, int64_t p0, int64_t
         hipEvent_t ec = g_prof.stride > 1 ? nullptr : prof_begin(st, PK_STEP_C);
         hipLaunchKernelGGL((k_window_step<T>), dim3((unsigned)W), dim3(WSTEP_NT), 0, st, d, j, p0, (int)jj,
                            (const ArgBest*)(w.wcp + (jj & 1) * QR_WIN_MAX), w.wcp + ((jj + 1) & 1) * QR_WIN_MAX,
-                           w.wpiv, w.vbuf, w.wstep, w.Gbuf, (int)UNGQR_NB);
+                           w.wpiv, w.vbuf, w.wstep, w.Gbuf, (int)UNGQR_NB, fixed);
         // algorithmic traffic of one step: the window right of the pivot read and written once
         const double cols = (double)(p0 + W - j - 1), rows = (double)(d.m - j);
         prof_end(ec, st, PK_STEP_C, 2.0 * sizeof(T) * rows * cols, 16.0 * rows * cols);
@@ -604,10 +603,9 @@ static void run_window_steps(UpdateWs<T>& w, hipStream_t st, int64_t p0, int64_t
 }
 
 template <typename T>
-static void window_reorder(UpdateWs<T>& w, hipStream_t st, int64_t p0, int nbe)
+static void window_reorder(UpdateWs<T>& w, hipStream_t st, int64_t p0, int nbe, int W)
 {
     QrcpDev<T>& d = w.d;
-    const int W = w.win;
     hipEvent_t ew = prof_begin(st);
     hipLaunchKernelGGL(k_window_order, dim3(1), dim3(1024), 0, st, (const int32_t*)w.wpiv, nbe, p0, W, w.worder);
     // at most 2 nbe columns move
@@ -617,6 +615,30 @@ static void window_reorder(UpdateWs<T>& w, hipStream_t st, int64_t p0, int nbe)
     hipLaunchKernelGGL((k_window_gather<T>), grid, dim3(256), 0, st, d, (const int32_t*)w.worder, p0,
                        (const T*)w.vbuf, w.wtmp, w.wtnu, w.wtnuref, w.wtperm, 1);
     prof_end(ew, st, PK_WINDOW, (double)sizeof(T) * 8.0 * (double)d.m * nbe, 0.0);
+}
+
+// Unpivoted Householder QR with every column in one window (n <= WSTEP_NT,
+// m <= WSTEP_NT * WSTEP_RPT): per panel of nb columns, one k_window_step
+// launch per column in position order (each step applies its reflector to
+// every remaining column, so no trailing update is left), then the panel's
+// reflectors are written into place.  Half the launches of the delayed-update
+// steps, for the centre moves of bonds up to a few hundred.
+template <typename T>
+static hipError_t run_window_fixed(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats)
+{
+    QrcpDev<T>& d = w.d;
+    const int64_t n = d.n, k = d.k;
+    const int nb = w.nb > 0 && w.nb < QR_NBMAX ? w.nb : 32;
+    for (int64_t p0 = 0; p0 < k; p0 += nb) {
+        const int64_t nsteps = (p0 + nb < k ? p0 + nb : k) - p0;
+        const int W = (int)(n - p0);
+        hipLaunchKernelGGL(k_ctl_panel, dim3(1), dim3(64), 0, st, d.ctl, (int32_t)p0);
+        hipLaunchKernelGGL(k_fixed_partials, dim3(1), dim3(1024), 0, st, w.wcp, p0, W);
+        run_window_steps<T>(w, st, p0, nsteps, W, 1);
+        window_reorder<T>(w, st, p0, (int)nsteps, W);
+        if (stats) stats->panels++;
+    }
+    return hipGetLastError();
 }
 
 // One candidate-window panel at p0 (see window.hpp).  On return *jend is the
@@ -639,7 +661,7 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
     window_setup<T>(w, st, p0, true);
     prof_end(ew, st, PK_WINDOW, (double)sizeof(T) * 4.0 * (double)m * W, 0.0);
     hipLaunchKernelGGL(k_ctl_panel, dim3(1), dim3(64), 0, st, d.ctl, (int32_t)p0);
-    if (right) run_window_steps<T>(w, st, p0, nsteps);
+    if (right) run_window_steps<T>(w, st, p0, nsteps, W);
     else run_panel_steps<T>(d, st, p0, nsteps, cend, true, 1);
     int32_t hctl[CTL_COUNT];
     hipError_t e = read_ctl<T>(d, st, hctl);
@@ -653,7 +675,7 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
     }
     int nbe = (int)(jend - p0);
     bool refresh = hctl[CTL_STOP] != 0;
-    if (right) window_reorder<T>(w, st, p0, nbe);
+    if (right) window_reorder<T>(w, st, p0, nbe, W);
 
     // block reflector of the panel and the R rows of the outside columns
     const T* V = d.A + p0 + d.lda * p0;
@@ -730,7 +752,7 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
         window_setup<T>(w, st, p0, false);   // same window, no swaps left: restores the first partial
         prof_end(er, st, PK_WINDOW, (double)sizeof(T) * 2.0 * (double)m * W, 0.0);
         hipLaunchKernelGGL(k_ctl_panel, dim3(1), dim3(64), 0, st, d.ctl, (int32_t)p0);
-        if (right) run_window_steps<T>(w, st, p0, tstar);
+        if (right) run_window_steps<T>(w, st, p0, tstar, W);
         else run_panel_steps<T>(d, st, p0, tstar, cend, true, 1);
         e = read_ctl<T>(d, st, hctl);
         if (e != hipSuccess) return e;
@@ -739,7 +761,7 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
                     tstar, (int)(hctl[CTL_JDONE] - p0), (long long)m, (long long)n, (long long)k);
             return hipErrorUnknown;
         }
-        if (right) window_reorder<T>(w, st, p0, tstar);
+        if (right) window_reorder<T>(w, st, p0, tstar, W);
         nbe = tstar;
         jend = p0 + tstar;
         if (stats) stats->window_misses++;
@@ -783,7 +805,13 @@ static hipError_t run_qrcp(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats, int
 {
     QrcpDev<T>& d = w.d;
     g_qr_diag[0] = 0;
-    if (!d.pivoting) return run_blocked_fixed<T>(w, st, stats);
+    if (!d.pivoting) {
+        // the a10 trailing norm is only needed when the factorisation truncates
+        const bool trunc = d.m > d.k && d.n > d.k;
+        if (!trunc && d.n <= WSTEP_NT && d.m <= (int64_t)WSTEP_NT * WSTEP_RPT && d.n <= QR_WIN_MAX)
+            return run_window_fixed<T>(w, st, stats);
+        return run_blocked_fixed<T>(w, st, stats);
+    }
     const int64_t m = d.m, n = d.n, k = d.k;
     const int nb = w.nb;
     int64_t j = 0;
@@ -796,6 +824,30 @@ static hipError_t run_qrcp(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats, int
             if (e != hipSuccess) return e;
             j = jend;
             continue;
+        }
+        if (w.win > 0 && n - p0 <= WSTEP_NT && n - p0 <= QR_WIN_MAX && m - p0 <= (int64_t)WSTEP_NT * WSTEP_RPT) {
+            // every remaining column fits one window: right-looking steps over
+            // all of them keep every norm exact, so there is nothing outside to
+            // replay against and every later panel fits as well
+            for (int64_t q0 = p0; q0 < k; q0 += nb) {
+                const int64_t nsteps = (q0 + nb < k ? q0 + nb : k) - q0;
+                const int W = (int)(n - q0);
+                hipLaunchKernelGGL(k_ctl_panel, dim3(1), dim3(64), 0, st, d.ctl, (int32_t)q0);
+                hipLaunchKernelGGL((k_nu_partials<T>), dim3(1), dim3(1024), 0, st, d, w.wcp, q0, W);
+                run_window_steps<T>(w, st, q0, nsteps, W);
+                window_reorder<T>(w, st, q0, (int)nsteps, W);
+                if (stats) stats->panels++;
+            }
+            int32_t hctl[CTL_COUNT];
+            hipError_t e = read_ctl<T>(d, st, hctl);
+            if (e != hipSuccess) return e;
+            if (hctl[CTL_JDONE] != k) {
+                qr_diag("all-column window panels from p0=%lld ended at step %d of %lld (m=%lld n=%lld)",
+                        (long long)p0, (int)hctl[CTL_JDONE], (long long)k, (long long)m, (long long)n);
+                return hipErrorUnknown;
+            }
+            j = k;
+            break;
         }
         if (nparts == 0) {
             // the previous panel left no partials: take them from the norms

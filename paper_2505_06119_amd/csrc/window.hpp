@@ -531,9 +531,13 @@ __device__ __forceinline__ void block_sum_ws3(double& a, double& b, double& c, d
     c = sc;
 }
 
+// fixed != 0: unpivoted QR in column order (a centre move).  The partials
+// then carry W - b instead of the norm, so the live column of smallest
+// position wins every argmax (seeded by k_fixed_partials).
 template <typename T>
 __global__ __launch_bounds__(WSTEP_NT) void k_window_step(QrcpDev<T> d, int64_t j, int64_t p0, int jj, const ArgBest* cin,
-                                                      ArgBest* cout, int32_t* wpiv, T* vbuf, int32_t* wstep, T* gbuf, int ldg)
+                                                      ArgBest* cout, int32_t* wpiv, T* vbuf, int32_t* wstep, T* gbuf, int ldg,
+                                                      int fixed)
 {
     __shared__ double s_red[3 * WSTEP_NW];
     __shared__ ArgBest s_arg[WSTEP_NW];
@@ -676,10 +680,39 @@ __global__ __launch_bounds__(WSTEP_NT) void k_window_step(QrcpDev<T> d, int64_t 
         d.nu[c] = nn;
         (void)nuref_c;
         ArgBest mine;
-        mine.val = nn;
+        mine.val = fixed ? (double)(W - b) : nn;
         mine.key = key_c;
         mine.slot = (int32_t)c;
         cout[b] = mine;
+    }
+}
+
+// First partials of a pivoted panel whose window is every remaining column
+// (one per column, from the current norms).  One block of W <= 1024 threads.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_nu_partials(QrcpDev<T> d, ArgBest* cp, int64_t p0, int W)
+{
+    const int b = threadIdx.x;
+    if (b < W) {
+        ArgBest a;
+        a.val = d.nu[p0 + b];
+        a.key = d.perm[p0 + b];
+        a.slot = (int32_t)(p0 + b);
+        cp[b] = a;
+    }
+}
+
+// First partials of an unpivoted window panel: column p0 + b gets priority
+// W - b.  One block of W <= 1024 threads.
+__global__ __launch_bounds__(1024) void k_fixed_partials(ArgBest* cp, int64_t p0, int W)
+{
+    const int b = threadIdx.x;
+    if (b < W) {
+        ArgBest a;
+        a.val = (double)(W - b);
+        a.key = b;
+        a.slot = (int32_t)(p0 + b);
+        cp[b] = a;
     }
 }
 
