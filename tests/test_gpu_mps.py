@@ -129,3 +129,28 @@ def test_centre_moves_both_directions(M):
     ref = oracle.brute_force(n, layers)
     sv = _gpu_statevector(st)
     assert np.max(np.abs(sv - ref)) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_wide_bonds_exact_without_chains(M, prec):
+    """16 qubits, brickwork depth 12, chi cap 256 = 2^(n/2), every operation
+    on the multi-kernel path: centre moves factor site matrices of up to 256
+    columns (eight 32-step panels of right-looking window steps) and the
+    updates finish with panels whose window holds every remaining column."""
+    print(f"case wide bonds prec={prec}", flush=True)
+    n = 16
+    layers = synth.brickwork(synth.rng(120), n, 12)
+    M.set_small_bond_limit(0)
+    try:
+        st = M.MPS(n, 256, prec)
+        infos = st.apply_layers(layers)
+        dims = st.bond_dims()
+    finally:
+        M.set_small_bond_limit(64)
+    assert max(dims) == 256
+    assert all(i["panels"] > 0 for i in infos)
+    ref = oracle.brute_force(n, layers)
+    sv = _gpu_statevector(st)
+    tol = 1e-10 if prec == 0 else 1e-4
+    assert np.max(np.abs(sv - ref)) <= tol * 10 * np.max(np.abs(ref))
+    assert abs(st.log_norm_fidelity()) <= tol * 10
