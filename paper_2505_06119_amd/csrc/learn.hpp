@@ -249,7 +249,7 @@ __global__ __launch_bounds__(256) void k_certificate(const ArgBest* cpart, int n
     mins[threadIdx.x] = mn;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) mins[threadIdx.x] = fmin(mins[threadIdx.x], mins[threadIdx.x + s]);
+        if ((int)threadIdx.x < s) mins[threadIdx.x] = fmin(mins[threadIdx.x], mins[threadIdx.x + s]);
         __syncthreads();
     }
     (void)red;
