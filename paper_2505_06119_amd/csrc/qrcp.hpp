@@ -117,7 +117,6 @@ __global__ __launch_bounds__(256) void k_step_a(QrcpDev<T> d, int64_t j, int64_t
     __shared__ ArgBest arg_lds[4];
     __shared__ int s_fl;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const T zero = from_d<T>(czero());
     const int32_t stop = d.ctl[CTL_STOP];
     const int64_t i = (int64_t)blockIdx.x * 256 + tid;
     const bool in = i < d.m, below = in && i >= j;

@@ -136,10 +136,34 @@ __global__ __launch_bounds__(1024) void k_window_select(QrcpDev<T> d, int64_t p0
     for (int shift = 56; shift >= 0; shift -= 8) {
         if (tid < 256) s_hist[tid] = 0;
         __syncthreads();
+        // Norms of similar size share the top digits, so most entries of a
+        // pass land in one bin.  Each thread first merges runs of equal digits
+        // among its entries; when every lane of a wave holds a single run of
+        // one digit, the wave adds its total with one atomic instead of 64.
+        uint32_t run_d = 0xffffffffu, run_c = 0;
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int q = tid + 1024 * u;
-            if (q < L && (s_b[q] & mask) == prefix) atomicAdd(&s_hist[(s_b[q] >> shift) & 255], 1u);
+            if (q < L && (s_b[q] & mask) == prefix) {
+                const uint32_t dg = (uint32_t)(s_b[q] >> shift) & 255u;
+                if (dg == run_d) {
+                    ++run_c;
+                } else {
+                    if (run_c) atomicAdd(&s_hist[run_d], run_c);
+                    run_d = dg;
+                    run_c = 1;
+                }
+            }
+        }
+        {
+            const uint32_t d0 = (uint32_t)__shfl((int)run_d, 0, MPS_WAVE);
+            if (__all(run_c == 0 || run_d == d0)) {
+                uint32_t tot = run_c;
+                for (int off = 32; off > 0; off >>= 1) tot += (uint32_t)__shfl_xor((int)tot, off, MPS_WAVE);
+                if (lane == 0 && tot) atomicAdd(&s_hist[d0], tot);
+            } else if (run_c) {
+                atomicAdd(&s_hist[run_d], run_c);
+            }
         }
         __syncthreads();
         if (tid < 64) {
