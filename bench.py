@@ -111,6 +111,27 @@ def time_path(M, L, torch, name, prec, a, b, g, chi, steps, warmup, learned=None
             "per_step": per_step, "A_out": A_out, "B_out": B_out}
 
 
+def seed_spread(M, L, torch, synth, chi, seeds, steps, warmup):
+    """The headline measurement on further seeds (a new canonical pair and
+    gate each, same construction): mixed and FP64 updates/s and the mixed
+    path's norm-fidelity deviation, with fewer timed steps."""
+    out = []
+    scale = 150.0 * chi / 1024.0
+    for sd in seeds:
+        log(f"[bench] seed {sd}: generating the chi={chi} pair")
+        r = synth.rng(sd)
+        a, b = synth.canonical_pair_device(r, chi, chi, chi, synth.exp_spectrum(chi, scale))
+        g = synth.haar_unitary(r, 4)
+        rm = time_path(M, L, torch, f"mixed seed {sd}", M.MPS_MIXED, a, b, g, chi, steps, warmup)
+        rf = time_path(M, L, torch, f"fp64 seed {sd}", M.MPS_FP64, a, b, g, chi, steps, warmup)
+        dv = deviation(torch, rm, rf, chi)
+        out.append({"seed": sd, "mixed": steps / rm["seconds"], "fp64": steps / rf["seconds"],
+                    "norm_fidelity_rel": dv["norm_fidelity_rel"], "within_1e-4": dv["within_1e-4"]})
+        del rm, rf, a, b
+        torch.cuda.empty_cache()
+    return out
+
+
 def step_stats(per_step):
     """Median, interquartile range and extremes of the per-update wall times (ms)."""
     v = sorted(1000.0 * x for x in per_step)
@@ -344,6 +365,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--chi", type=int, default=4096)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--seeds", type=int, default=3,
+                    help="also time the headline on this many seeds in all (seed, seed+1, ...), fewer steps each")
     ap.add_argument("--cpu-sample-chi", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -476,7 +499,21 @@ def main():
             res[f"path_{k}"]["deviation_vs_fp64"] = devs[k]
     if "fp64" in rates:
         res["speedup_vs_fp64_qrcp"] = rates[head] / rates["fp64"]
-    del runs
+    if "fp64" in runs and args.seeds > 1:
+        log("[bench] the headline on further seeds")
+        first = {"seed": args.seed, "mixed": rates["mixed"], "fp64": rates["fp64"],
+                 "norm_fidelity_rel": devs["mixed"]["norm_fidelity_rel"], "within_1e-4": devs["mixed"]["within_1e-4"]}
+        del runs
+        torch.cuda.empty_cache()
+        per_seed = [first] + seed_spread(M, L, torch, synth, chi, [args.seed + i for i in range(1, args.seeds)],
+                                         max(5, args.steps // 2), 1)
+        mx = sorted(x["mixed"] for x in per_seed)
+        fx = sorted(x["fp64"] for x in per_seed)
+        res["seeds"] = {"per_seed": per_seed, "mixed_median": mx[len(mx) // 2], "mixed_min": mx[0],
+                        "mixed_max": mx[-1], "fp64_median": fx[len(fx) // 2],
+                        "all_within_1e-4": all(x["within_1e-4"] for x in per_seed)}
+    else:
+        del runs
     torch.cuda.empty_cache()
     if not args.no_layers:
         log("[bench] circuit layers with and without small-bond chains")
