@@ -587,12 +587,23 @@ static void run_window_steps(UpdateWs<T>& w, hipStream_t st, int64_t p0, int64_t
     // sampled profiling times the whole run with one event pair
     hipEvent_t er = prof_begin_run(st);
     double rbytes = 0.0, rflops = 0.0;
+    // the block shape follows the rows left: one wave of 8 rows per lane up to
+    // 512 rows, four waves up to 2048, otherwise 512 threads of 16 rows
+    const int64_t rows0 = d.m - p0;
     for (int64_t jj = 0; jj < nsteps; ++jj) {
         const int64_t j = p0 + jj;
         hipEvent_t ec = g_prof.stride > 1 ? nullptr : prof_begin(st, PK_STEP_C);
-        hipLaunchKernelGGL((k_window_step<T>), dim3((unsigned)W), dim3(WSTEP_NT), 0, st, d, j, p0, (int)jj,
-                           (const ArgBest*)(w.wcp + (jj & 1) * QR_WIN_MAX), w.wcp + ((jj + 1) & 1) * QR_WIN_MAX,
-                           w.wpiv, w.vbuf, w.wstep, w.Gbuf, (int)UNGQR_NB, fixed);
+        const ArgBest* cin = w.wcp + (jj & 1) * QR_WIN_MAX;
+        ArgBest* cout = w.wcp + ((jj + 1) & 1) * QR_WIN_MAX;
+        if (rows0 <= 64 * 8)
+            hipLaunchKernelGGL((k_window_step<T, 64, 8>), dim3((unsigned)W), dim3(64), 0, st, d, j, p0, (int)jj, cin,
+                               cout, w.wpiv, w.vbuf, w.wstep, w.Gbuf, (int)UNGQR_NB, fixed);
+        else if (rows0 <= 256 * 8)
+            hipLaunchKernelGGL((k_window_step<T, 256, 8>), dim3((unsigned)W), dim3(256), 0, st, d, j, p0, (int)jj,
+                               cin, cout, w.wpiv, w.vbuf, w.wstep, w.Gbuf, (int)UNGQR_NB, fixed);
+        else
+            hipLaunchKernelGGL((k_window_step<T>), dim3((unsigned)W), dim3(WSTEP_NT), 0, st, d, j, p0, (int)jj, cin,
+                               cout, w.wpiv, w.vbuf, w.wstep, w.Gbuf, (int)UNGQR_NB, fixed);
         // algorithmic traffic of one step: the window right of the pivot read and written once
         const double cols = (double)(p0 + W - j - 1), rows = (double)(d.m - j);
         prof_end(ec, st, PK_STEP_C, 2.0 * sizeof(T) * rows * cols, 16.0 * rows * cols);

@@ -502,8 +502,7 @@ __global__ __launch_bounds__(256) void k_nu_argmax(QrcpDev<T> d, int64_t c0)
 // (rows j..m, shared through L2) and forms the reflector with the same
 // arithmetic as every other block.  The pivot's block stores beta and v in
 // vbuf[:, jj] (column p itself is read by all blocks during the step and is
-// left as it is).  grid: W blocks of WSTEP_NT threads; requires
-// m - j <= WSTEP_NT * WSTEP_RPT.
+// left as it is).  grid: W blocks of NT threads; requires m - j <= NT * RPT.
 // ---------------------------------------------------------------------------
 #define WSTEP_NT 512    // threads per block (8 waves)
 #define WSTEP_RPT 16    // rows per thread
@@ -518,6 +517,7 @@ __device__ __forceinline__ ArgBest e0_dead()
     return z;
 }
 
+template <int NW>
 __device__ __forceinline__ double block_sum_ws(double v, double* lds)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -526,12 +526,13 @@ __device__ __forceinline__ double block_sum_ws(double v, double* lds)
     if (lane == 0) lds[wid] = v;
     __syncthreads();
     double s = 0.0;
-    for (int w = 0; w < WSTEP_NW; ++w) s += lds[w];
+    for (int w = 0; w < NW; ++w) s += lds[w];
     return s;
 }
 
 // three block sums in one round
-__device__ __forceinline__ void block_sum_ws3(double& a, double& b, double& c, double* lds /* 3 * WSTEP_NW */)
+template <int NW>
+__device__ __forceinline__ void block_sum_ws3(double& a, double& b, double& c, double* lds /* 3 * NW */)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     a = wave_sum(a);
@@ -540,15 +541,15 @@ __device__ __forceinline__ void block_sum_ws3(double& a, double& b, double& c, d
     __syncthreads();
     if (lane == 0) {
         lds[wid] = a;
-        lds[WSTEP_NW + wid] = b;
-        lds[2 * WSTEP_NW + wid] = c;
+        lds[NW + wid] = b;
+        lds[2 * NW + wid] = c;
     }
     __syncthreads();
     double sa = 0.0, sb = 0.0, sc = 0.0;
-    for (int w = 0; w < WSTEP_NW; ++w) {
+    for (int w = 0; w < NW; ++w) {
         sa += lds[w];
-        sb += lds[WSTEP_NW + w];
-        sc += lds[2 * WSTEP_NW + w];
+        sb += lds[NW + w];
+        sc += lds[2 * NW + w];
     }
     a = sa;
     b = sb;
@@ -558,13 +559,16 @@ __device__ __forceinline__ void block_sum_ws3(double& a, double& b, double& c, d
 // fixed != 0: unpivoted QR in column order (a centre move).  The partials
 // then carry W - b instead of the norm, so the live column of smallest
 // position wins every argmax (seeded by k_fixed_partials).
-template <typename T>
-__global__ __launch_bounds__(WSTEP_NT) void k_window_step(QrcpDev<T> d, int64_t j, int64_t p0, int jj, const ArgBest* cin,
+// NT threads per block with RPT rows each (NT * RPT >= m - j): 512 x 16 for
+// the large factorisations, smaller blocks when few rows remain.
+template <typename T, int NT = WSTEP_NT, int RPT = WSTEP_RPT>
+__global__ __launch_bounds__(NT) void k_window_step(QrcpDev<T> d, int64_t j, int64_t p0, int jj, const ArgBest* cin,
                                                       ArgBest* cout, int32_t* wpiv, T* vbuf, int32_t* wstep, T* gbuf, int ldg,
                                                       int fixed)
 {
-    __shared__ double s_red[3 * WSTEP_NW];
-    __shared__ ArgBest s_arg[WSTEP_NW];
+    constexpr int NW = NT / 64;
+    __shared__ double s_red[3 * NW];
+    __shared__ ArgBest s_arg[NW];
     __shared__ double2 s_alpha, s_aj;
     __shared__ int s_dead;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -574,15 +578,16 @@ __global__ __launch_bounds__(WSTEP_NT) void k_window_step(QrcpDev<T> d, int64_t 
     T* colc = d.A + d.lda * c;
     const int32_t stop = d.ctl[CTL_STOP];
 
-    // independent loads first: all partials, this column's rows j.., its key
-    // (W <= QR_WIN_MAX <= WSTEP_NT: one partial per thread)
+    // independent loads first: the first NT partials (all of them when
+    // W <= NT), this block's own partial, this column's rows j.., its key
     const ArgBest e = cin[tid < W ? tid : 0];
+    const int32_t own_slot = cin[b].slot;
     const int32_t key_c = d.perm[c];
     const double nuref_c = d.nuref[c];
-    T a[WSTEP_RPT];
+    T a[RPT];
 #pragma unroll
-    for (int q = 0; q < WSTEP_RPT; ++q) {
-        const int i = j0 + tid + WSTEP_NT * q;
+    for (int q = 0; q < RPT; ++q) {
+        const int i = j0 + tid + NT * q;
         a[q] = colc[i < m ? i : m - 1];
     }
     ArgBest best;
@@ -590,12 +595,16 @@ __global__ __launch_bounds__(WSTEP_NT) void k_window_step(QrcpDev<T> d, int64_t 
     best.key = 0x7fffffff;
     best.slot = -1;
     if (tid < W && e.slot >= 0) best = e;
-    if (tid == b) s_dead = e.slot < 0 ? 1 : 0;
+    for (int t = tid + NT; t < W; t += NT) {   // windows wider than the block
+        const ArgBest f = cin[t];
+        if (f.slot >= 0 && arg_better(f.val, f.key, best.val, best.key)) best = f;
+    }
+    if (tid == 0) s_dead = own_slot < 0 ? 1 : 0;
     best = wave_argmax(best);
     if (lane == 0) s_arg[wid] = best;
     __syncthreads();
     ArgBest bb = s_arg[0];
-    for (int w = 1; w < WSTEP_NW; ++w)
+    for (int w = 1; w < NW; ++w)
         if (arg_better(s_arg[w].val, s_arg[w].key, bb.val, bb.key)) bb = s_arg[w];
     if (stop || bb.slot < 0) return;   // uniform over the block
     // a dead block is the pivot of an earlier step i of this panel: it forms
@@ -606,11 +615,11 @@ __global__ __launch_bounds__(WSTEP_NT) void k_window_step(QrcpDev<T> d, int64_t 
     const int64_t p = bb.slot;
 
     // the pivot column and its reflector (identical arithmetic in every block)
-    T x[WSTEP_RPT];   // kept in the storage type, converted at each use
+    T x[RPT];   // kept in the storage type, converted at each use
     const T* colp = d.A + d.lda * p;
 #pragma unroll
-    for (int q = 0; q < WSTEP_RPT; ++q) {
-        const int i = j0 + tid + WSTEP_NT * q;
+    for (int q = 0; q < RPT; ++q) {
+        const int i = j0 + tid + NT * q;
         x[q] = colp[i < m ? i : m - 1];
     }
     if (gi >= 0) {
@@ -618,8 +627,8 @@ __global__ __launch_bounds__(WSTEP_NT) void k_window_step(QrcpDev<T> d, int64_t 
         // column, and g = sum_{r>j} conj(v_i[r]) x_r is formed below
         const T* vi = vbuf + d.lda * gi;
 #pragma unroll
-        for (int q = 0; q < WSTEP_RPT; ++q) {
-            const int i = j0 + tid + WSTEP_NT * q;
+        for (int q = 0; q < RPT; ++q) {
+            const int i = j0 + tid + NT * q;
             a[q] = vi[i < m ? i : m - 1];
         }
     }
@@ -627,8 +636,8 @@ __global__ __launch_bounds__(WSTEP_NT) void k_window_step(QrcpDev<T> d, int64_t 
     // then v^H a = a_j + conj(scale) g with v = (1, scale * x_rest)
     double rest = 0.0, gre = 0.0, gim = 0.0;
 #pragma unroll
-    for (int q = 0; q < WSTEP_RPT; ++q) {
-        const int i = j0 + tid + WSTEP_NT * q;
+    for (int q = 0; q < RPT; ++q) {
+        const int i = j0 + tid + NT * q;
         if (i > j0 && i < m) {
             const double2 xi = to_d(x[q]);
             rest += cabs2(xi);
@@ -642,7 +651,7 @@ __global__ __launch_bounds__(WSTEP_NT) void k_window_step(QrcpDev<T> d, int64_t 
         s_alpha = to_d(x[0]);
         s_aj = to_d(a[0]);
     }
-    block_sum_ws3(rest, gre, gim, s_red);   // its barriers also publish s_alpha, s_aj
+    block_sum_ws3<NW>(rest, gre, gim, s_red);   // its barriers also publish s_alpha, s_aj
     const double2 alpha = s_alpha;
     double2 tau, scale;
     double beta;
@@ -666,8 +675,8 @@ __global__ __launch_bounds__(WSTEP_NT) void k_window_step(QrcpDev<T> d, int64_t 
     if (c == p) {
         // this column is the pivot: beta and v go to vbuf[j.., jj]
 #pragma unroll
-        for (int q = 0; q < WSTEP_RPT; ++q) {
-            const int i = j0 + tid + WSTEP_NT * q;
+        for (int q = 0; q < RPT; ++q) {
+            const int i = j0 + tid + NT * q;
             if (i == j0) vbuf[i + d.lda * jj] = from_d<T>(make_double2(beta, 0.0));
             else if (i < m) vbuf[i + d.lda * jj] = from_d<T>(cmul(scale, to_d(x[q])));
         }
@@ -690,8 +699,8 @@ __global__ __launch_bounds__(WSTEP_NT) void k_window_step(QrcpDev<T> d, int64_t 
     // a -= conj(tau) v (v^H a); exact residual norm of rows > j afterwards
     double nn = 0.0;
 #pragma unroll
-    for (int q = 0; q < WSTEP_RPT; ++q) {
-        const int i = j0 + tid + WSTEP_NT * q;
+    for (int q = 0; q < RPT; ++q) {
+        const int i = j0 + tid + NT * q;
         if (i < m) {
             const double2 vi = i == j0 ? make_double2(1.0, 0.0) : cmul(scale, to_d(x[q]));
             const T an = from_d<T>(csub(to_d(a[q]), cmul(coef, vi)));
@@ -699,7 +708,7 @@ __global__ __launch_bounds__(WSTEP_NT) void k_window_step(QrcpDev<T> d, int64_t 
             if (i > j0) nn += cabs2(to_d(an));
         }
     }
-    nn = block_sum_ws(nn, s_red);
+    nn = block_sum_ws<NW>(nn, s_red);
     if (tid == 0) {
         d.nu[c] = nn;
         (void)nuref_c;
