@@ -11,7 +11,13 @@ Pieces and the passages they follow (arXiv 2505.06119):
   tensor application: the two sites are contracted over their shared bond and
   the gate over the two physical indices.
 * ``qrcp``              -- Table III, QR with pivoting M = Q R P^T; the greedy
-  definition with exact residual norms, in plain C (``qrcp_oracle.c``).
+  definition with exact residual norms, in plain C (``qrcp_oracle.c``), with
+  the relative margin between the two largest residual norms at every step.
+* ``known_order_qr``, ``certificate``, ``learned_update`` -- the learned pivot
+  proposal's factorisation and acceptance (an addition of this library, not of
+  the paper): Householder QR with a given column order, the truncation error
+  of the column set it selects, and the two acceptance rules with the plain
+  pivoted-QR fallback.
 * ``two_site_update``   -- Sec. III-C.2: contract, truncated pivoted-QR
   decomposition, split back into two sites; with ``truncation="svd"`` the
   truncated decomposition is the SVD of Table III (M = U S V^dagger), the
@@ -29,7 +35,8 @@ Pieces and the passages they follow (arXiv 2505.06119):
 
 Where the paper is silent the oracle takes these readings: site 0 is the most
 significant qubit; the gate's row index is 2a'+b' with a on the lower site;
-equal residual norms go to the smallest original column; the truncation rank
+theta's column index is 2r + b' (the right site's physical index runs
+fastest), and equal residual norms go to the smallest such column; the truncation rank
 is k = min(chi_cap, m, n) with no tolerance cut-off; the orthogonality centre
 is moved to site i (or i+1 when it lies right of i) before each update and the
 split leaves Q on the left site.
@@ -67,7 +74,7 @@ def _load():
         i64 = ctypes.c_int64
         lib.orc_qrcp.restype = ctypes.c_int
         lib.orc_qrcp.argtypes = [i64, i64, i64, ctypes.c_int, p, i64, p, i64, p, i64,
-                                 p, p, p, p]
+                                 p, p, p, p, p]
         lib.orc_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -83,7 +90,9 @@ def qrcp(a: np.ndarray, kmax: int, pivoting: bool = True) -> dict:
     """Greedy column-pivoted Householder QR of ``a`` stopped after k steps.
 
     Returns a dict with Q (m x k), R (k x n, pivoted column order), piv (n),
-    diagR (k), err (||R22||_F), k.  See ``qrcp_oracle.c``."""
+    diagR (k), err (||R22||_F), k, and gaps (k): the relative margin
+    (nu_1 - nu_2) / nu_1 between the two largest squared residual norms at each
+    pivoting step (1 without pivoting).  See ``qrcp_oracle.c``."""
     lib = _load()
     a = np.asfortranarray(a, dtype=np.complex128)
     m, n = a.shape
@@ -94,14 +103,15 @@ def qrcp(a: np.ndarray, kmax: int, pivoting: bool = True) -> dict:
     diag = np.zeros(max(k, 1), dtype=np.float64)
     err = np.zeros(1, dtype=np.float64)
     kout = np.zeros(1, dtype=np.int64)
+    gaps = np.ones(max(k, 1), dtype=np.float64)
     rc = lib.orc_qrcp(m, n, int(kmax), 1 if pivoting else 0,
                       a.ctypes.data, max(m, 1), q.ctypes.data, max(m, 1),
                       r.ctypes.data, max(k, 1), piv.ctypes.data, diag.ctypes.data,
-                      err.ctypes.data, kout.ctypes.data)
+                      err.ctypes.data, kout.ctypes.data, gaps.ctypes.data)
     if rc != 0:
         raise ValueError("orc_qrcp rejected its arguments")
     return {"Q": q, "R": r, "piv": piv.astype(np.int64), "diagR": diag[:k],
-            "err": float(err[0]), "k": int(kout[0])}
+            "err": float(err[0]), "k": int(kout[0]), "gaps": gaps[:k]}
 
 
 def r_unpivot(r: np.ndarray, piv: np.ndarray) -> np.ndarray:
@@ -111,18 +121,81 @@ def r_unpivot(r: np.ndarray, piv: np.ndarray) -> np.ndarray:
     return out
 
 
+# --- learned pivot proposal: factorisation with a given order, acceptance ----
+
+def known_order_qr(a: np.ndarray, order, kmax: int) -> dict:
+    """Householder QR of ``a`` with its columns taken in the given order (no
+    pivot search), stopped after k = min(kmax, m, n) steps.
+
+    ``order`` lists every column once; its first k entries form the selected
+    set S.  Returns the same fields as ``qrcp`` (piv = order) plus err =
+    ||R22||_F, which equals ||(I - Pi_S) a||_F, the distance of ``a`` from
+    the span of its columns S."""
+    order = np.asarray(order, dtype=np.int64)
+    n = a.shape[1]
+    if sorted(order.tolist()) != list(range(n)):
+        raise ValueError("order must be a permutation of the columns")
+    f = qrcp(np.asarray(a, dtype=np.complex128)[:, order], kmax, pivoting=False)
+    f["piv"] = order.copy()
+    return f
+
+
+def residual_norms(a: np.ndarray, q: np.ndarray, cols) -> np.ndarray:
+    """Euclidean norms of the columns ``cols`` of (I - Q Q^H) a."""
+    x = np.asarray(a, dtype=np.complex128)[:, np.asarray(cols, dtype=np.int64)]
+    return np.linalg.norm(x - q @ (q.conj().T @ x), axis=0)
+
+
+def certificate(a: np.ndarray, f: dict) -> bool:
+    """Acceptance without a reference factorisation: every unselected column's
+    residual norm is at most the smallest |R_jj| of the selected ones, the
+    inequality plain pivoted QR satisfies by construction."""
+    k = f["k"]
+    rest = f["piv"][k:]
+    if k == 0 or len(rest) == 0:
+        return True
+    return float(np.max(residual_norms(a, f["Q"], rest))) <= float(np.min(np.abs(f["diagR"])))
+
+
+def learned_update(a: np.ndarray, order, kmax: int, ratio: float = 1.01, verify: bool = True) -> dict:
+    """The learned path's decision for one matrix: factorise with the proposed
+    order, then keep that factorisation if it passes, else fall back to plain
+    pivoted QR.  verify=True keeps it when its error is at most ``ratio``
+    times plain pivoted QR's; verify=False applies ``certificate``.  Returns
+    the kept factorisation with ``accepted``, ``err_s`` (the proposal's error)
+    and ``err_q`` (plain pivoted QR's, when it ran)."""
+    fs = known_order_qr(a, order, kmax)
+    fq = qrcp(a, kmax) if verify else None
+    if verify:
+        accepted = fs["err"] <= ratio * fq["err"]
+    else:
+        accepted = certificate(a, fs)
+    if not accepted and fq is None:
+        fq = qrcp(a, kmax)
+    out = dict(fs if accepted else fq)
+    out.update(accepted=bool(accepted), err_s=fs["err"], err_q=None if fq is None else fq["err"])
+    return out
+
+
 # --- two-site update -----------------------------------------------------------
 
 def theta(a: np.ndarray, b: np.ndarray, g: np.ndarray) -> np.ndarray:
     """theta[(l,a'),(b',r)] = sum_{a,b} G[a'b',ab] sum_m A[l,a,m] B[m,b,r].
 
     Returned as a (2*chi_l) x (2*chi_r) matrix with row index 2*l + a' and
-    column index chi_r*b' + r."""
+    column index 2*r + b'.  The column index is what "smallest original
+    column" refers to when pivoted QR breaks a tie."""
     chi_l, chi_r = a.shape[0], b.shape[2]
     t0 = np.tensordot(a, b, axes=(2, 0))                 # [l, a, b, r]
     g4 = np.asarray(g, dtype=np.complex128).reshape(2, 2, 2, 2)
-    t = np.einsum("xyab,labr->lxyr", g4, t0)
+    t = np.einsum("xyab,labr->lxry", g4, t0)
     return t.reshape(2 * chi_l, 2 * chi_r)
+
+
+def split_right(rp: np.ndarray, chi_r: int) -> np.ndarray:
+    """The right site [k, b, r] from a k x (2 chi_r) factor with column 2r + b."""
+    k = rp.shape[0]
+    return np.ascontiguousarray(rp.reshape(k, chi_r, 2).transpose(0, 2, 1))
 
 
 def svd_truncate(th: np.ndarray, kmax: int) -> dict:
@@ -148,7 +221,7 @@ def two_site_update(a: np.ndarray, b: np.ndarray, g: np.ndarray, chi_cap: int, t
         f = svd_truncate(th, chi_cap)
         k = f["k"]
         return {"A": np.ascontiguousarray(f["U"].reshape(chi_l, 2, k)),
-                "B": np.ascontiguousarray(f["SVh"].reshape(k, 2, chi_r)), "k": k, "err": f["err"],
+                "B": split_right(f["SVh"], chi_r), "k": k, "err": f["err"],
                 "norm2": float(np.vdot(th, th).real), "theta": th, "s": f["s"]}
     if truncation != "qrcp":
         raise ValueError(f"unknown truncation {truncation!r}")
@@ -156,10 +229,9 @@ def two_site_update(a: np.ndarray, b: np.ndarray, g: np.ndarray, chi_cap: int, t
     k = f["k"]
     a2 = f["Q"].reshape(chi_l, 2, k)
     rp = r_unpivot(f["R"], f["piv"])
-    b2 = rp.reshape(k, 2, chi_r)
-    return {"A": np.ascontiguousarray(a2), "B": np.ascontiguousarray(b2), "k": k,
+    return {"A": np.ascontiguousarray(a2), "B": split_right(rp, chi_r), "k": k,
             "err": f["err"], "norm2": float(np.vdot(th, th).real), "theta": th,
-            "piv": f["piv"], "diagR": f["diagR"]}
+            "piv": f["piv"], "diagR": f["diagR"], "gaps": f["gaps"]}
 
 
 class MPS:

@@ -15,8 +15,11 @@ paper uses plain pivoted QR).  This module computes, plainly and in FP64:
 * ``forward``   score = w2 . tanh(W1 phi + b1) + b2 (4 -> 16 -> 1).
 * ``loss_grad`` mean logistic loss sum_c [softplus(s_c) - y_c s_c]/n and its
   gradient by the chain rule, written out by hand.
+* ``adam_step`` one step of the Adam optimiser that trains the network.
 
-The gradient is pinned against central finite differences in the tests.
+The gradient is pinned against central finite differences in the tests, and
+the Adam step against its closed forms (the first step, and every step under
+a constant gradient, moves each parameter by lr * sign(g) up to eps).
 Parameter layout (97 values): W1[h*4 + f] (64), b1 (16), w2 (16), b2 (1).
 """
 from __future__ import annotations
@@ -102,3 +105,17 @@ def loss_grad(p: np.ndarray, phi: np.ndarray, labels: np.ndarray):
     g_b1 = dz.sum(axis=0)
     g = np.concatenate([g_w1.reshape(-1), g_b1, g_w2, [g_b2]])
     return g, float(np.mean(np.logaddexp(0.0, s) - y * s))
+
+
+def adam_step(p: np.ndarray, g: np.ndarray, m1: np.ndarray, m2: np.ndarray, t: int, lr: float,
+              beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    """One Adam step (Kingma and Ba, ICLR 2015, Algorithm 1) in FP64: first and
+    second moment estimates, their bias corrections by 1 - beta^t, and the
+    update p - lr * m_hat / (sqrt(v_hat) + eps).  Returns new (p, m1, m2)."""
+    p = np.asarray(p, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    m1 = beta1 * np.asarray(m1, dtype=np.float64) + (1.0 - beta1) * g
+    m2 = beta2 * np.asarray(m2, dtype=np.float64) + (1.0 - beta2) * g * g
+    m_hat = m1 / (1.0 - beta1 ** t)
+    v_hat = m2 / (1.0 - beta2 ** t)
+    return p - lr * m_hat / (np.sqrt(v_hat) + eps), m1, m2

@@ -60,12 +60,18 @@ static cplx householder(cplx* x, int64_t len)
  *   piv   : piv[j] = original column placed at position j (all n entries)
  *   diagR : R[j, j] for j < k (real)
  *   err_fro : Frobenius norm of the trailing block left after k steps (||R22||_F)
+ *   gaps  : optional (may be NULL), k doubles: at pivoting step j the relative
+ *           margin (nu_1 - nu_2) / nu_1 between the largest and the second
+ *           largest squared residual norm among the candidates (1 when only one
+ *           candidate is left or nu_1 = 0).  A margin near the rounding level
+ *           marks a step whose pivot another correct implementation may take
+ *           differently.
  * Returns 0, or -1 on bad arguments / allocation failure.
  */
 int orc_qrcp(int64_t m, int64_t n, int64_t kmax, int pivoting,
              const cplx* A, int64_t lda,
              cplx* Q, int64_t ldq, cplx* R, int64_t ldr,
-             int32_t* piv, double* diagR, double* err_fro, int64_t* k_out)
+             int32_t* piv, double* diagR, double* err_fro, int64_t* k_out, double* gaps)
 {
     if (m < 0 || n < 0 || kmax < 0 || lda < (m > 1 ? m : 1)) return -1;
     int64_t k = kmax;
@@ -95,12 +101,20 @@ int orc_qrcp(int64_t m, int64_t n, int64_t kmax, int pivoting,
             for (int64_t c = j + 1; c < n; ++c)
                 if (nrm[c] > nrm[best] || (nrm[c] == nrm[best] && piv[c] < piv[best]))
                     best = c;
+            if (gaps) {
+                double second = -1.0;
+                for (int64_t c = j; c < n; ++c)
+                    if (c != best && nrm[c] > second) second = nrm[c];
+                gaps[j] = (second < 0.0 || nrm[best] <= 0.0) ? 1.0 : (nrm[best] - second) / nrm[best];
+            }
             if (best != j) {
                 cplx* a = W + j * m;
                 cplx* b = W + best * m;
                 for (int64_t i = 0; i < m; ++i) { cplx t = a[i]; a[i] = b[i]; b[i] = t; }
                 int32_t t = piv[j]; piv[j] = piv[best]; piv[best] = t;
             }
+        } else if (gaps) {
+            gaps[j] = 1.0;
         }
         cplx* x = W + j * m + j;
         tau[j] = householder(x, m - j);

@@ -233,7 +233,7 @@ def test_two_site_update_projection():
     g = synth.haar_unitary(r, 4)
     u = oracle.two_site_update(a, b, g, 8)
     th = u["theta"]
-    tt = np.tensordot(u["A"], u["B"], axes=(2, 0)).reshape(th.shape)
+    tt = np.tensordot(u["A"], u["B"], axes=(2, 0)).transpose(0, 1, 3, 2).reshape(th.shape)
     q = u["A"].reshape(-1, u["k"])
     np.testing.assert_allclose(tt, q @ (q.conj().T @ th), atol=1e-13)
     assert abs(np.linalg.norm(th - tt) - u["err"]) < 1e-13
@@ -283,3 +283,89 @@ def test_gate_identities():
     np.testing.assert_allclose(synth.gate_fsim(), fs, atol=1e-15)
     for g in (synth.gate_fsim(), synth.gate_sqrt_w(), synth.gate_h()):
         np.testing.assert_allclose(g @ g.conj().T, np.eye(len(g)), atol=1e-15)
+
+
+# --- learned pivot proposal: known-order QR, certificate, fallback ---------------
+
+def _projection_error(a, cols):
+    basis = a[:, cols]
+    coef, *_ = np.linalg.lstsq(basis, a, rcond=None)
+    return np.linalg.norm(a - basis @ coef)
+
+
+@pytest.mark.parametrize("m,n,k,seed", [(30, 24, 10, 40), (16, 40, 16, 41), (50, 50, 20, 42)])
+def test_known_order_error_is_the_projection_residual(m, n, k, seed):
+    """eps_S = ||(I - Pi_S) A||_F for the first k columns S of the order,
+    computed independently by least squares; Q spans A[:, S]."""
+    r = synth.rng(seed)
+    a = synth.cgauss(r, (m, n))
+    order = r.permutation(n)
+    f = oracle.known_order_qr(a, order, k)
+    s = list(order[:f["k"]])
+    assert abs(f["err"] - _projection_error(a, s)) <= 1e-12 * np.linalg.norm(a)
+    q = f["Q"]
+    np.testing.assert_allclose(q.conj().T @ q, np.eye(f["k"]), atol=1e-12)
+    np.testing.assert_allclose(q @ (q.conj().T @ a[:, s]), a[:, s], atol=1e-12)
+    np.testing.assert_allclose(q @ oracle.r_unpivot(f["R"], f["piv"]), q @ (q.conj().T @ a), atol=1e-12)
+    assert list(f["piv"]) == list(order)
+
+
+def test_known_order_with_the_greedy_order_is_qrcp():
+    a = synth.cgauss(synth.rng(43), (40, 32))
+    fq = oracle.qrcp(a, 12)
+    fs = oracle.known_order_qr(a, fq["piv"], 12)
+    assert abs(fs["err"] - fq["err"]) <= 1e-12 * np.linalg.norm(a)
+    np.testing.assert_allclose(np.abs(fs["diagR"]), np.abs(fq["diagR"]), rtol=1e-12)
+
+
+def test_certificate_and_fallback_rules():
+    """The greedy order always passes the certificate (its pivots dominate every
+    residual) and the 1% rule; the order of smallest columns fails both, and
+    the fallback then returns plain pivoted QR."""
+    r = synth.rng(44)
+    u = synth.haar_isometry(r, 60, 40)
+    w = synth.haar_isometry(r, 48, 40)
+    a = (u * synth.exp_spectrum(40, 8.0)) @ w.conj().T
+    k = 12
+    fq = oracle.qrcp(a, k)
+    assert oracle.certificate(a, oracle.known_order_qr(a, fq["piv"], k))
+    good = oracle.learned_update(a, fq["piv"], k, ratio=1.01, verify=True)
+    assert good["accepted"] and abs(good["err_s"] - fq["err"]) <= 1e-12
+    bad_order = np.argsort(np.linalg.norm(a, axis=0), kind="stable")     # smallest columns first
+    fb = oracle.known_order_qr(a, bad_order, k)
+    assert fb["err"] > 1.01 * fq["err"]
+    assert not oracle.certificate(a, fb)
+    for verify in (True, False):
+        out = oracle.learned_update(a, bad_order, k, ratio=1.01, verify=verify)
+        assert not out["accepted"]
+        assert list(out["piv"]) == list(fq["piv"])
+        assert out["err"] == fq["err"]
+
+
+def test_theta_column_order_reading():
+    """theta's column index is 2r + b' (the reading behind 'smallest original
+    column' in a tie): a right site with one non-zero entry at (b, r) and the
+    identity gate puts the single non-zero column of theta at 2r + b."""
+    chi_l, chi_m, chi_r = 3, 2, 5
+    a = np.zeros((chi_l, 2, chi_m), dtype=np.complex128)
+    a[1, 0, 0] = 1.0
+    for b, rr in [(0, 0), (1, 0), (0, 3), (1, 4)]:
+        bs = np.zeros((chi_m, 2, chi_r), dtype=np.complex128)
+        bs[0, b, rr] = 1.0
+        th = oracle.theta(a, bs, np.eye(4))
+        nz = np.flatnonzero(np.linalg.norm(th, axis=0))
+        assert list(nz) == [2 * rr + b]
+        assert np.flatnonzero(np.linalg.norm(th, axis=1)).tolist() == [2 * 1 + 0]
+
+
+def test_margins_flag_exact_ties():
+    """The per-step margin is 0 at an exact tie and positive otherwise."""
+    b = np.zeros((4, 5), dtype=np.complex128)
+    b[0, 3] = b[1, 1] = 2.0
+    b[2, 0] = 1.0
+    b[3, 4] = 0.5
+    f = oracle.qrcp(b, 4)
+    assert f["gaps"][0] == 0.0                      # columns 1 and 3 tie
+    assert f["gaps"][1] == pytest.approx(0.75)      # 4 against 1
+    assert f["gaps"][2] == pytest.approx(0.75)      # 1 against 0.25
+    assert f["gaps"][3] == 1.0                      # nothing left to compare

@@ -65,3 +65,45 @@ def test_forward_special_cases():
     p[0] = 1.0                                               # W1[0, 0]
     p[pivnet.H * pivnet.F + pivnet.H] = 2.0                 # w2[0]
     np.testing.assert_allclose(pivnet.forward(p, phi), 2.0 * np.tanh(phi[:, 0]), rtol=1e-15)
+
+
+def test_adam_first_step_moves_by_lr_sign():
+    """Adam's first step (bias-corrected moments m_hat = g, v_hat = g^2) moves
+    every parameter by lr * sign(g), up to eps / |g|."""
+    r = synth.rng(13)
+    p0 = r.standard_normal(pivnet.P)
+    g = r.standard_normal(pivnet.P) * 10.0 ** r.uniform(-3, 2, pivnet.P)
+    lr = 3e-3
+    p1, m1, m2 = pivnet.adam_step(p0, g, np.zeros(pivnet.P), np.zeros(pivnet.P), 1, lr)
+    step = p0 - p1
+    np.testing.assert_allclose(step, lr * np.sign(g) * np.abs(g) / (np.abs(g) + 1e-8), rtol=1e-12)
+    assert np.all(np.abs(step - lr * np.sign(g)) <= lr * 1e-8 / np.abs(g) + 1e-15)
+    np.testing.assert_allclose(m1, 0.1 * g, rtol=1e-15)
+    np.testing.assert_allclose(m2, 1e-3 * g * g, rtol=1e-12)
+
+
+def test_adam_constant_gradient_steps_are_lr_sign():
+    """Under a constant gradient both bias-corrected moments equal g and g^2 at
+    every step, so every step moves by lr * sign(g) (up to eps)."""
+    r = synth.rng(14)
+    g = r.standard_normal(pivnet.P)
+    p = r.standard_normal(pivnet.P)
+    m1 = np.zeros(pivnet.P)
+    m2 = np.zeros(pivnet.P)
+    lr = 1e-2
+    for t in range(1, 40):
+        p_new, m1, m2 = pivnet.adam_step(p, g, m1, m2, t, lr)
+        assert np.all(np.abs((p - p_new) - lr * np.sign(g)) <= lr * 1e-8 / np.abs(g) + 1e-13)
+        p = p_new
+
+
+def test_adam_minimises_a_quadratic():
+    """On f(p) = |p - c|^2 / 2 (gradient p - c) Adam approaches the minimiser."""
+    r = synth.rng(15)
+    c = r.standard_normal(8)
+    p = np.zeros(8)
+    m1 = np.zeros(8)
+    m2 = np.zeros(8)
+    for t in range(1, 3001):
+        p, m1, m2 = pivnet.adam_step(p, p - c, m1, m2, t, 1e-2)
+    assert np.max(np.abs(p - c)) < 1e-3
