@@ -31,7 +31,16 @@
  *   errors            every call returns an mps_status; on failure
  *                     mps_last_error() gives a thread-local message.  Argument
  *                     errors (MPS_EINVAL) are detected on the host before any
- *                     device work and leave every output untouched.
+ *                     device work and leave every output untouched.  After
+ *                     MPS_ENUMERIC (a non-finite value in theta or A) the
+ *                     device outputs of a stateless call are unspecified, and a
+ *                     context is marked unusable (later calls: MPS_ESTATE).
+ *   threads           the stateless calls (qrcp_truncate, mps_update_bond,
+ *                     mps_theta, pivnet_*) may run concurrently from several
+ *                     host threads, each on its own stream and workspace.  A
+ *                     context serves one thread at a time.  mps_set_tuning,
+ *                     mps_set_small_bond_limit and mps_profile change
+ *                     process-wide settings and must not overlap other calls.
  */
 #ifndef MPS_ABI_H
 #define MPS_ABI_H
@@ -48,7 +57,8 @@ typedef enum {
     MPS_ENOMEM = 2,   /* workspace / arena too small: nothing was done */
     MPS_EDEVICE = 3,  /* a HIP call failed */
     MPS_ENUMERIC = 4, /* non-finite input or result */
-    MPS_ESTATE = 5    /* context unusable after an earlier device failure */
+    MPS_ESTATE = 5    /* context unusable after an earlier device failure or a
+                         non-finite update result */
 } mps_status;
 
 typedef enum { MPS_FP64 = 0, MPS_MIXED = 1 } mps_precision;
@@ -98,25 +108,38 @@ const char* mps_last_error(void);
  * k = min(k_max, m, n) steps (Table III, "QR with pivoting", M = Q R P^T,
  * truncated as in Sec. II-B).  Stateless.
  *
+ *   mode  MPS_PIVOT_QRCP: greedy pivoting, the largest residual column norm
+ *         at every step; exact ties go to the smaller original column index.
+ *         MPS_PIVOT_LEARNED: the column order proposed by `learned` (see
+ *         mps_learned_cfg above) is factorised without pivot search and kept
+ *         if it passes the acceptance rule, else plain pivoted QR runs
+ *         (info->fallback = 1).
+ *   learned host, required for MPS_PIVOT_LEARNED (copied), else ignored.
  *   A     device, read-only, m x n (lda >= m), precision prec.
  *   Q     device, m x k (ldq >= m): orthonormal columns Q_k.
  *   RPt   device, k x n (ldr >= k): R_k P^T, i.e. column piv[j] of RPt holds
  *         column j of the upper-trapezoidal R_k.  Q RPt is the rank-k
  *         approximation of A.
  *   piv   device, n int32: piv[j] = original column placed at position j
- *         (0-based; all n entries).
+ *         (0-based; all n entries).  For an accepted learned proposal this is
+ *         the proposed order, so piv[0..k) is the selected column set S.
  *   diagR device, k doubles: R_jj (real; sign as produced by the reflector
  *         beta = -sign(Re alpha) ||x||).
  *   k_out, err_fro (= ||R22||_F), a_fro (= ||A||_F): host, may be NULL.
- *   work  device scratch of at least qrcp_work_bytes(...) bytes.
- * Pivot rule: largest residual column norm; exact ties go to the smaller
- * original column index.
+ *   info  host, may be NULL: k, ||R22||^2 (trunc_err_sq), ||A||^2 (norm_sq),
+ *         fallback and the statistics of mps_update_info.
+ *   work  device scratch of at least qrcp_work_bytes(m, n, k_max, prec, mode)
+ *         bytes.
+ * Errors: MPS_EINVAL (sizes, null pointers, leading dimensions, an invalid
+ * learned configuration) and MPS_ENOMEM (work too small) before any device
+ * work; MPS_ENUMERIC when A holds a non-finite value (outputs unspecified);
+ * MPS_EDEVICE when a HIP call fails.
  * ------------------------------------------------------------------------ */
-int64_t qrcp_work_bytes(int64_t m, int64_t n, int64_t k_max, mps_precision prec);
-mps_status qrcp_truncate(int64_t m, int64_t n, int64_t k_max, mps_precision prec,
-                         const void* A, int64_t lda, void* Q, int64_t ldq, void* RPt, int64_t ldr,
-                         int32_t* piv, double* diagR, int64_t* k_out, double* err_fro, double* a_fro,
-                         void* work, int64_t work_bytes, void* hip_stream);
+int64_t qrcp_work_bytes(int64_t m, int64_t n, int64_t k_max, mps_precision prec, mps_pivot mode);
+mps_status qrcp_truncate(int64_t m, int64_t n, int64_t k_max, mps_precision prec, mps_pivot mode,
+                         const mps_learned_cfg* learned, const void* A, int64_t lda, void* Q, int64_t ldq,
+                         void* RPt, int64_t ldr, int32_t* piv, double* diagR, int64_t* k_out, double* err_fro,
+                         double* a_fro, mps_update_info* info, void* work, int64_t work_bytes, void* hip_stream);
 
 /* ------------------------------------------------------------------------
  * mps_update_bond -- one two-site update on explicit site tensors
@@ -192,13 +215,28 @@ typedef struct {
     int32_t sketch_rows;   /* learned pivots: rows of the Gaussian sketch */
     int32_t pad;
     uint64_t seed;
+    /* learned pivots, optional: the proposal network's parameters (device,
+     * MPS_PIVNET_PARAMS float32, must stay valid) and the acceptance rule
+     * (learned_verify 0: certificate, 1: verification against plain pivoted
+     * QR).  NULL leaves the network unset until mps_set_pivot_network. */
+    const float* mlp_weights;
+    int32_t learned_verify;
+    int32_t pad2;
 } mps_config;
 
-/* Device bytes the arena of mps_create must provide for this configuration. */
+/* Device bytes the arena of mps_create must provide for this configuration:
+ * one slot per site sized for its largest bond dimensions min(2^b, 2^(n-b),
+ * chi_max) (the bond bound of the MPS form, Sec. II-B, Eq. (2)), then the
+ * workspace of the largest two-site update (Sec. III-C.2).  -1 for an
+ * invalid configuration. */
 int64_t mps_arena_bytes(const mps_config* cfg);
 
-/* The arena (device, >= mps_arena_bytes) stays owned by the caller and must
- * outlive the context; the stream is used by every later call on it. */
+/* A new MPS (Sec. II-B, Eq. (2)) in the product state |0...0> with every bond
+ * dimension 1 and the orthogonality centre on site 0 (a product state is in
+ * canonical form, Sec. III-C.1).  The arena (device, >= mps_arena_bytes)
+ * stays owned by the caller and must outlive the context; the stream is used
+ * by every later call on it.  Errors: MPS_EINVAL (configuration, null
+ * pointers), MPS_ENOMEM (arena too small). */
 mps_status mps_create(const mps_config* cfg, void* dev_arena, int64_t arena_bytes, void* hip_stream,
                       mps_ctx** out);
 mps_status mps_destroy(mps_ctx* ctx);
@@ -215,10 +253,11 @@ mps_status mps_set_pivot_network(mps_ctx* ctx, const mps_learned_cfg* cfg);
  * runs and the centre ends on site i+1.  info (host) may be NULL. */
 mps_status mps_apply_gate(mps_ctx* ctx, int32_t i, const double* g, mps_update_info* info);
 
-/* Apply n gates on pairwise disjoint bonds (i[t] + 1 < i[t+1]), in array
- * order, with the semantics of n calls of mps_apply_gate.  g: n x 32 doubles;
- * info: n entries or NULL.  Overlapping or unsorted bonds: MPS_EINVAL, no
- * state change. */
+/* Apply one layer of two-site gates (Sec. III-C.2, tensor application; a
+ * circuit layer acts on disjoint neighbouring pairs, Sec. III-D) on pairwise
+ * disjoint bonds (i[t] + 1 < i[t+1]), in array order, with the semantics of n
+ * calls of mps_apply_gate.  g: n x 32 doubles; info: n entries or NULL.
+ * Overlapping or unsorted bonds: MPS_EINVAL, no state change. */
 mps_status mps_apply_layer(mps_ctx* ctx, int64_t n, const int32_t* i, const double* g,
                            mps_update_info* info);
 
@@ -258,7 +297,7 @@ mps_status mps_set_tuning(int32_t panel_width, int32_t qr_window);
  * Small-bond chains, process-wide (not thread-safe; affects later calls).
  * mps_apply_gate / mps_apply_layer run a gate sequence as the ordered chain
  * of centre moves (unpivoted QR / LQ, Sec. III-C.1) and two-site updates
- * (Sec. III-C.3) that sequential application defines.  Every maximal run of
+ * (Sec. III-C.2) that sequential application defines.  Every maximal run of
  * consecutive operations whose bond dimensions are all <= max_dim executes
  * as ONE kernel launch: a single workgroup performs the run's moves and
  * updates in order, in FP64 on workspace copies (contraction and gate,

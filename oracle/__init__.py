@@ -36,7 +36,9 @@ Pieces and the passages they follow (arXiv 2505.06119):
 Where the paper is silent the oracle takes these readings: site 0 is the most
 significant qubit; the gate's row index is 2a'+b' with a on the lower site;
 theta's column index is 2r + b' (the right site's physical index runs
-fastest), and equal residual norms go to the smallest such column; the truncation rank
+fastest), and equal residual norms go to the smallest such column, where
+"equal" means equal after rounding the FP64 squared norms to 40 significant
+bits; the truncation rank
 is k = min(chi_cap, m, n) with no tolerance cut-off; the orthogonality centre
 is moved to site i (or i+1 when it lies right of i) before each update and the
 split leaves Q on the left site.

@@ -14,7 +14,10 @@
  *   norm.  The residual norms are recomputed exactly at every step from the
  *   current trailing block -- no norm downdating -- so the pivot rule is the
  *   greedy definition written out.  Equal norms go to the smallest original
- *   column index.
+ *   column index.  "Equal" is read at 40 significant bits: the squared norms
+ *   are compared after rounding off the low 12 bits of their FP64 mantissa,
+ *   so a tie that is exact in exact arithmetic resolves by index whatever
+ *   last-bit rounding the summation left (see pivot_key).
  *
  *   Householder convention (LAPACK xLARFG): for x = (alpha, x_rest),
  *     if x_rest = 0 and Im(alpha) = 0:  tau = 0 (H = I), beta = alpha;
@@ -33,6 +36,20 @@
 typedef double _Complex cplx;
 
 static double abs2(cplx z) { return creal(z) * creal(z) + cimag(z) * cimag(z); }
+
+/* A non-negative squared norm rounded to the nearest value with 40
+ * significant mantissa bits (the low 12 bits rounded off): values within
+ * about 2^-41 relative compare equal.  Rounding to nearest keeps simple
+ * values such as 1/2 in the middle of their interval, so last-bit rounding
+ * on either side of them does not separate them. */
+static double pivot_key(double v)
+{
+    uint64_t b;
+    memcpy(&b, &v, sizeof b);
+    b = (b + (uint64_t)0x800) & ~(uint64_t)0xfff;
+    memcpy(&v, &b, sizeof v);
+    return v;
+}
 
 /* Generate the reflector for x[0..len-1] in place: x[0] <- beta, x[1:] <- v[1:].
  * Returns tau. */
@@ -98,9 +115,11 @@ int orc_qrcp(int64_t m, int64_t n, int64_t kmax, int pivoting,
                 nrm[c] = s;
             }
             int64_t best = j;
-            for (int64_t c = j + 1; c < n; ++c)
-                if (nrm[c] > nrm[best] || (nrm[c] == nrm[best] && piv[c] < piv[best]))
+            for (int64_t c = j + 1; c < n; ++c) {
+                const double kc = pivot_key(nrm[c]), kb = pivot_key(nrm[best]);
+                if (kc > kb || (kc == kb && piv[c] < piv[best]))
                     best = c;
+            }
             if (gaps) {
                 double second = -1.0;
                 for (int64_t c = j; c < n; ++c)

@@ -98,82 +98,98 @@ static int64_t update_ws_bytes(int64_t m, int64_t n, int64_t k)
     return cv.used + 256;
 }
 
+// two-site update, learned proposal entry points
+#include "bond.hpp"
+
 // ---------------------------------------------------------------------------
 // qrcp_truncate
 // ---------------------------------------------------------------------------
-extern "C" int64_t qrcp_work_bytes(int64_t m, int64_t n, int64_t k_max, mps_precision prec)
+extern "C" int64_t qrcp_work_bytes(int64_t m, int64_t n, int64_t k_max, mps_precision prec, mps_pivot mode)
 {
     if (m < 0 || n < 0 || k_max < 0 || !valid_prec(prec)) return -1;
+    if (mode != MPS_PIVOT_QRCP && mode != MPS_PIVOT_LEARNED) return -1;
     int64_t k = k_max < m ? k_max : m;
     k = k < n ? k : n;
-    return prec == MPS_FP64 ? update_ws_bytes<double2>(m, n, k) : update_ws_bytes<float2>(m, n, k);
+    int64_t b = prec == MPS_FP64 ? update_ws_bytes<double2>(m, n, k) : update_ws_bytes<float2>(m, n, k);
+    if (mode == MPS_PIVOT_LEARNED)
+        b += prec == MPS_FP64 ? learn_ws_bytes<double2>(m, n, k, PN_ELL_MAX) : learn_ws_bytes<float2>(m, n, k, PN_ELL_MAX);
+    return b;
 }
 
 template <typename T>
-static mps_status qrcp_impl(int64_t m, int64_t n, int64_t k, mps_precision prec, const void* A, int64_t lda,
-                            void* Q, int64_t ldq, void* RPt, int64_t ldr, int32_t* piv, double* diagR,
-                            int64_t* k_out, double* err_fro, double* a_fro, void* work, int64_t work_bytes,
-                            hipStream_t st)
+static mps_status qrcp_impl(int64_t m, int64_t n, int64_t k, mps_precision prec, const mps_learned_cfg* lc,
+                            const void* A, int64_t lda, void* Q, int64_t ldq, void* RPt, int64_t ldr, int32_t* piv,
+                            double* diagR, int64_t* k_out, double* err_fro, double* a_fro, mps_update_info* info,
+                            void* work, int64_t work_bytes, hipStream_t st)
 {
     Carver cv{(char*)work, work_bytes, 0};
     UpdateWs<T> w;
     if (!carve_update_ws<T>(cv, w, m, n, k, true))
         return fail(MPS_ENOMEM, "qrcp_truncate: work_bytes %lld too small", (long long)work_bytes);
+    LearnWs<T> L;
+    if (lc && !carve_learn_ws<T>(cv, L, m, n, k, lc->sketch_rows))
+        return fail(MPS_ENOMEM, "qrcp_truncate: work_bytes %lld too small for learned pivots", (long long)work_bytes);
     w.nb = panel_width(m, n);
     w.win = qr_window(w.nb);
     w.d.tol = recompute_tol(prec);
     w.d.pivoting = 1;
-    if (n > 0 && m > 0) {
+    {
         dim3 grid((unsigned)(rup(m, 256) < 64 ? rup(m, 256) : 64), (unsigned)n);
         hipLaunchKernelGGL((k_copy_cols<T>), grid, dim3(256), 0, st, (const T*)A, lda, w.d.A, w.d.lda, m);
     }
     const int nparts = init_norms<T>(w, st);
     HIPCHK(hipGetLastError(), "qrcp_truncate launch");
-    QrcpStats stats;
-    if (k > 0) HIPCHK(run_qrcp<T>(w, st, &stats, nparts), "qrcp_truncate factorisation");
-    if (k > 0) {
-        HIPCHK(form_q<T>(w, (T*)Q, ldq, st), "qrcp_truncate Q");
-        hipLaunchKernelGGL((k_rpt<T>), dim3((unsigned)n), dim3(256), 0, st, (const T*)w.d.A, w.d.lda,
-                           (const int32_t*)w.d.perm, k, n, (T*)RPt, ldr, (const double*)w.d.dsc, 0);
-        HIPCHK(hipMemcpyAsync(diagR, w.d.diagR, sizeof(double) * k, hipMemcpyDeviceToDevice, st), "diagR");
-    }
-    if (n > 0) HIPCHK(hipMemcpyAsync(piv, w.d.perm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st), "piv");
+    FactorOut<T> f;
+    mps_status s = factorise<T>(w, lc ? &L : nullptr, lc, nparts, st, f);
+    if (s != MPS_OK) return s;
+    QrcpDev<T>& du = f.use->d;
+    HIPCHK(form_q<T>(*f.use, (T*)Q, ldq, st), "qrcp_truncate Q");
+    hipLaunchKernelGGL((k_rpt<T>), dim3((unsigned)n), dim3(256), 0, st, (const T*)du.A, du.lda,
+                       (const int32_t*)du.perm, k, n, (T*)RPt, ldr, (const double*)du.dsc, 0);
+    HIPCHK(hipMemcpyAsync(diagR, du.diagR, sizeof(double) * k, hipMemcpyDeviceToDevice, st), "diagR");
+    HIPCHK(hipMemcpyAsync(piv, du.perm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st), "piv");
     double dsc[DSC_COUNT];
-    HIPCHK(hipMemcpyAsync(dsc, w.d.dsc, sizeof(dsc), hipMemcpyDeviceToHost, st), "qrcp_truncate readback");
+    HIPCHK(hipMemcpyAsync(dsc, du.dsc, sizeof(dsc), hipMemcpyDeviceToHost, st), "qrcp_truncate readback");
     HIPCHK(hipStreamSynchronize(st), "qrcp_truncate sync");
+    prof_flush();
+    if (!isfinite(dsc[DSC_NORM2]) || !isfinite(dsc[DSC_EPS2])) return fail(MPS_ENUMERIC, "qrcp_truncate: non-finite input");
     if (k_out) *k_out = k;
     if (err_fro) *err_fro = sqrt(dsc[DSC_EPS2] > 0 ? dsc[DSC_EPS2] : 0.0);
     if (a_fro) *a_fro = sqrt(dsc[DSC_NORM2]);
-    if (!isfinite(dsc[DSC_NORM2])) return fail(MPS_ENUMERIC, "qrcp_truncate: non-finite input");
+    fill_info<T>(info, k, dsc, f, lc != nullptr);
     return MPS_OK;
 }
 
-extern "C" mps_status qrcp_truncate(int64_t m, int64_t n, int64_t k_max, mps_precision prec, const void* A,
-                                    int64_t lda, void* Q, int64_t ldq, void* RPt, int64_t ldr, int32_t* piv,
-                                    double* diagR, int64_t* k_out, double* err_fro, double* a_fro, void* work,
+extern "C" mps_status qrcp_truncate(int64_t m, int64_t n, int64_t k_max, mps_precision prec, mps_pivot mode,
+                                    const mps_learned_cfg* learned, const void* A, int64_t lda, void* Q, int64_t ldq,
+                                    void* RPt, int64_t ldr, int32_t* piv, double* diagR, int64_t* k_out,
+                                    double* err_fro, double* a_fro, mps_update_info* info, void* work,
                                     int64_t work_bytes, void* hip_stream)
 {
     if (m < 1 || n < 1 || k_max < 1) return fail(MPS_EINVAL, "qrcp_truncate: m, n, k_max must be >= 1");
     if (!valid_prec(prec)) return fail(MPS_EINVAL, "qrcp_truncate: bad precision %d", (int)prec);
+    if (mode != MPS_PIVOT_QRCP && mode != MPS_PIVOT_LEARNED)
+        return fail(MPS_EINVAL, "qrcp_truncate: bad pivot mode %d", (int)mode);
+    if (mode == MPS_PIVOT_LEARNED && !learned_cfg_valid(learned))
+        return fail(MPS_EINVAL, "qrcp_truncate: learned pivots need a valid mps_learned_cfg");
     if (m > (1 << 20) || n > (1 << 20)) return fail(MPS_EINVAL, "qrcp_truncate: dimension too large");
     int64_t k = k_max < m ? k_max : m;
     k = k < n ? k : n;
     if (!A || !Q || !RPt || !piv || !diagR || !work)
         return fail(MPS_EINVAL, "qrcp_truncate: null device pointer");
     if (lda < m || ldq < m || ldr < k) return fail(MPS_EINVAL, "qrcp_truncate: leading dimension too small");
-    if (work_bytes < qrcp_work_bytes(m, n, k_max, prec))
-        return fail(MPS_ENOMEM, "qrcp_truncate: need %lld work bytes, got %lld",
-                    (long long)qrcp_work_bytes(m, n, k_max, prec), (long long)work_bytes);
+    const int64_t need = qrcp_work_bytes(m, n, k_max, prec, mode);
+    if (work_bytes < need)
+        return fail(MPS_ENOMEM, "qrcp_truncate: need %lld work bytes, got %lld", (long long)need,
+                    (long long)work_bytes);
     hipStream_t st = (hipStream_t)hip_stream;
+    const mps_learned_cfg* lc = mode == MPS_PIVOT_LEARNED ? learned : nullptr;
     if (prec == MPS_FP64)
-        return qrcp_impl<double2>(m, n, k, prec, A, lda, Q, ldq, RPt, ldr, piv, diagR, k_out, err_fro, a_fro,
-                                  work, work_bytes, st);
-    return qrcp_impl<float2>(m, n, k, prec, A, lda, Q, ldq, RPt, ldr, piv, diagR, k_out, err_fro, a_fro, work,
-                             work_bytes, st);
+        return qrcp_impl<double2>(m, n, k, prec, lc, A, lda, Q, ldq, RPt, ldr, piv, diagR, k_out, err_fro, a_fro,
+                                  info, work, work_bytes, st);
+    return qrcp_impl<float2>(m, n, k, prec, lc, A, lda, Q, ldq, RPt, ldr, piv, diagR, k_out, err_fro, a_fro, info,
+                             work, work_bytes, st);
 }
-
-// two-site update, learned proposal entry points
-#include "bond.hpp"
 
 // stateful MPS context
 #include "context.hpp"

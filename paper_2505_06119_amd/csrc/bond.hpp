@@ -86,6 +86,120 @@ __global__ void k_copy_norm2(const double* src, double* dst)
     if (threadIdx.x == 0) dst[DSC_NORM2] = src[DSC_NORM2];
 }
 
+// Result of the factorisation step: the workspace whose factors are kept
+// (the plain or the learned one), the QR statistics and the acceptance data.
+template <typename T>
+struct FactorOut {
+    UpdateWs<T>* use = nullptr;
+    QrcpStats stats;
+    int fallback = 0;
+    double eps_s2 = -1.0, eps_q2 = -1.0;
+};
+
+// ||A||^2 of the matrix in d after its norm kernels: one readback, taken
+// before the learned proposal so that a non-finite input is refused before
+// anything depends on its ranking.
+template <typename T>
+static hipError_t read_norm2(const QrcpDev<T>& d, hipStream_t st, double* out)
+{
+    hipError_t e = hipMemcpyAsync(out, d.dsc + DSC_NORM2, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(st);
+    prof_flush();
+    return e;
+}
+
+// a4-a10 (plain pivoted QR) or a15-a18 (learned proposal, QR with the proposed
+// order fixed, acceptance, fallback) on the matrix in w.d.A, whose column
+// norms, argmax partials (nparts of them) and ||A||^2 are in place.  L and lc
+// are null for plain pivoted QR.
+template <typename T>
+static mps_status factorise(UpdateWs<T>& w, LearnWs<T>* L, const mps_learned_cfg* lc, int nparts, hipStream_t st,
+                            FactorOut<T>& out)
+{
+    QrcpDev<T>& d = w.d;
+    const int64_t m = d.m, n = d.n, k = d.k;
+    out.use = &w;
+    if (!lc) {
+        HIPCHK(run_qrcp<T>(w, st, &out.stats, nparts), "pivoted QR");
+        return MPS_OK;
+    }
+    double n2 = 0.0;
+    HIPCHK(read_norm2<T>(d, st, &n2), "norm readback");
+    if (!isfinite(n2)) return fail(MPS_ENUMERIC, "learned pivots: non-finite input");
+    // a15-a17: proposal, then QR with the proposed order fixed
+    hipEvent_t ep = prof_begin(st);
+    HIPCHK(propose_order<T>(d, *L, lc, w.gsplit, w.gsplit_bytes, st), "learned proposal");
+    QrcpDev<T>& d2 = L->w2.d;
+    dim3 ggrid((unsigned)(rup(m, 256) < 64 ? rup(m, 256) : 64), (unsigned)n);
+    hipLaunchKernelGGL((k_gather_cols<T>), ggrid, dim3(256), 0, st, (const T*)d.A, d.lda, d2.A, d2.lda, m,
+                       (const int32_t*)L->order, d2.perm, n);
+    prof_end(ep, st, PK_PROPOSE, (double)sizeof(T) * 3.0 * (double)m * (double)n,
+             8.0 * (double)lc->sketch_rows * (double)m * (double)n);
+    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, st, d2.ctl, d2.dsc);
+    hipLaunchKernelGGL(k_copy_norm2, dim3(1), dim3(64), 0, st, (const double*)d.dsc, d2.dsc);
+    L->w2.nb = w.nb;
+    L->w2.win = w.win;
+    d2.tol = 0.0;
+    d2.pivoting = 0;
+    QrcpStats s2;
+    HIPCHK(run_qrcp<T>(L->w2, st, &s2, 0), "known-order QR");
+    // a18: certificate = (largest squared residual norm of an unselected
+    // column, smallest |R_jj| of a selected one)
+    int nblk = 0;
+    if (m > k && n > k) {
+        nblk = (int)rup(n - k, QR_CW);
+        hipLaunchKernelGGL((k_colnorms<T>), dim3((unsigned)nblk), dim3(256), 0, st, d2, k, k, 1, 0);
+    }
+    hipLaunchKernelGGL(k_certificate, dim3(1), dim3(256), 0, st, (const ArgBest*)d2.cpart, nblk,
+                       (const double*)d2.diagR, k, L->cert);
+    double cert[2], dsc2[DSC_COUNT];
+    HIPCHK(hipMemcpyAsync(cert, L->cert, sizeof(cert), hipMemcpyDeviceToHost, st), "certificate readback");
+    HIPCHK(hipMemcpyAsync(dsc2, d2.dsc, sizeof(dsc2), hipMemcpyDeviceToHost, st), "certificate readback");
+    HIPCHK(hipStreamSynchronize(st), "certificate sync");
+    prof_flush();
+    out.eps_s2 = dsc2[DSC_EPS2];
+    bool accept;
+    if (lc->verify) {
+        HIPCHK(run_qrcp<T>(w, st, &out.stats, nparts), "verification QRCP");
+        double dq[DSC_COUNT];
+        HIPCHK(hipMemcpyAsync(dq, d.dsc, sizeof(dq), hipMemcpyDeviceToHost, st), "verification readback");
+        HIPCHK(hipStreamSynchronize(st), "verification sync");
+        prof_flush();
+        out.eps_q2 = dq[DSC_EPS2];
+        const double r2 = lc->fallback_ratio * lc->fallback_ratio;
+        accept = out.eps_s2 <= r2 * out.eps_q2 + 1e-300;
+    } else {
+        accept = cert[0] <= cert[1] * cert[1] * (1.0 + 1e-12);
+    }
+    if (accept) {
+        out.use = &L->w2;
+        out.stats = s2;
+    } else {
+        out.fallback = 1;
+        if (!lc->verify) HIPCHK(run_qrcp<T>(w, st, &out.stats, nparts), "fallback QRCP");
+    }
+    return MPS_OK;
+}
+
+template <typename T>
+static void fill_info(mps_update_info* info, int64_t k, const double* dsc, const FactorOut<T>& f, bool learned)
+{
+    if (!info) return;
+    info->k = k;
+    info->trunc_err_sq = dsc[DSC_EPS2];
+    info->norm_sq = dsc[DSC_NORM2];
+    info->retained = dsc[DSC_NORM2] > 0 ? 1.0 - dsc[DSC_EPS2] / dsc[DSC_NORM2] : 1.0;
+    info->fallback = f.fallback;
+    info->panels = f.stats.panels;
+    info->refreshes = f.stats.refreshes;
+    info->window_misses = f.stats.window_misses;
+    info->learned_err_sq = f.eps_s2;
+    // plain pivoted QR's error: measured by the verification, or the kept
+    // result itself when plain pivoted QR produced it
+    info->qrcp_err_sq = !learned || f.fallback ? dsc[DSC_EPS2] : f.eps_q2;
+}
+
 // theta is formed in the workspace before any output is written, so the
 // outputs may alias the input sites.
 template <typename T>
@@ -125,69 +239,11 @@ static mps_status update_core(int64_t chi_l, int64_t chi_m, int64_t chi_r, int64
     prof_end(e2, st, PK_GATE, 2.0 * sizeof(T) * (double)m * (double)n, 64.0 * (double)m * (double)n / 4.0);
     HIPCHK(hipGetLastError(), "update launch");
 
-    QrcpStats stats;
-    UpdateWs<T>* use = &w;            // factorisation whose result is returned
-    int fallback = 0;
-    double eps_s2 = -1.0, eps_q2 = -1.0;
-    if (lc) {
-        // a15-a17: proposal, then pivoted QR with the proposed order fixed
-        hipEvent_t ep = prof_begin(st);
-        HIPCHK(propose_order<T>(d, L, lc, w.gsplit, w.gsplit_bytes, st), "learned proposal");
-        QrcpDev<T>& d2 = L.w2.d;
-        dim3 ggrid((unsigned)(rup(m, 256) < 64 ? rup(m, 256) : 64), (unsigned)n);
-        hipLaunchKernelGGL((k_gather_cols<T>), ggrid, dim3(256), 0, st, (const T*)d.A, d.lda, d2.A, d2.lda, m,
-                           (const int32_t*)L.order, d2.perm);
-        prof_end(ep, st, PK_PROPOSE, (double)sizeof(T) * 3.0 * (double)m * (double)n,
-                 8.0 * (double)lc->sketch_rows * (double)m * (double)n);
-        hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, st, d2.ctl, d2.dsc);
-        hipLaunchKernelGGL(k_copy_norm2, dim3(1), dim3(64), 0, st, (const double*)d.dsc, d2.dsc);
-        L.w2.nb = panel_width(m, n);
-        d2.tol = 0.0;
-        d2.pivoting = 0;
-        QrcpStats s2;
-        HIPCHK(run_qrcp<T>(L.w2, st, &s2, 0), "known-order QR");
-        // a18: certificate = (largest squared residual norm of an unselected
-        // column, smallest |R_jj| of a selected one)
-        int nblk = 0;
-        if (m > k && n > k) {
-            nblk = (int)rup(n - k, QR_CW);
-            hipLaunchKernelGGL((k_colnorms<T>), dim3((unsigned)nblk), dim3(256), 0, st, d2, k, k, 1, 0);
-        }
-        hipLaunchKernelGGL(k_certificate, dim3(1), dim3(256), 0, st, (const ArgBest*)d2.cpart, nblk,
-                           (const double*)d2.diagR, k, L.cert);
-        double cert[2], dsc2[DSC_COUNT];
-        HIPCHK(hipMemcpyAsync(cert, L.cert, sizeof(cert), hipMemcpyDeviceToHost, st), "certificate readback");
-        HIPCHK(hipMemcpyAsync(dsc2, d2.dsc, sizeof(dsc2), hipMemcpyDeviceToHost, st), "certificate readback");
-        HIPCHK(hipStreamSynchronize(st), "certificate sync");
-        prof_flush();
-        eps_s2 = dsc2[DSC_EPS2];
-        bool accept;
-        if (lc->verify) {
-            HIPCHK(run_qrcp<T>(w, st, &stats, (int)chi_r), "verification QRCP");
-            double dq[DSC_COUNT];
-            HIPCHK(hipMemcpyAsync(dq, d.dsc, sizeof(dq), hipMemcpyDeviceToHost, st), "verification readback");
-            HIPCHK(hipStreamSynchronize(st), "verification sync");
-            prof_flush();
-            eps_q2 = dq[DSC_EPS2];
-            const double r2 = lc->fallback_ratio * lc->fallback_ratio;
-            accept = eps_s2 <= r2 * eps_q2 + 1e-300;
-        } else {
-            accept = cert[0] <= cert[1] * cert[1] * (1.0 + 1e-12);
-        }
-        if (accept) {
-            use = &L.w2;
-            stats = s2;
-        } else {
-            fallback = 1;
-            if (!lc->verify) {
-                HIPCHK(run_qrcp<T>(w, st, &stats, (int)chi_r), "fallback QRCP");
-            }
-        }
-    } else {
-        HIPCHK(run_qrcp<T>(w, st, &stats, (int)chi_r), "update factorisation");
-    }
-    QrcpDev<T>& du = use->d;
-    HIPCHK(form_q<T>(*use, A_out, m, st), "update Q");
+    FactorOut<T> f;
+    mps_status s = factorise<T>(w, lc ? &L : nullptr, lc, (int)chi_r, st, f);
+    if (s != MPS_OK) return s;
+    QrcpDev<T>& du = f.use->d;
+    HIPCHK(form_q<T>(*f.use, A_out, m, st), "update Q");
     hipEvent_t e3 = prof_begin(st);
     hipLaunchKernelGGL((k_rpt<T>), dim3((unsigned)n), dim3(256), 0, st, (const T*)du.A, du.lda,
                        (const int32_t*)du.perm, k, n, B_out, k, (const double*)du.dsc, renorm);
@@ -198,19 +254,7 @@ static mps_status update_core(int64_t chi_l, int64_t chi_m, int64_t chi_r, int64
     prof_flush();
     if (!isfinite(dsc[DSC_NORM2]) || !isfinite(dsc[DSC_EPS2]))
         return fail(MPS_ENUMERIC, "update: non-finite theta");
-    if (lc && fallback) eps_q2 = dsc[DSC_EPS2];
-    if (info) {
-        info->k = k;
-        info->trunc_err_sq = dsc[DSC_EPS2];
-        info->norm_sq = dsc[DSC_NORM2];
-        info->retained = dsc[DSC_NORM2] > 0 ? 1.0 - dsc[DSC_EPS2] / dsc[DSC_NORM2] : 1.0;
-        info->fallback = fallback;
-        info->panels = stats.panels;
-        info->refreshes = stats.refreshes;
-        info->window_misses = stats.window_misses;
-        info->learned_err_sq = eps_s2;
-        info->qrcp_err_sq = lc ? eps_q2 : dsc[DSC_EPS2];
-    }
+    fill_info<T>(info, k, dsc, f, lc != nullptr);
     return MPS_OK;
 }
 

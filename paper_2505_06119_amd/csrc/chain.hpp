@@ -4,7 +4,7 @@
 // operations: before each two-site update the orthogonality centre moves to
 // the bond by unpivoted QR (to the right) or LQ (to the left) of the sites on
 // the way, then the update contracts, pivots, truncates and splits (paper
-// Sec. III-C.1 and III-C.3; the ordering reading is the sequential one).  Near
+// Sec. III-C.1 and III-C.2; the ordering reading is the sequential one).  Near
 // the ends of the chain the bonds are small (2, 4, 8, ...), and on the
 // multi-kernel path such an operation costs launch and host-synchronisation
 // latency, not arithmetic.  Here one workgroup runs a whole run of

@@ -171,11 +171,31 @@ struct ArgBest {
     int32_t slot;
 };
 
+// Pivot comparisons see a non-negative squared residual norm rounded to the
+// nearest value with 40 significant mantissa bits (the low 12 bits rounded
+// off): norms that agree to about 2^-41 relative count as equal and the
+// smaller key wins.  A tie that is exact in exact arithmetic then resolves by
+// key whatever last-bit rounding the evaluation of the two norms carried;
+// rounding to nearest keeps simple values such as 1/2 or 1/4 in the middle of
+// their interval, where a few ulps either way do not move them out of it.
+__device__ __forceinline__ double pivot_key(double v)
+{
+    return __longlong_as_double((__double_as_longlong(v) + 0x800LL) & ~0xfffLL);
+}
+
 __device__ __forceinline__ bool arg_better(double v1, int32_t k1, double v2, int32_t k2)
+{
+    const double a = pivot_key(v1), b = pivot_key(v2);
+    return a > b || (a == b && k1 < k2);
+}
+
+// The same order on the exact values (for maxima that are not pivot choices).
+__device__ __forceinline__ bool arg_better_exact(double v1, int32_t k1, double v2, int32_t k2)
 {
     return v1 > v2 || (v1 == v2 && k1 < k2);
 }
 
+template <bool EXACT = false>
 __device__ __forceinline__ ArgBest wave_argmax(ArgBest a)
 {
 #pragma unroll
@@ -183,22 +203,27 @@ __device__ __forceinline__ ArgBest wave_argmax(ArgBest a)
         double v = __shfl_xor(a.val, off, MPS_WAVE);
         int32_t k = __shfl_xor(a.key, off, MPS_WAVE);
         int32_t s = __shfl_xor(a.slot, off, MPS_WAVE);
-        if (arg_better(v, k, a.val, a.key)) { a.val = v; a.key = k; a.slot = s; }
+        const bool better = EXACT ? arg_better_exact(v, k, a.val, a.key) : arg_better(v, k, a.val, a.key);
+        if (better) { a.val = v; a.key = k; a.slot = s; }
     }
     return a;
 }
 
-// Block (256 threads) argmax; result valid in every thread.
+// Block (256 threads) argmax; result valid in every thread.  EXACT: on the
+// exact values instead of the pivot comparison.
+template <bool EXACT = false>
 __device__ __forceinline__ ArgBest block_argmax256(ArgBest a, ArgBest* scratch)
 {
-    a = wave_argmax(a);
+    a = wave_argmax<EXACT>(a);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     __syncthreads();
     if (lane == 0) scratch[wid] = a;
     __syncthreads();
     ArgBest b = scratch[0];
-    for (int w = 1; w < 4; ++w)
-        if (arg_better(scratch[w].val, scratch[w].key, b.val, b.key)) b = scratch[w];
+    for (int w = 1; w < 4; ++w) {
+        const bool better = EXACT ? arg_better_exact(scratch[w].val, scratch[w].key, b.val, b.key)
+                                  : arg_better(scratch[w].val, scratch[w].key, b.val, b.key);
+        if (better) b = scratch[w];
+    }
     return b;
 }
-

@@ -168,6 +168,17 @@ extern "C" mps_status mps_create(const mps_config* cfg, void* dev_arena, int64_t
     *out = nullptr;
     if (!cfg_valid(cfg)) return fail(MPS_EINVAL, "mps_create: invalid configuration");
     if (!dev_arena) return fail(MPS_EINVAL, "mps_create: arena is NULL");
+    if (cfg->pivot == MPS_PIVOT_LEARNED && cfg->mlp_weights) {
+        mps_learned_cfg lc;
+        lc.params = cfg->mlp_weights;
+        lc.sketch_rows = cfg->sketch_rows;
+        lc.verify = cfg->learned_verify;
+        lc.seed = cfg->seed;
+        lc.fallback_ratio = cfg->fallback_ratio;
+        if (!learned_cfg_valid(&lc))
+            return fail(MPS_EINVAL, "mps_create: invalid learned-pivot settings (sketch_rows, learned_verify, "
+                                    "fallback_ratio)");
+    }
     CtxLayout L;
     ctx_layout(cfg, L);
     if (arena_bytes < L.total)
@@ -198,6 +209,14 @@ extern "C" mps_status mps_create(const mps_config* cfg, void* dev_arena, int64_t
     c->log_fid = 0.0;
     c->poisoned = false;
     c->has_net = false;
+    if (cfg->pivot == MPS_PIVOT_LEARNED && cfg->mlp_weights) {
+        c->lcfg.params = cfg->mlp_weights;
+        c->lcfg.sketch_rows = cfg->sketch_rows;
+        c->lcfg.verify = cfg->learned_verify;
+        c->lcfg.seed = cfg->seed;
+        c->lcfg.fallback_ratio = cfg->fallback_ratio;
+        c->has_net = true;
+    }
     c->trunc = MPS_TRUNC_QRCP;
     mps_status s = c->prec == MPS_FP64 ? ctx_init_sites<double2>(c) : ctx_init_sites<float2>(c);
     if (s != MPS_OK) {
@@ -514,7 +533,8 @@ extern "C" mps_status mps_set_pivot_network(mps_ctx* ctx, const mps_learned_cfg*
 static mps_status ctx_check(const mps_ctx* c)
 {
     if (!c) return fail(MPS_EINVAL, "NULL context");
-    if (c->poisoned) return fail(MPS_ESTATE, "context unusable after an earlier device failure");
+    if (c->poisoned)
+        return fail(MPS_ESTATE, "context unusable after an earlier device failure or non-finite result");
     return MPS_OK;
 }
 
@@ -530,7 +550,8 @@ extern "C" mps_status mps_apply_gate(mps_ctx* ctx, int32_t i, const double* g, m
     const int32_t one = i;
     s = ctx->prec == MPS_FP64 ? ctx_run_gates<double2>(ctx, 1, &one, g, info)
                               : ctx_run_gates<float2>(ctx, 1, &one, g, info);
-    if (s == MPS_EDEVICE) ctx->poisoned = true;
+    // a non-finite theta has already rewritten sites: the state is lost
+    if (s == MPS_EDEVICE || s == MPS_ENUMERIC) ctx->poisoned = true;
     return s;
 }
 
@@ -551,7 +572,7 @@ extern "C" mps_status mps_apply_layer(mps_ctx* ctx, int64_t n, const int32_t* id
     }
     if (n == 0) return MPS_OK;
     s = ctx->prec == MPS_FP64 ? ctx_run_gates<double2>(ctx, n, idx, g, info) : ctx_run_gates<float2>(ctx, n, idx, g, info);
-    if (s == MPS_EDEVICE) ctx->poisoned = true;
+    if (s == MPS_EDEVICE || s == MPS_ENUMERIC) ctx->poisoned = true;
     return s;
 }
 

@@ -68,14 +68,14 @@ __global__ __launch_bounds__(256) void k_sketch_stats(const double* s, int64_t n
     b.slot = -1;
     for (int64_t c = threadIdx.x; c < n; c += 256) {
         sum += s[c];
-        if (arg_better(s[c], (int32_t)c, b.val, b.key)) {
+        if (arg_better_exact(s[c], (int32_t)c, b.val, b.key)) {
             b.val = s[c];
             b.key = (int32_t)c;
             b.slot = (int32_t)c;
         }
     }
     sum = block_sum256(sum, red);
-    b = block_argmax256(b, arg_lds);
+    b = block_argmax256<true>(b, arg_lds);
     if (threadIdx.x == 0) {
         stats[0] = n > 0 ? sum / (double)n : 0.0;
         stats[1] = b.val;
@@ -194,17 +194,21 @@ __global__ __launch_bounds__(128) void k_pn_adam(float* params, const float* gra
 }
 
 // order[rank(c)] = c, rank(c) = #{c' : score[c'] > score[c] or (== and c' < c)}.
-// Exact ranking by counting, in LDS tiles of the score vector.
+// Exact ranking by counting, in LDS tiles of the score vector.  A NaN score
+// counts as -infinity, so the ranks stay a permutation of 0..n-1 (every order
+// slot is written) whatever the scores hold.
+__device__ __forceinline__ float rank_key(float v) { return v != v ? -INFINITY : v; }
+
 __global__ __launch_bounds__(256) void k_rank_desc(const float* scores, int64_t n, int32_t* order)
 {
     __shared__ float tile[1024];
     const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const float sc = c < n ? scores[c] : 0.f;
+    const float sc = c < n ? rank_key(scores[c]) : 0.f;
     int64_t rank = 0;
     for (int64_t t0 = 0; t0 < n; t0 += 1024) {
         __syncthreads();
         for (int q = threadIdx.x; q < 1024; q += 256)
-            tile[q] = (t0 + q < n) ? scores[t0 + q] : -INFINITY;
+            tile[q] = (t0 + q < n) ? rank_key(scores[t0 + q]) : -INFINITY;
         __syncthreads();
         const int64_t lim = (n - t0) < 1024 ? (n - t0) : 1024;
         for (int q = 0; q < lim; ++q) {
@@ -216,13 +220,15 @@ __global__ __launch_bounds__(256) void k_rank_desc(const float* scores, int64_t 
     if (c < n) order[rank] = (int32_t)c;
 }
 
-// dst[:, j] = src[:, order[j]] (m rows), and perm[j] = order[j].
+// dst[:, j] = src[:, order[j]] (m rows), and perm[j] = order[j].  An entry
+// outside [0, n) is clamped, so a corrupt order cannot read outside src.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gather_cols(const T* src, int64_t lds, T* dst, int64_t ldd, int64_t m,
-                                                     const int32_t* order, int32_t* perm)
+                                                     const int32_t* order, int32_t* perm, int64_t n)
 {
     const int64_t j = blockIdx.y;
-    const int64_t c = order[j];
+    const int64_t o = order[j];
+    const int64_t c = o < 0 ? 0 : (o >= n ? n - 1 : o);
     if (blockIdx.x == 0 && threadIdx.x == 0) perm[j] = (int32_t)c;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256)
         dst[i + ldd * j] = src[i + lds * c];
@@ -240,8 +246,8 @@ __global__ __launch_bounds__(256) void k_certificate(const ArgBest* cpart, int n
     b.key = 0x7fffffff;
     b.slot = -1;
     for (int q = threadIdx.x; q < nparts; q += 256)
-        if (cpart[q].slot >= 0 && arg_better(cpart[q].val, cpart[q].key, b.val, b.key)) b = cpart[q];
-    b = block_argmax256(b, arg_lds);
+        if (cpart[q].slot >= 0 && arg_better_exact(cpart[q].val, cpart[q].key, b.val, b.key)) b = cpart[q];
+    b = block_argmax256<true>(b, arg_lds);
     double mn = 1e300;
     for (int64_t j = threadIdx.x; j < k; j += 256) mn = fmin(mn, fabs(diagR[j]));
     // block min via negated max of a sum-free reduction

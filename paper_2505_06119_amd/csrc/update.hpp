@@ -15,6 +15,7 @@
 // theta is column-major (2 chi_l) x (2 chi_r); Q_k is the new site i and
 // R_k P^T the new site i+1 without any transposition.
 #pragma once
+#include <mutex>
 #include <vector>
 #include "gemm.hpp"
 #include "prof.hpp"
@@ -23,10 +24,9 @@
 #include <stdarg.h>
 #include <stdio.h>
 
-// What the last failed pivoted QR found inconsistent (the hipErrorUnknown
-// returns of run_qrcp and window_panel below); empty when none.  Thread-unsafe, like the
-// rest of the host sequencing.
-static char g_qr_diag[320];
+// What the last failed pivoted QR of this host thread found inconsistent (the
+// hipErrorUnknown returns of run_qrcp and window_panel below); empty when none.
+static thread_local char g_qr_diag[320];
 
 static void qr_diag(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
 static void qr_diag(const char* fmt, ...)
@@ -501,15 +501,20 @@ static int run_panel_steps(QrcpDev<T>& d, hipStream_t st, int64_t p0, int64_t ns
 // coherent pinned host memory and then publishes a sequence number there; the
 // host spins on that number instead of synchronising the stream and copying
 // into pageable memory (about 7 us per readback instead of about 23).  The
-// mailbox is process-global (the host sequencing is single-threaded) and is
-// allocated on first use; without it the readback is a copy and a stream
-// synchronisation.
+// mailbox is process-global and is allocated on first use; a mutex makes each
+// readback (export launch and spin) one critical section, so host threads
+// that factorise on different streams never read each other's control blocks.
+// Without the mailbox the readback is a copy and a stream synchronisation.
 struct CtlMailbox {
     int32_t* buf = nullptr;   // CTL_COUNT values, then the sequence number
     int32_t seq = 0;
     bool tried = false;
+    std::mutex mu;
 };
 static CtlMailbox g_ctl_mbox;
+// Set for the duration of a call that must not allocate: the readback then
+// uses the mailbox only if an earlier call has already allocated it.
+static thread_local bool g_no_alloc = false;
 
 __global__ __launch_bounds__(64) void k_ctl_export(const int32_t* ctl, int32_t* hbuf, int32_t seq)
 {
@@ -524,7 +529,8 @@ template <typename T>
 static hipError_t read_ctl(const QrcpDev<T>& d, hipStream_t st, int32_t* hctl)
 {
     CtlMailbox& mb = g_ctl_mbox;
-    if (!mb.tried) {
+    std::lock_guard<std::mutex> lock(mb.mu);
+    if (!mb.tried && !g_no_alloc) {
         mb.tried = true;
         void* p = nullptr;
         if (hipHostMalloc(&p, 64 * sizeof(int32_t), hipHostMallocCoherent | hipHostMallocPortable) == hipSuccess) {

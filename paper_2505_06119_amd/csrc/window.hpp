@@ -403,7 +403,7 @@ __global__ __launch_bounds__(256) void k_window_check(QrcpDev<T> d, const T* R12
                 const int t = t0 + u;
                 if (done || t >= nbe) break;
                 const double pv = d.pivval[t];
-                if (s > pv || (s == pv && key < d.pivkey[t])) {
+                if (arg_better(s, key, pv, d.pivkey[t])) {
                     tfail = t;
                     done = true;
                     break;

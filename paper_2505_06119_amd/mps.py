@@ -58,7 +58,8 @@ class LearnedCfg(ctypes.Structure):
 class Config(ctypes.Structure):
     _fields_ = [("n_sites", ctypes.c_int32), ("chi_max", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("pivot", ctypes.c_int32), ("fallback_ratio", ctypes.c_double), ("sketch_rows", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("pad", ctypes.c_int32), ("seed", ctypes.c_uint64), ("mlp_weights", ctypes.c_void_p),
+                ("learned_verify", ctypes.c_int32), ("pad2", ctypes.c_int32)]
 
 
 _lib = None
@@ -71,15 +72,19 @@ def lib() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2505_06119_amd.build.build()")
+    # the library and torch share one HIP runtime in the process: let torch
+    # bring it up first (on a host without a GPU this only reports False)
+    _torch().cuda.is_available()
     L = ctypes.CDLL(LIB_PATH)
     p, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     pd, pi64 = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)
     L.mps_last_error.restype = ctypes.c_char_p
     L.mps_last_error.argtypes = []
     L.qrcp_work_bytes.restype = i64
-    L.qrcp_work_bytes.argtypes = [i64, i64, i64, i32]
+    L.qrcp_work_bytes.argtypes = [i64, i64, i64, i32, i32]
     L.qrcp_truncate.restype = i32
-    L.qrcp_truncate.argtypes = [i64, i64, i64, i32, p, i64, p, i64, p, i64, p, p, pi64, pd, pd, p, i64, p]
+    L.qrcp_truncate.argtypes = [i64, i64, i64, i32, i32, ctypes.POINTER(LearnedCfg), p, i64, p, i64, p, i64, p,
+                                p, pi64, pd, pd, ctypes.POINTER(UpdateInfo), p, i64, p]
     L.mps_update_work_bytes.restype = i64
     L.mps_update_work_bytes.argtypes = [i64, i64, i64, i64, i32, i32]
     L.mps_update_bond.restype = i32
@@ -213,13 +218,18 @@ def set_small_bond_limit(max_dim: int = 64):
     _check(lib().mps_set_small_bond_limit(max_dim))
 
 
-def qrcp_work_bytes(m: int, n: int, k_max: int, prec: int) -> int:
-    return int(lib().qrcp_work_bytes(m, n, k_max, prec))
+def qrcp_work_bytes(m: int, n: int, k_max: int, prec: int, mode: int = MPS_PIVOT_QRCP) -> int:
+    return int(lib().qrcp_work_bytes(m, n, k_max, prec, mode))
 
 
-def qrcp_truncate(A, k_max: int, prec: int, work=None, stream=None) -> dict:
-    """Pivoted QR of the column-major device matrix A (m x n), k = min(k_max, m, n)."""
+def qrcp_truncate(A, k_max: int, prec: int, work=None, stream=None, learned=None) -> dict:
+    """Pivoted QR of the column-major device matrix A (m x n), k = min(k_max, m, n).
+
+    learned: a LearnedCfg (see learned_cfg) to factorise with the proposed
+    column order (MPS_PIVOT_LEARNED); "piv" is then the proposed order when
+    the proposal was accepted (info["fallback"] == 0)."""
     torch = _torch()
+    mode = MPS_PIVOT_QRCP if learned is None else MPS_PIVOT_LEARNED
     m, n = A.shape
     k = max(0, min(k_max, m, n))
     lda = A.stride(1) if n > 1 else max(m, 1)
@@ -229,17 +239,19 @@ def qrcp_truncate(A, k_max: int, prec: int, work=None, stream=None) -> dict:
     R = empty_colmajor(k, n, prec)
     piv = torch.empty(n, dtype=torch.int32, device=A.device)
     diag = torch.empty(max(k, 1), dtype=torch.float64, device=A.device)
-    wb = qrcp_work_bytes(m, n, k_max, prec)
+    wb = qrcp_work_bytes(m, n, k_max, prec, mode)
     if work is None:
         work = torch.empty(max(wb, 1), dtype=torch.uint8, device=A.device)
     kout = ctypes.c_int64(0)
     err = ctypes.c_double(0)
     afro = ctypes.c_double(0)
-    _check(lib().qrcp_truncate(m, n, k_max, prec, _ptr(A), lda, _ptr(Q), m, _ptr(R), max(k, 1), _ptr(piv),
-                               _ptr(diag), ctypes.byref(kout), ctypes.byref(err), ctypes.byref(afro), _ptr(work),
-                               work.numel(), stream if stream is not None else stream_ptr()))
+    info = UpdateInfo()
+    _check(lib().qrcp_truncate(m, n, k_max, prec, mode, ctypes.byref(learned) if learned is not None else None,
+                               _ptr(A), lda, _ptr(Q), m, _ptr(R), max(k, 1), _ptr(piv), _ptr(diag),
+                               ctypes.byref(kout), ctypes.byref(err), ctypes.byref(afro), ctypes.byref(info),
+                               _ptr(work), work.numel(), stream if stream is not None else stream_ptr()))
     return {"Q": Q, "RPt": R, "piv": piv, "diagR": diag[:k], "k": int(kout.value), "err": float(err.value),
-            "a_fro": float(afro.value)}
+            "a_fro": float(afro.value), "info": info.as_dict()}
 
 
 def mps_update_work_bytes(chi_l, chi_m, chi_r, chi_cap, prec, pivot=MPS_PIVOT_QRCP) -> int:
@@ -347,9 +359,16 @@ class MPS:
     """An MPS held by the library (mps_create ... mps_destroy)."""
 
     def __init__(self, n_sites: int, chi_max: int, prec: int = MPS_FP64, pivot: int = MPS_PIVOT_QRCP,
-                 device="cuda"):
+                 device="cuda", learned: LearnedCfg | None = None):
+        """learned: optional LearnedCfg whose network and acceptance rule are set
+        at creation (mps_config.mlp_weights); otherwise set_pivot_network."""
         torch = _torch()
-        self.cfg = Config(n_sites, chi_max, prec, pivot, 1.01, 64, 0, 0)
+        if learned is not None:
+            self.cfg = Config(n_sites, chi_max, prec, MPS_PIVOT_LEARNED, learned.fallback_ratio, learned.sketch_rows,
+                              0, learned.seed, learned.params, learned.verify, 0)
+            self._lcfg = learned
+        else:
+            self.cfg = Config(n_sites, chi_max, prec, pivot, 1.01, 64, 0, 0, None, 0, 0)
         nbytes = int(lib().mps_arena_bytes(ctypes.byref(self.cfg)))
         if nbytes < 0:
             raise MpsError(1, "invalid configuration")

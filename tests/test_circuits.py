@@ -77,11 +77,11 @@ def test_grid_rcs_gpu_truncated_vs_oracle(prec):
     f_o = oracle.norm_fidelity(om.sites)
     f_g = np.exp(st.log_norm_fidelity())
     assert f_o < 0.9999
-    assert abs(f_g - f_o) <= tol * 10 * f_o
+    assert abs(f_g - f_o) <= tol * f_o
     sv_o = oracle.statevector(om.sites)
     sv_g = oracle.statevector(st.sites()) * np.sqrt(f_g)
     fid = abs(np.vdot(sv_o, sv_g)) ** 2 / (np.vdot(sv_o, sv_o).real * np.vdot(sv_g, sv_g).real)
-    assert 1 - fid <= tol * 10
+    assert 1 - fid <= tol
 
 
 @pytest.mark.gpu
@@ -99,7 +99,7 @@ def test_grid_rcs_gpu_fused_vs_oracle(prec):
     st.apply_layers(fused)
     ref = oracle.brute_force(12, layers)
     sv = oracle.statevector(st.sites()) * np.sqrt(np.exp(st.log_norm_fidelity()))
-    assert np.max(np.abs(sv - ref)) <= tol * 10 * np.max(np.abs(ref))
+    assert np.max(np.abs(sv - ref)) <= tol * np.max(np.abs(ref))
     st = mps.MPS(12, 16, prec)
     st.apply_layers(fused)
     om = oracle.MPS(synth.product_state_sites(12), chi_cap=16)
@@ -107,11 +107,11 @@ def test_grid_rcs_gpu_fused_vs_oracle(prec):
     f_o = oracle.norm_fidelity(om.sites)
     f_g = np.exp(st.log_norm_fidelity())
     assert f_o < 0.9999
-    assert abs(f_g - f_o) <= tol * 10 * f_o
+    assert abs(f_g - f_o) <= tol * f_o
     sv_o = oracle.statevector(om.sites)
     sv_g = oracle.statevector(st.sites()) * np.sqrt(f_g)
     fid = abs(np.vdot(sv_o, sv_g)) ** 2 / (np.vdot(sv_o, sv_o).real * np.vdot(sv_g, sv_g).real)
-    assert 1 - fid <= tol * 10
+    assert 1 - fid <= tol
 
 
 @pytest.mark.gpu
@@ -119,13 +119,10 @@ def test_grid_rcs_gpu_fused_vs_oracle(prec):
 def test_grid_rcs_gpu_lazy_routing_vs_oracle(prec):
     """The grid circuit on logical qubits routed on demand (routing.route_lazy).
     chi cap 64: the state equals the logical brute force through the final
-    qubit order.  chi cap 16: SWAP-heavy routing makes many exactly or
-    rounding-level tied residual norms in untruncated updates; which of the
-    tied columns comes first fixes the new bond's basis, and pivoted-QR
-    truncation depends on that basis, so truncated QR runs are compared by
-    what holds for any tie resolution (norm fidelity tracks the overlap with
-    the exact state), while the SVD-truncated run, which no basis choice
-    changes, follows the oracle's SVD MPS."""
+    qubit order.  chi cap 16, truncating: the QR-truncated run follows the
+    oracle MPS (SWAP-heavy routing makes exactly tied residual norms in
+    untruncated updates; both sides give a tie to the smaller column 2r + b'
+    of theta), and so does the SVD-truncated run."""
     from paper_2505_06119_amd import mps, routing
     print(f"case grid rcs lazy prec={prec}", flush=True)
     ops = synth.grid_rcs_logical(synth.rng(6), 3, 4, 8)
@@ -140,15 +137,21 @@ def test_grid_rcs_gpu_lazy_routing_vs_oracle(prec):
     st.apply_layers(layers)
     sv = oracle.statevector(st.sites()) * np.sqrt(np.exp(st.log_norm_fidelity()))
     sv = np.transpose(sv.reshape((2,) * 12), perm).reshape(-1)
-    assert np.max(np.abs(sv - ref)) <= tol * 10 * np.max(np.abs(ref))
-    # pivoted QR, truncating: norm fidelity against the overlap fidelity
+    assert np.max(np.abs(sv - ref)) <= tol * np.max(np.abs(ref))
+    # pivoted QR, truncating: against the oracle MPS
     st = mps.MPS(12, 16, prec)
     st.apply_layers(layers)
-    fbar = np.exp(st.log_norm_fidelity())
-    sv = np.transpose(oracle.statevector(st.sites()).reshape((2,) * 12), perm).reshape(-1)
-    f = abs(np.vdot(ref, sv)) ** 2 / np.vdot(sv, sv).real
-    assert 0.01 < fbar < 0.9999
-    assert abs(np.log(fbar) - np.log(f)) < 0.25
+    om = oracle.MPS(synth.product_state_sites(12), chi_cap=16)
+    om.apply_layers(layers)
+    f_o = oracle.norm_fidelity(om.sites)
+    f_g = np.exp(st.log_norm_fidelity())
+    assert 0.01 < f_o < 0.9999
+    assert abs(f_g - f_o) <= tol * f_o
+    assert st.bond_dims() == [1] + om.bond_dims() + [1]
+    sv_o = oracle.statevector(om.sites)
+    sv_g = oracle.statevector(st.sites()) * np.sqrt(f_g)
+    fid = abs(np.vdot(sv_o, sv_g)) ** 2 / (np.vdot(sv_o, sv_o).real * np.vdot(sv_g, sv_g).real)
+    assert 1 - fid <= tol
     # SVD, truncating: against the oracle
     st = mps.MPS(12, 16, prec)
     st.set_truncation(mps.MPS_TRUNC_SVD)
@@ -158,11 +161,11 @@ def test_grid_rcs_gpu_lazy_routing_vs_oracle(prec):
     f_o = oracle.norm_fidelity(om.sites)
     f_g = np.exp(st.log_norm_fidelity())
     assert f_o < 0.9999
-    assert abs(f_g - f_o) <= tol * 10 * f_o
+    assert abs(f_g - f_o) <= tol * f_o
     sv_o = oracle.statevector(om.sites)
     sv_g = oracle.statevector(st.sites()) * np.sqrt(f_g)
     fid = abs(np.vdot(sv_o, sv_g)) ** 2 / (np.vdot(sv_o, sv_o).real * np.vdot(sv_g, sv_g).real)
-    assert 1 - fid <= tol * 10
+    assert 1 - fid <= tol
 
 
 @pytest.mark.gpu

@@ -47,8 +47,8 @@ def test_chain_exact_vs_statevector(M, prec):
     ref = oracle.brute_force(n, layers)
     tol = TOL[prec]
     sv = _sv(st)
-    assert np.max(np.abs(sv - ref)) <= tol * 10 * np.max(np.abs(ref))
-    assert abs(st.log_norm_fidelity()) <= tol * 10
+    assert np.max(np.abs(sv - ref)) <= tol * np.max(np.abs(ref))
+    assert abs(st.log_norm_fidelity()) <= tol
     assert all(i["panels"] == 0 for i in infos)
     assert all(abs(i["retained"] - 1.0) <= tol for i in infos)
 
@@ -68,16 +68,16 @@ def test_chain_truncated_vs_oracle(M, prec):
     for gi, rec in zip(infos, om.history):
         assert gi["k"] == rec["k"]
         ret_o = 1.0 - rec["err"] ** 2 / rec["norm2"]
-        assert abs(gi["retained"] - ret_o) <= tol * 10
+        assert abs(gi["retained"] - ret_o) <= tol
         assert gi["panels"] == 0
     fbar_o = oracle.norm_fidelity(om.sites)
     assert fbar_o < 0.999
-    assert abs(np.exp(st.log_norm_fidelity()) - fbar_o) <= tol * 10 * fbar_o
+    assert abs(np.exp(st.log_norm_fidelity()) - fbar_o) <= tol * fbar_o
     assert st.bond_dims() == [1] + om.bond_dims() + [1]
     sv_o = oracle.statevector(om.sites)
     sv_g = _sv(st)
-    assert 1 - _fid(sv_o, sv_g) <= tol * 10
-    assert np.max(np.abs(sv_g - sv_o)) <= tol * 10 * np.max(np.abs(sv_o))
+    assert 1 - _fid(sv_o, sv_g) <= tol
+    assert np.max(np.abs(sv_g - sv_o)) <= tol * np.max(np.abs(sv_o))
 
 
 def test_chain_matches_multikernel(M):
@@ -110,7 +110,7 @@ def test_chain_partial_runs(M, prec):
     assert any(i["panels"] == 0 for i in infos) and any(i["panels"] > 0 for i in infos)
     ref = oracle.brute_force(n, layers)
     tol = TOL[prec]
-    assert np.max(np.abs(_sv(st) - ref)) <= tol * 10 * np.max(np.abs(ref))
+    assert np.max(np.abs(_sv(st) - ref)) <= tol * np.max(np.abs(ref))
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -134,5 +134,5 @@ def test_chain_left_and_right_moves(M, prec):
     assert st.bond_dims() == [1] + om.bond_dims() + [1]
     assert st.centre() == om.centre
     fbar_o = oracle.norm_fidelity(om.sites)
-    assert abs(np.exp(st.log_norm_fidelity()) - fbar_o) <= tol * 10 * fbar_o
-    assert 1 - _fid(oracle.statevector(om.sites), _sv(st)) <= tol * 10
+    assert abs(np.exp(st.log_norm_fidelity()) - fbar_o) <= tol * fbar_o
+    assert 1 - _fid(oracle.statevector(om.sites), _sv(st)) <= tol

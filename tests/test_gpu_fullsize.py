@@ -8,6 +8,8 @@ update at this size).  theta is rebuilt independently here in complex128:
   * pivoted QR of the same theta (qrcp_truncate): |R_jj| non-increasing, and
     |R_jj|^2 >= sum_{t=j..i} |R_ti|^2 for every later column i (sampled j);
   * the mixed and FP64 updates agree in norm fidelity to 1e-4."""
+import os
+
 import numpy as np
 import pytest
 
@@ -68,13 +70,13 @@ def test_fullsize_update_properties(setup, prec):
     assert abs(info["norm_sq"] - nrm2) <= tol * nrm2
     g_qq = q.conj().transpose(0, 1) @ q
     eye = torch.eye(k, dtype=torch.complex128, device="cuda")
-    assert torch.max(torch.abs(g_qq - eye)).item() <= tol * 10
+    assert torch.max(torch.abs(g_qq - eye)).item() <= tol
     del g_qq, eye
     proj = q.conj().transpose(0, 1) @ theta
-    assert (torch.linalg.norm(proj - rp) / np.sqrt(nrm2)).item() <= tol * 10
+    assert (torch.linalg.norm(proj - rp) / np.sqrt(nrm2)).item() <= tol
     del proj
     res = torch.sum(torch.abs(theta - q @ rp) ** 2).item()
-    assert abs(res - info["trunc_err_sq"]) <= tol * 10 * nrm2
+    assert abs(res - info["trunc_err_sq"]) <= tol * nrm2
     assert 0.0 < info["trunc_err_sq"] < nrm2
 
 
@@ -112,3 +114,145 @@ def test_fullsize_qrcp_invariants(setup, prec):
         last = torch.clamp(torch.arange(ncols, device="cuda"), max=seg.shape[0] - 1)
         tot = cs[last, torch.arange(ncols, device="cuda")]
         assert torch.all(tot <= d[j] ** 2 * (1 + 2 * tol) + 1e-300).item(), j
+
+
+# --- oracle parity at full size ---------------------------------------------------
+
+MARGIN = {0: 1e-10, 1: 1e-3}   # pivot equality is asserted up to the first step
+                                # whose oracle margin is below this (near tie)
+K_PANELS = 64                   # pivot steps the live oracle comparison covers
+
+
+def _first_diff(x, y):
+    n = min(len(x), len(y))
+    d = np.flatnonzero(np.asarray(x[:n]) != np.asarray(y[:n]))
+    return int(d[0]) if len(d) else n
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fullsize_first_panels_match_oracle(setup, prec):
+    """The first K_PANELS pivot steps of the full-size pivoted QR (two window
+    panels, their greedy replays and block updates) against the oracle on the
+    same input bytes: theta element by element, then pivots (up to the first
+    near tie), R_jj, Q_K, the R rows and the rank-K truncation error."""
+    import oracle
+    mps, torch, a, b, g, theta = setup
+    print(f"case full-size first panels vs oracle prec={prec}", flush=True)
+    cd = mps.cdtype(prec)
+    A, B = a.to(cd).contiguous(), b.to(cd).contiguous()
+    a_h = mps.site_from_device(A, CHI, CHI)
+    b_h = mps.site_from_device(B, CHI, CHI)
+    th_g = mps.mps_theta(A, B, g, CHI, CHI, CHI, prec)
+    out = mps.qrcp_truncate(th_g, K_PANELS, prec)
+    torch.cuda.synchronize()
+    # the oracle's theta (rows 2l + a', columns 2r + b') with its rows put in
+    # the library's order l + chi a': the reflectors' signs depend on the row
+    # order, so both factorise the same matrix and Q, R compare entry by entry
+    th_o = oracle.theta(a_h, b_h, g).reshape(CHI, 2, 2 * CHI).transpose(1, 0, 2).reshape(2 * CHI, 2 * CHI)
+    th_gh = th_g.cpu().numpy().astype(np.complex128)                  # rows l + chi a', columns b' + 2r
+    tol = TOL[prec]
+    tmax = np.max(np.abs(th_o))
+    assert np.max(np.abs(th_gh - th_o)) <= tol * tmax
+    del th_gh
+    o = oracle.qrcp(th_o, K_PANELS)
+    piv_g = out["piv"].cpu().numpy().astype(np.int64)[:K_PANELS]
+    near = np.flatnonzero(o["gaps"] < MARGIN[prec])
+    upto = int(near[0]) if len(near) else K_PANELS
+    first = _first_diff(piv_g, o["piv"][:K_PANELS])
+    print(f"first {K_PANELS} steps: pivots agree up to step {first}; first oracle margin < {MARGIN[prec]:g} "
+          f"at step {upto}; smallest margin {o['gaps'].min():.3e}", flush=True)
+    assert first >= upto
+    if first == K_PANELS:
+        scale = np.sqrt(np.sum(np.abs(th_o) ** 2))
+        np.testing.assert_allclose(out["diagR"].cpu().numpy(), o["diagR"], rtol=tol, atol=tol * scale)
+        q_g = out["Q"].cpu().numpy().astype(np.complex128)
+        assert np.max(np.abs(q_g - o["Q"])) <= tol
+        rp_g = out["RPt"].cpu().numpy().astype(np.complex128)
+        rp_o = oracle.r_unpivot(o["R"], o["piv"])
+        assert np.max(np.abs(rp_g - rp_o)) <= tol * scale
+        assert abs(out["err"] - o["err"]) <= tol * scale
+
+
+def _golden(prec):
+    import json
+    name = "chi4096_fp64.json" if prec == 0 else "chi4096_c64.json"
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    with open(path) as fh:
+        return json.load(fh)
+
+
+@pytest.fixture(scope="module")
+def cpu_inputs():
+    """The headline inputs built on the CPU, as tests/golden/make_chi4096.py
+    builds them (numpy QR of the seeded Gaussians)."""
+    import importlib.util
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "make_chi4096.py")
+    spec = importlib.util.spec_from_file_location("make_chi4096", path)
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    print("building the chi 4096 inputs on the CPU", flush=True)
+    return mk, mk.inputs("fp64")
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fullsize_update_matches_oracle(cpu_inputs, prec):
+    """The whole chi = 4096 update that bench.py times (same construction, same
+    launch configuration) against the oracle's stored result for the same input
+    bytes (tests/golden/make_chi4096.py): pivots up to the first near tie,
+    eps^2, ||theta||^2 and the norm-fidelity factor, and theta_T at 512 stored
+    positions where the pivot sets agree.  The first step where the pivots
+    part, with its oracle margin, is printed."""
+    import torch
+    from paper_2505_06119_amd import mps
+    mk, (a, b, g) = cpu_inputs
+    gold = _golden(prec)
+    if prec == 1:
+        a = a.astype(np.complex64).astype(np.complex128)
+        b = b.astype(np.complex64).astype(np.complex128)
+    if mk.input_digest(a, b, g) != gold["input_sha256"]:
+        pytest.skip("this host's LAPACK built other input bytes than the stored oracle run's")
+    print(f"case full-size update vs stored oracle prec={prec}", flush=True)
+    A, B = mps.site_to_device(a, prec), mps.site_to_device(b, prec)
+    out = mps.mps_update_bond(A, B, g, CHI, CHI, CHI, CHI, prec, renormalize=False)
+    th = mps.mps_theta(A, B, g, CHI, CHI, CHI, prec)
+    q = mps.qrcp_truncate(th, CHI, prec)
+    torch.cuda.synchronize()
+    info = out["info"]
+    k = gold["k"]
+    assert out["k"] == k
+    piv_g = q["piv"].cpu().numpy().astype(np.int64)[:k]
+    # the update's own pivots, read off R_k P^T: column piv[j] of R_k P^T ends
+    # at row j (R_k is upper trapezoidal), for every j < k - 1
+    b2 = mps.site_from_device(out["B"], k, CHI)
+    rp = b2.transpose(0, 2, 1).reshape(k, 2 * CHI)        # columns 2r + b'
+    last = k - 1 - np.argmax(np.abs(rp[::-1, :]) > 0, axis=0)
+    own = np.full(k - 1, -1, dtype=np.int64)
+    for c in np.flatnonzero(last < k - 1):
+        own[last[c]] = c
+    assert list(own) == list(piv_g[:k - 1])
+    gaps = np.asarray(gold["gaps"])
+    near = np.flatnonzero(gaps < MARGIN[prec])
+    upto = int(near[0]) if len(near) else k
+    first = _first_diff(piv_g, gold["piv"])
+    same_set = set(piv_g.tolist()) == set(gold["piv"])
+    gap_at = float(gaps[first]) if first < k else float("nan")
+    print(f"pivots agree up to step {first} of {k} (oracle margin there {gap_at:.3e}); first oracle margin < "
+          f"{MARGIN[prec]:g} at step {upto}; same pivot set: {same_set}", flush=True)
+    assert first >= upto
+    tol = TOL[prec]
+    assert abs(info["norm_sq"] - gold["norm2"]) <= tol * gold["norm2"]
+    ret_g = 1.0 - info["trunc_err_sq"] / info["norm_sq"]
+    print(f"retained: gpu {ret_g:.12e} oracle {gold['retained']:.12e} rel dev "
+          f"{abs(ret_g - gold['retained']) / gold['retained']:.3e}; eps^2 gpu {info['trunc_err_sq']:.12e} "
+          f"oracle {gold['err2']:.12e}", flush=True)
+    assert abs(ret_g - gold["retained"]) <= tol * gold["retained"]
+    if same_set:
+        assert abs(info["trunc_err_sq"] - gold["err2"]) <= tol * gold["norm2"]
+        a2 = mps.site_from_device(out["A"], CHI, k)
+        qo = a2.reshape(2 * CHI, k)                       # rows 2l + a'
+        ri, ci = np.asarray(gold["theta_T_rows"]), np.asarray(gold["theta_T_cols"])
+        tt = np.einsum("sk,ks->s", qo[ri, :], rp[:, ci])
+        ref = np.asarray(gold["theta_T_re"]) + 1j * np.asarray(gold["theta_T_im"])
+        assert np.max(np.abs(tt - ref)) <= tol * np.max(np.abs(ref))

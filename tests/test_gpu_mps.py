@@ -39,7 +39,7 @@ def test_brickwork_exact_vs_statevector(M, prec):
     tol = TOL[prec]
     sv = _gpu_statevector(st)
     assert np.max(np.abs(sv - ref)) <= tol * np.max(np.abs(ref)) * 10
-    assert abs(st.log_norm_fidelity()) <= tol * 10
+    assert abs(st.log_norm_fidelity()) <= tol
     for x in synth.rng(101).integers(0, 2 ** n, size=12):
         amp = st.amplitude(_bits(int(x), n))
         assert abs(amp - ref[int(x)]) <= tol * np.max(np.abs(ref)) * 10
@@ -59,13 +59,13 @@ def test_brickwork_truncated_vs_oracle(M, prec):
     fbar_g = np.exp(st.log_norm_fidelity())
     tol = TOL[prec]
     assert fbar_o < 0.999
-    assert abs(fbar_g - fbar_o) <= tol * 10 * fbar_o
+    assert abs(fbar_g - fbar_o) <= tol * fbar_o
     assert st.bond_dims() == [1] + om.bond_dims() + [1]
     sv_o = oracle.statevector(om.sites)
     sv_g = _gpu_statevector(st)
     fid = abs(np.vdot(sv_o, sv_g)) ** 2 / (np.vdot(sv_o, sv_o).real * np.vdot(sv_g, sv_g).real)
-    assert 1 - fid <= tol * 10
-    assert np.max(np.abs(sv_g - sv_o)) <= tol * 10 * np.max(np.abs(sv_o))
+    assert 1 - fid <= tol
+    assert np.max(np.abs(sv_g - sv_o)) <= tol * np.max(np.abs(sv_o))
     assert len(infos) == 55
 
 
@@ -89,7 +89,7 @@ def test_ghz_and_qft(M, prec):
     N = 2 ** n
     ref = np.exp(2j * np.pi * x * np.arange(N) / N) / np.sqrt(N)
     sv = _gpu_statevector(st)
-    assert np.max(np.abs(sv - ref)) <= tol * 10
+    assert np.max(np.abs(sv - ref)) <= tol
 
 
 def test_swap_routing_roundtrip(M):
@@ -152,5 +152,5 @@ def test_wide_bonds_exact_without_chains(M, prec):
     ref = oracle.brute_force(n, layers)
     sv = _gpu_statevector(st)
     tol = 1e-10 if prec == 0 else 1e-4
-    assert np.max(np.abs(sv - ref)) <= tol * 10 * np.max(np.abs(ref))
-    assert abs(st.log_norm_fidelity()) <= tol * 10
+    assert np.max(np.abs(sv - ref)) <= tol * np.max(np.abs(ref))
+    assert abs(st.log_norm_fidelity()) <= tol

@@ -12,6 +12,12 @@ from paper_2505_06119_amd import synth
 pytestmark = pytest.mark.gpu
 
 TOL = {0: 1e-10, 1: 1e-4}
+# |R_jj| is non-increasing for the norms the pivot search compares.  Outside a
+# candidate window those are downdated and recomputed only once nu / nu_ref <=
+# sqrt(eps), so they can be off by about eps / sqrt(eps) = sqrt(eps) relative:
+# 1.5e-8 in FP64, 3.5e-4 in complex64 storage (bounds of that size, not the
+# parity bar, which applies to the factorisation itself).
+GREEDY_TOL = {0: 1e-7, 1: 1e-3}
 
 
 @pytest.fixture(scope="module")
@@ -48,9 +54,9 @@ def test_well_separated_pivots_exact(M, prec, m, n, seed):
     scale = np.linalg.norm(a)
     np.testing.assert_allclose(g["diagR"], o["diagR"], rtol=tol, atol=tol * scale)
     rp_o = oracle.r_unpivot(o["R"], o["piv"])
-    assert np.linalg.norm(g["RPt"] - rp_o) <= tol * 10 * scale
-    assert np.linalg.norm(g["Q"] - o["Q"]) <= tol * 10 * np.sqrt(n)
-    assert np.linalg.norm(a - g["Q"] @ g["RPt"]) <= tol * 10 * scale
+    assert np.linalg.norm(g["RPt"] - rp_o) <= tol * scale
+    assert np.linalg.norm(g["Q"] - o["Q"]) <= tol * np.sqrt(n)
+    assert np.linalg.norm(a - g["Q"] @ g["RPt"]) <= tol * scale
     assert abs(g["a_fro"] - scale) <= tol * scale
 
 
@@ -71,14 +77,14 @@ def test_truncated_gaussian(M, prec, m, n, k, seed):
     # the truncated approximation and its error agree (gauge invariant)
     approx_g = g["Q"] @ g["RPt"]
     approx_o = o["Q"] @ oracle.r_unpivot(o["R"], o["piv"])
-    assert np.linalg.norm(approx_g - approx_o) <= tol * 10 * scale
-    assert abs(g["err"] - o["err"]) <= tol * 10 * scale
+    assert np.linalg.norm(approx_g - approx_o) <= tol * scale
+    assert abs(g["err"] - o["err"]) <= tol * scale
     # invariants of the GPU result itself
     q = g["Q"]
-    np.testing.assert_allclose(q.conj().T @ q, np.eye(g["k"]), atol=tol * 10)
-    assert abs(np.linalg.norm(a - approx_g) - g["err"]) <= tol * 10 * scale
+    np.testing.assert_allclose(q.conj().T @ q, np.eye(g["k"]), atol=tol)
+    assert abs(np.linalg.norm(a - approx_g) - g["err"]) <= tol * scale
     d = np.abs(g["diagR"])
-    assert np.all(d[1:] <= d[:-1] * (1 + tol * 10))
+    assert np.all(d[1:] <= d[:-1] * (1 + GREEDY_TOL[prec]))
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -97,8 +103,8 @@ def test_edge_shapes(M, prec):
         approx_g = g["Q"] @ g["RPt"]
         approx_o = o["Q"] @ oracle.r_unpivot(o["R"], o["piv"])
         scale = np.linalg.norm(a)
-        assert np.linalg.norm(approx_g - approx_o) <= tol * 10 * scale
-        assert abs(g["err"] - o["err"]) <= tol * 10 * scale
+        assert np.linalg.norm(approx_g - approx_o) <= tol * scale
+        assert abs(g["err"] - o["err"]) <= tol * scale
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -112,9 +118,9 @@ def test_rank_deficient(M, prec):
     g = _run_qrcp(M, a, 10, prec)
     tol = TOL[prec]
     q = g["Q"]
-    np.testing.assert_allclose(q.conj().T @ q, np.eye(10), atol=tol * 10)
-    assert np.linalg.norm(a - q @ g["RPt"]) <= tol * 100 * np.linalg.norm(a)
-    assert g["err"] <= tol * 100 * np.linalg.norm(a)
+    np.testing.assert_allclose(q.conj().T @ q, np.eye(10), atol=tol)
+    assert np.linalg.norm(a - q @ g["RPt"]) <= tol * np.linalg.norm(a)
+    assert g["err"] <= tol * np.linalg.norm(a)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -137,10 +143,10 @@ def test_rank_deficient_past_the_rank(M, prec, rank):
     tol = TOL[prec]
     q = g["Q"]
     assert g["k"] == 40
-    np.testing.assert_allclose(q.conj().T @ q, np.eye(40), atol=tol * 10)
-    assert np.linalg.norm(a - q @ g["RPt"]) <= tol * 100 * np.linalg.norm(a)
+    np.testing.assert_allclose(q.conj().T @ q, np.eye(40), atol=tol)
+    assert np.linalg.norm(a - q @ g["RPt"]) <= tol * np.linalg.norm(a)
     assert abs(g["diagR"][rank - 1]) >= 1e-6 * abs(g["diagR"][0])
-    assert np.all(np.abs(g["diagR"][rank:]) <= tol * 100 * abs(g["diagR"][0]))
+    assert np.all(np.abs(g["diagR"][rank:]) <= tol * abs(g["diagR"][0]))
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -164,13 +170,13 @@ def test_update_bond_matches_oracle(M, prec, chl, chm, chr_, cap, seed):
     tt_g = np.tensordot(a2, b2, axes=(2, 0))
     tt_o = np.tensordot(u_o["A"], u_o["B"], axes=(2, 0))
     tol = TOL[prec]
-    assert np.linalg.norm(tt_g - tt_o) <= tol * 10
+    assert np.linalg.norm(tt_g - tt_o) <= tol
     info = out["info"]
-    assert abs(info["norm_sq"] - u_o["norm2"]) <= tol * 10
-    assert abs(info["trunc_err_sq"] - u_o["err"] ** 2) <= tol * 10
+    assert abs(info["norm_sq"] - u_o["norm2"]) <= tol
+    assert abs(info["trunc_err_sq"] - u_o["err"] ** 2) <= tol
     # left site is an isometry
     q = a2.transpose(1, 0, 2).reshape(2 * chl, k)
-    np.testing.assert_allclose(q.conj().T @ q, np.eye(k), atol=tol * 10)
+    np.testing.assert_allclose(q.conj().T @ q, np.eye(k), atol=tol)
 
 
 def test_update_bond_renormalises(M):

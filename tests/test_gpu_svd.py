@@ -46,8 +46,8 @@ def test_svd_exact_vs_statevector(M, prec):
     infos = st.apply_layers(layers)
     ref = oracle.brute_force(n, layers)
     tol = TOL[prec]
-    assert np.max(np.abs(_sv(st) - ref)) <= tol * 10 * np.max(np.abs(ref))
-    assert abs(st.log_norm_fidelity()) <= tol * 10
+    assert np.max(np.abs(_sv(st) - ref)) <= tol * np.max(np.abs(ref))
+    assert abs(st.log_norm_fidelity()) <= tol
     assert all(i["panels"] == 0 and i["qrcp_err_sq"] == -1.0 for i in infos)
 
 
@@ -66,12 +66,12 @@ def test_svd_truncated_vs_oracle(M, prec):
     assert len(infos) == len(om.history)
     for gi, rec in zip(infos, om.history):
         assert gi["k"] == rec["k"]
-        assert abs(gi["retained"] - (1.0 - rec["err"] ** 2 / rec["norm2"])) <= tol * 10
+        assert abs(gi["retained"] - (1.0 - rec["err"] ** 2 / rec["norm2"])) <= tol
     fbar_o = oracle.norm_fidelity(om.sites)
     assert fbar_o < 0.999
-    assert abs(np.exp(st.log_norm_fidelity()) - fbar_o) <= tol * 10 * fbar_o
+    assert abs(np.exp(st.log_norm_fidelity()) - fbar_o) <= tol * fbar_o
     assert st.bond_dims() == [1] + om.bond_dims() + [1]
-    assert 1 - _fid(oracle.statevector(om.sites), _sv(st)) <= tol * 10
+    assert 1 - _fid(oracle.statevector(om.sites), _sv(st)) <= tol
 
 
 def test_svd_first_truncation_no_worse_than_qr(M):

@@ -52,8 +52,8 @@ def test_window_pivots_exact_well_separated(M, prec, pw, win):
     tol = TOL[prec]
     scale = np.linalg.norm(a)
     np.testing.assert_allclose(g["diagR"], o["diagR"], rtol=tol, atol=tol * scale)
-    assert abs(g["err"] - o["err"]) <= tol * 10 * scale
-    assert np.linalg.norm(g["Q"] @ g["RPt"] - o["Q"] @ oracle.r_unpivot(o["R"], o["piv"])) <= tol * 10 * scale
+    assert abs(g["err"] - o["err"]) <= tol * scale
+    assert np.linalg.norm(g["Q"] @ g["RPt"] - o["Q"] @ oracle.r_unpivot(o["R"], o["piv"])) <= tol * scale
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -89,9 +89,9 @@ def test_window_matches_full_search(M, prec, win):
         assert list(gf["piv"][:chi]) == list(o["piv"][:chi])
     approx_o = o["Q"] @ oracle.r_unpivot(o["R"], o["piv"])
     for res in (gw, gf):
-        assert np.linalg.norm(res["Q"] @ res["RPt"] - approx_o) <= tol * 10 * scale
-        assert abs(res["err"] - o["err"]) <= tol * 10 * scale
-    assert abs(info["trunc_err_sq"] - o["err"] ** 2) <= tol * 10 * scale ** 2
+        assert np.linalg.norm(res["Q"] @ res["RPt"] - approx_o) <= tol * scale
+        assert abs(res["err"] - o["err"]) <= tol * scale
+    assert abs(info["trunc_err_sq"] - o["err"] ** 2) <= tol * scale ** 2
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -108,6 +108,6 @@ def test_window_tall_delayed_steps(M, prec):
     tol = TOL[prec]
     scale = np.linalg.norm(a)
     np.testing.assert_allclose(g["diagR"], o["diagR"], rtol=tol, atol=tol * scale)
-    assert abs(g["err"] - o["err"]) <= tol * 10 * scale
+    assert abs(g["err"] - o["err"]) <= tol * scale
     approx_o = o["Q"] @ oracle.r_unpivot(o["R"], o["piv"])
-    assert np.linalg.norm(g["Q"] @ g["RPt"] - approx_o) <= tol * 10 * scale
+    assert np.linalg.norm(g["Q"] @ g["RPt"] - approx_o) <= tol * scale

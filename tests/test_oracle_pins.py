@@ -369,3 +369,17 @@ def test_margins_flag_exact_ties():
     assert f["gaps"][1] == pytest.approx(0.75)      # 4 against 1
     assert f["gaps"][2] == pytest.approx(0.75)      # 1 against 0.25
     assert f["gaps"][3] == 1.0                      # nothing left to compare
+
+
+def test_ties_are_read_at_40_bits():
+    """Squared residual norms that agree to 40 significant bits tie (the
+    smaller column wins); a difference of 1e-9 relative does not.  A simple
+    value such as 1/2 with a few ulps of rounding on either side still ties."""
+    for base in (1.0 + 2.0 ** -30, 0.5, 0.25):
+        for rel, want in ((1e-15, 0), (-1e-15, 0), (1e-9, 1), (-1e-9, 0)):
+            a = np.zeros((3, 2), dtype=np.complex128)
+            a[0, 0] = np.sqrt(base)
+            a[1, 1] = np.sqrt(base * (1 + rel))
+            f = oracle.qrcp(a, 1)
+            assert f["piv"][0] == want, (base, rel, f["piv"])
+
