@@ -160,35 +160,57 @@ static mps_status qrcp_impl(int64_t m, int64_t n, int64_t k, mps_precision prec,
     return MPS_OK;
 }
 
-extern "C" mps_status qrcp_truncate(int64_t m, int64_t n, int64_t k_max, mps_precision prec, mps_pivot mode,
-                                    const mps_learned_cfg* learned, const void* A, int64_t lda, void* Q, int64_t ldq,
-                                    void* RPt, int64_t ldr, int32_t* piv, double* diagR, int64_t* k_out,
-                                    double* err_fro, double* a_fro, mps_update_info* info, void* work,
-                                    int64_t work_bytes, void* hip_stream)
+// Host-side checks shared by qrcp_truncate and qrcp_truncate_noalloc.
+static mps_status qrcp_check(const char* who, int64_t m, int64_t n, int64_t k_max, mps_precision prec,
+                             mps_pivot mode, const mps_learned_cfg* learned, const void* A, int64_t lda,
+                             const void* Q, int64_t ldq, const void* RPt, int64_t ldr, const int32_t* piv,
+                             const double* diagR)
 {
-    if (m < 1 || n < 1 || k_max < 1) return fail(MPS_EINVAL, "qrcp_truncate: m, n, k_max must be >= 1");
-    if (!valid_prec(prec)) return fail(MPS_EINVAL, "qrcp_truncate: bad precision %d", (int)prec);
+    if (m < 1 || n < 1 || k_max < 1) return fail(MPS_EINVAL, "%s: m, n, k_max must be >= 1", who);
+    if (!valid_prec(prec)) return fail(MPS_EINVAL, "%s: bad precision %d", who, (int)prec);
     if (mode != MPS_PIVOT_QRCP && mode != MPS_PIVOT_LEARNED)
-        return fail(MPS_EINVAL, "qrcp_truncate: bad pivot mode %d", (int)mode);
+        return fail(MPS_EINVAL, "%s: bad pivot mode %d", who, (int)mode);
     if (mode == MPS_PIVOT_LEARNED && !learned_cfg_valid(learned))
-        return fail(MPS_EINVAL, "qrcp_truncate: learned pivots need a valid mps_learned_cfg");
-    if (m > (1 << 20) || n > (1 << 20)) return fail(MPS_EINVAL, "qrcp_truncate: dimension too large");
+        return fail(MPS_EINVAL, "%s: learned pivots need a valid mps_learned_cfg", who);
+    if (m > (1 << 20) || n > (1 << 20)) return fail(MPS_EINVAL, "%s: dimension too large", who);
     int64_t k = k_max < m ? k_max : m;
     k = k < n ? k : n;
-    if (!A || !Q || !RPt || !piv || !diagR || !work)
-        return fail(MPS_EINVAL, "qrcp_truncate: null device pointer");
-    if (lda < m || ldq < m || ldr < k) return fail(MPS_EINVAL, "qrcp_truncate: leading dimension too small");
-    const int64_t need = qrcp_work_bytes(m, n, k_max, prec, mode);
-    if (work_bytes < need)
-        return fail(MPS_ENOMEM, "qrcp_truncate: need %lld work bytes, got %lld", (long long)need,
-                    (long long)work_bytes);
-    hipStream_t st = (hipStream_t)hip_stream;
+    if (!A || !Q || !RPt || !piv || !diagR) return fail(MPS_EINVAL, "%s: null device pointer", who);
+    if (lda < m || ldq < m || ldr < k) return fail(MPS_EINVAL, "%s: leading dimension too small", who);
+    return MPS_OK;
+}
+
+static mps_status qrcp_run(int64_t m, int64_t n, int64_t k_max, mps_precision prec, mps_pivot mode,
+                           const mps_learned_cfg* learned, const void* A, int64_t lda, void* Q, int64_t ldq,
+                           void* RPt, int64_t ldr, int32_t* piv, double* diagR, int64_t* k_out, double* err_fro,
+                           double* a_fro, mps_update_info* info, void* work, int64_t work_bytes, hipStream_t st)
+{
+    int64_t k = k_max < m ? k_max : m;
+    k = k < n ? k : n;
     const mps_learned_cfg* lc = mode == MPS_PIVOT_LEARNED ? learned : nullptr;
     if (prec == MPS_FP64)
         return qrcp_impl<double2>(m, n, k, prec, lc, A, lda, Q, ldq, RPt, ldr, piv, diagR, k_out, err_fro, a_fro,
                                   info, work, work_bytes, st);
     return qrcp_impl<float2>(m, n, k, prec, lc, A, lda, Q, ldq, RPt, ldr, piv, diagR, k_out, err_fro, a_fro, info,
                              work, work_bytes, st);
+}
+
+extern "C" mps_status qrcp_truncate(int64_t m, int64_t n, int64_t k_max, mps_precision prec, mps_pivot mode,
+                                    const mps_learned_cfg* learned, const void* A, int64_t lda, void* Q, int64_t ldq,
+                                    void* RPt, int64_t ldr, int32_t* piv, double* diagR, int64_t* k_out,
+                                    double* err_fro, double* a_fro, mps_update_info* info, void* work,
+                                    int64_t work_bytes, void* hip_stream)
+{
+    mps_status s = qrcp_check("qrcp_truncate", m, n, k_max, prec, mode, learned, A, lda, Q, ldq, RPt, ldr, piv,
+                              diagR);
+    if (s != MPS_OK) return s;
+    if (!work) return fail(MPS_EINVAL, "qrcp_truncate: null device pointer");
+    const int64_t need = qrcp_work_bytes(m, n, k_max, prec, mode);
+    if (work_bytes < need)
+        return fail(MPS_ENOMEM, "qrcp_truncate: need %lld work bytes, got %lld", (long long)need,
+                    (long long)work_bytes);
+    return qrcp_run(m, n, k_max, prec, mode, learned, A, lda, Q, ldq, RPt, ldr, piv, diagR, k_out, err_fro, a_fro,
+                    info, work, work_bytes, (hipStream_t)hip_stream);
 }
 
 // stateful MPS context
