@@ -142,6 +142,32 @@ mps_status qrcp_truncate(int64_t m, int64_t n, int64_t k_max, mps_precision prec
                          double* a_fro, mps_update_info* info, void* work, int64_t work_bytes, void* hip_stream);
 
 /* ------------------------------------------------------------------------
+ * qrcp_truncate_noalloc -- for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * qrcp_truncate with the same arguments and results, minus work and
+ * work_bytes.  Its scratch is a static device array of
+ * qrcp_noalloc_scratch_bytes() = 64 MiB that every GPU the library runs on
+ * holds until the process ends (its device address is looked up once per
+ * device, with that device current); the call uses the array of the current
+ * device, so hip_stream must belong to it.  It calls no hipMalloc, hipFree or
+ * other allocating routine; the one pinned host word of the control readback
+ * is used only if an earlier call of another entry point has created it,
+ * else the readback copies and synchronises the stream.
+ * Limit: qrcp_work_bytes(m, n, k_max, prec, mode) <= 64 MiB (for example
+ * m = n = 1024 in FP64 with plain pivoting, or in complex64 with learned
+ * pivots); larger problems return MPS_ENOMEM before any device work.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (other host threads, or other streams before this call has returned)
+ * race and corrupt each other's results.  The array keeps the last call's
+ * contents; nothing in it needs to start at zero.
+ * ------------------------------------------------------------------------ */
+int64_t qrcp_noalloc_scratch_bytes(void);
+mps_status qrcp_truncate_noalloc(int64_t m, int64_t n, int64_t k_max, mps_precision prec, mps_pivot mode,
+                                 const mps_learned_cfg* learned, const void* A, int64_t lda, void* Q, int64_t ldq,
+                                 void* RPt, int64_t ldr, int32_t* piv, double* diagR, int64_t* k_out,
+                                 double* err_fro, double* a_fro, mps_update_info* info, void* hip_stream);
+
+/* ------------------------------------------------------------------------
  * mps_update_bond -- one two-site update on explicit site tensors
  * (Sec. III-C.2): theta = G (A B) contracted over the shared bond chi_m,
  * truncated pivoted QR of theta as a (2 chi_l) x (2 chi_r) matrix, split into

@@ -213,6 +213,71 @@ extern "C" mps_status qrcp_truncate(int64_t m, int64_t n, int64_t k_max, mps_pre
                     info, work, work_bytes, (hipStream_t)hip_stream);
 }
 
+// ---------------------------------------------------------------------------
+// qrcp_truncate_noalloc: qrcp_truncate with its scratch in a static device
+// array instead of a workspace argument, for callers that cannot allocate.
+// `scratch` is a host-side stand-in in host code: its device address is taken
+// once per device with hipGetSymbolAddress (with that device current) and
+// only that address is passed on.  Each GPU holds its own copy until the
+// process ends.  Nothing in it needs to start at zero: the factorisation
+// writes every scratch word before reading it (the same holds for the
+// uninitialised workspace qrcp_truncate accepts).
+// ---------------------------------------------------------------------------
+#define NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
+#define NOALLOC_MAX_DEVICES 64
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+static void* g_scratch_ptr[NOALLOC_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+static mps_status noalloc_scratch(void** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "qrcp_truncate_noalloc: hipGetDevice");
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(MPS_EINVAL, "qrcp_truncate_noalloc: device %d beyond the %d supported", dev, NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "qrcp_truncate_noalloc: hipGetSymbolAddress");
+        if (!p) return fail(MPS_EDEVICE, "qrcp_truncate_noalloc: no device address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MPS_OK;
+}
+
+// Marks the calling thread as one that must not allocate for the scope.
+struct NoAllocScope {
+    bool prev;
+    NoAllocScope() : prev(g_no_alloc) { g_no_alloc = true; }
+    ~NoAllocScope() { g_no_alloc = prev; }
+};
+
+extern "C" int64_t qrcp_noalloc_scratch_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
+
+extern "C" mps_status qrcp_truncate_noalloc(int64_t m, int64_t n, int64_t k_max, mps_precision prec,
+                                            mps_pivot mode, const mps_learned_cfg* learned, const void* A,
+                                            int64_t lda, void* Q, int64_t ldq, void* RPt, int64_t ldr, int32_t* piv,
+                                            double* diagR, int64_t* k_out, double* err_fro, double* a_fro,
+                                            mps_update_info* info, void* hip_stream)
+{
+    mps_status s = qrcp_check("qrcp_truncate_noalloc", m, n, k_max, prec, mode, learned, A, lda, Q, ldq, RPt, ldr,
+                              piv, diagR);
+    if (s != MPS_OK) return s;
+    const int64_t need = qrcp_work_bytes(m, n, k_max, prec, mode);
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return fail(MPS_ENOMEM, "qrcp_truncate_noalloc: needs %lld bytes of scratch, the static array holds %lld",
+                    (long long)need, (long long)NOALLOC_SCRATCH_BYTES);
+    void* work = nullptr;
+    s = noalloc_scratch(&work);
+    if (s != MPS_OK) return s;
+    NoAllocScope guard;
+    return qrcp_run(m, n, k_max, prec, mode, learned, A, lda, Q, ldq, RPt, ldr, piv, diagR, k_out, err_fro, a_fro,
+                    info, work, NOALLOC_SCRATCH_BYTES, (hipStream_t)hip_stream);
+}
+
 // stateful MPS context
 #include "context.hpp"
 

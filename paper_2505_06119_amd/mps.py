@@ -85,6 +85,11 @@ def lib() -> ctypes.CDLL:
     L.qrcp_truncate.restype = i32
     L.qrcp_truncate.argtypes = [i64, i64, i64, i32, i32, ctypes.POINTER(LearnedCfg), p, i64, p, i64, p, i64, p,
                                 p, pi64, pd, pd, ctypes.POINTER(UpdateInfo), p, i64, p]
+    L.qrcp_noalloc_scratch_bytes.restype = i64
+    L.qrcp_noalloc_scratch_bytes.argtypes = []
+    L.qrcp_truncate_noalloc.restype = i32
+    L.qrcp_truncate_noalloc.argtypes = [i64, i64, i64, i32, i32, ctypes.POINTER(LearnedCfg), p, i64, p, i64, p,
+                                        i64, p, p, pi64, pd, pd, ctypes.POINTER(UpdateInfo), p]
     L.mps_update_work_bytes.restype = i64
     L.mps_update_work_bytes.argtypes = [i64, i64, i64, i64, i32, i32]
     L.mps_update_bond.restype = i32
@@ -250,6 +255,34 @@ def qrcp_truncate(A, k_max: int, prec: int, work=None, stream=None, learned=None
                                _ptr(A), lda, _ptr(Q), m, _ptr(R), max(k, 1), _ptr(piv), _ptr(diag),
                                ctypes.byref(kout), ctypes.byref(err), ctypes.byref(afro), ctypes.byref(info),
                                _ptr(work), work.numel(), stream if stream is not None else stream_ptr()))
+    return {"Q": Q, "RPt": R, "piv": piv, "diagR": diag[:k], "k": int(kout.value), "err": float(err.value),
+            "a_fro": float(afro.value), "info": info.as_dict()}
+
+
+def qrcp_truncate_noalloc(A, k_max: int, prec: int, stream=None, learned=None) -> dict:
+    """qrcp_truncate_noalloc: the same factorisation with the library's static
+    device scratch instead of a workspace (the outputs are still allocated
+    here, by torch)."""
+    torch = _torch()
+    mode = MPS_PIVOT_QRCP if learned is None else MPS_PIVOT_LEARNED
+    m, n = A.shape
+    k = max(0, min(k_max, m, n))
+    lda = A.stride(1) if n > 1 else max(m, 1)
+    if A.stride(0) != 1:
+        raise ValueError("A must be column-major (stride (1, lda))")
+    Q = empty_colmajor(m, k, prec)
+    R = empty_colmajor(k, n, prec)
+    piv = torch.empty(n, dtype=torch.int32, device=A.device)
+    diag = torch.empty(max(k, 1), dtype=torch.float64, device=A.device)
+    kout = ctypes.c_int64(0)
+    err = ctypes.c_double(0)
+    afro = ctypes.c_double(0)
+    info = UpdateInfo()
+    _check(lib().qrcp_truncate_noalloc(m, n, k_max, prec, mode,
+                                       ctypes.byref(learned) if learned is not None else None, _ptr(A), lda, _ptr(Q),
+                                       m, _ptr(R), max(k, 1), _ptr(piv), _ptr(diag), ctypes.byref(kout),
+                                       ctypes.byref(err), ctypes.byref(afro), ctypes.byref(info),
+                                       stream if stream is not None else stream_ptr()))
     return {"Q": Q, "RPt": R, "piv": piv, "diagR": diag[:k], "k": int(kout.value), "err": float(err.value),
             "a_fro": float(afro.value), "info": info.as_dict()}
 
