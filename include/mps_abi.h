@@ -195,6 +195,29 @@ mps_status mps_update_bond(int64_t chi_l, int64_t chi_m, int64_t chi_r, int64_t 
                            const mps_learned_cfg* learned, mps_update_info* info, void* work,
                            int64_t work_bytes, void* hip_stream);
 
+/* ------------------------------------------------------------------------
+ * mps_move_centre -- one move of the orthogonality centre on explicit sites
+ * (Sec. III-C.1: canonicalisation by QR to the right, LQ to the left), the
+ * operation a context performs before a two-site update away from the
+ * centre.  Sites A (chi_l x 2 x chi_c) and B (chi_c x 2 x chi_r) share the
+ * bond chi_c; layout as for mps_update_bond.
+ *   direction +1: A is the centre.  A = Q R (unpivoted Householder QR of the
+ *     (2 chi_l) x chi_c matrix, xLARFG convention), k = min(2 chi_l, chi_c);
+ *     A_out = Q (chi_l x 2 x k, left-orthonormal), B_out = R B (k x 2 x chi_r).
+ *   direction -1: B is the centre.  B = L Q' (LQ of the chi_c x (2 chi_r)
+ *     matrix, as the QR of its conjugate transpose), k = min(chi_c, 2 chi_r);
+ *     B_out = Q' (k x 2 x chi_r, right-orthonormal), A_out = A L
+ *     (chi_l x 2 x k).
+ * A, B: device, read-only.  A_out, B_out: device, must not overlap the inputs
+ * or each other.  k_out: host, may be NULL.  work: device scratch of at least
+ * mps_move_work_bytes(...) bytes.  Errors: MPS_EINVAL / MPS_ENOMEM before
+ * any device work, MPS_EDEVICE when a HIP call fails.
+ * ------------------------------------------------------------------------ */
+int64_t mps_move_work_bytes(int64_t chi_l, int64_t chi_c, int64_t chi_r, mps_precision prec, int32_t direction);
+mps_status mps_move_centre(int64_t chi_l, int64_t chi_c, int64_t chi_r, mps_precision prec, int32_t direction,
+                           const void* A, const void* B, void* A_out, void* B_out, int64_t* k_out, void* work,
+                           int64_t work_bytes, void* hip_stream);
+
 /* theta = G (A B) of the two-site update (steps before the factorisation),
  * written column-major (2 chi_l) x (2 chi_r) into the device buffer theta
  * (ld >= 2 chi_l).  work: at least mps_update_work_bytes(chi_l, chi_m, chi_r,

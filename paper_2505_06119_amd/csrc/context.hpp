@@ -236,20 +236,22 @@ extern "C" mps_status mps_destroy(mps_ctx* ctx)
 
 // Unpivoted QR of M (m x n, ld m) in the context workspace: Q (m x k', ldq)
 // and R (k' x n, ld k') into rbuf.  k' = min(m, n).
+// Unpivoted Householder QR of the m x n matrix M (or of M^H when transpose_in:
+// M is then given as the n x m matrix with leading dimension ld_in), k =
+// min(m, n): Q (m x k, ldq) and R (k x n, ld k) into R_out.  The workspace
+// (ws, ws_bytes) holds the factorisation.  A centre move (Sec. III-C.1).
 template <typename T>
-static mps_status ctx_qr(mps_ctx* c, const T* M, int64_t m, int64_t n, bool transpose_in, int64_t ld_in, T* Q,
-                         int64_t ldq, int64_t* kout)
+static mps_status move_qr(char* ws, int64_t ws_bytes, hipStream_t st, const T* M, int64_t m, int64_t n,
+                          bool transpose_in, int64_t ld_in, T* Q, int64_t ldq, T* R_out, int64_t* kout)
 {
     const int64_t k = m < n ? m : n;
-    Carver cv{c->ws, c->ws_bytes, 0};
+    Carver cv{ws, ws_bytes, 0};
     UpdateWs<T> w;
     if (!carve_update_ws<T>(cv, w, m, n, k, true)) return fail(MPS_ENOMEM, "centre move: workspace too small");
     w.nb = panel_width(m, n);
     w.d.tol = 0.0;
     w.d.pivoting = 0;
-    hipStream_t st = c->st;
     if (transpose_in) {
-        // M is given as its conjugate transpose: an n x m matrix with ld ld_in
         dim3 grid((unsigned)rup(n, 32), (unsigned)rup(m, 32));
         hipLaunchKernelGGL((k_conj_transpose<T>), grid, dim3(256), 0, st, M, ld_in, n, m, w.d.A, w.d.lda);
     } else {
@@ -262,10 +264,17 @@ static mps_status ctx_qr(mps_ctx* c, const T* M, int64_t m, int64_t n, bool tran
     HIPCHK(run_qrcp<T>(w, st, nullptr, 0), "centre move QR");
     HIPCHK(form_q<T>(w, Q, ldq, st), "centre move Q");
     hipLaunchKernelGGL((k_rpt<T>), dim3((unsigned)n), dim3(256), 0, st, (const T*)w.d.A, w.d.lda,
-                       (const int32_t*)w.d.perm, k, n, (T*)c->rbuf, k, (const double*)w.d.dsc, 0);
+                       (const int32_t*)w.d.perm, k, n, R_out, k, (const double*)w.d.dsc, 0);
     HIPCHK(hipGetLastError(), "centre move R");
     *kout = k;
     return MPS_OK;
+}
+
+template <typename T>
+static mps_status ctx_qr(mps_ctx* c, const T* M, int64_t m, int64_t n, bool transpose_in, int64_t ld_in, T* Q,
+                         int64_t ldq, int64_t* kout)
+{
+    return move_qr<T>(c->ws, c->ws_bytes, c->st, M, m, n, transpose_in, ld_in, Q, ldq, (T*)c->rbuf, kout);
 }
 
 template <typename T>
@@ -650,4 +659,89 @@ extern "C" mps_status mps_get_site(mps_ctx* ctx, int32_t j, void* dst, int64_t d
     HIPCHK(hipMemcpyAsync(dst, ctx->site[j], bytes, hipMemcpyDeviceToDevice, ctx->st), "mps_get_site copy");
     HIPCHK(hipStreamSynchronize(ctx->st), "mps_get_site sync");
     return MPS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Stateless centre move on explicit sites (Sec. III-C.1), the operation a
+// context performs before an update whose bond is away from the centre.
+// ---------------------------------------------------------------------------
+template <typename T>
+static int64_t move_ws_bytes_t(int64_t chi_l, int64_t chi_c, int64_t chi_r, int direction)
+{
+    const int64_t m = direction > 0 ? 2 * chi_l : 2 * chi_r, n = chi_c;
+    const int64_t k = m < n ? m : n;
+    Carver cv{nullptr, (int64_t)1 << 62, 0};
+    UpdateWs<T> w;
+    carve_update_ws<T>(cv, w, m, n, k, true);
+    cv.take((int64_t)sizeof(T) * k * n);        // R
+    if (direction < 0) cv.take((int64_t)sizeof(T) * m * k);   // Q' before its conjugate transpose
+    return cv.used + 256;
+}
+
+extern "C" int64_t mps_move_work_bytes(int64_t chi_l, int64_t chi_c, int64_t chi_r, mps_precision prec,
+                                       int32_t direction)
+{
+    if (chi_l < 1 || chi_c < 1 || chi_r < 1 || !valid_prec(prec) || (direction != 1 && direction != -1)) return -1;
+    return prec == MPS_FP64 ? move_ws_bytes_t<double2>(chi_l, chi_c, chi_r, direction)
+                            : move_ws_bytes_t<float2>(chi_l, chi_c, chi_r, direction);
+}
+
+template <typename T>
+static mps_status move_impl(int64_t chi_l, int64_t chi_c, int64_t chi_r, int direction, const T* A, const T* B,
+                            T* A_out, T* B_out, int64_t* k_out, void* work, int64_t work_bytes, hipStream_t st)
+{
+    const int64_t m = direction > 0 ? 2 * chi_l : 2 * chi_r, n = chi_c;
+    const int64_t k = m < n ? m : n;
+    Carver cv{(char*)work, work_bytes, 0};
+    UpdateWs<T> probe;
+    if (!carve_update_ws<T>(cv, probe, m, n, k, true)) return fail(MPS_ENOMEM, "mps_move_centre: work too small");
+    const int64_t ws_used = cv.used;
+    T* R = (T*)cv.take((int64_t)sizeof(T) * k * n);
+    T* Qt = direction < 0 ? (T*)cv.take((int64_t)sizeof(T) * m * k) : nullptr;
+    if (!R || (direction < 0 && !Qt)) return fail(MPS_ENOMEM, "mps_move_centre: work too small");
+    int64_t kk = 0;
+    mps_status s;
+    if (direction > 0) {
+        // A (2 chi_l x chi_c) = Q R;  A_out = Q, B_out = R B
+        s = move_qr<T>((char*)work, ws_used, st, A, m, n, false, m, A_out, m, R, &kk);
+        if (s != MPS_OK) return s;
+        if (!zgemm<T>(st, OP_N, false, OP_N, false, k, 2 * chi_r, chi_c, C_ONE, (const T*)R, k, B, chi_c, C_ZERO,
+                      B_out, k, nullptr, 0))
+            return fail(MPS_EINVAL, "mps_move_centre: gemm form unavailable");
+    } else {
+        // B (chi_c x 2 chi_r): B^H = Q' R', B = R'^H Q'^H;  B_out = Q'^H, A_out = A R'^H
+        s = move_qr<T>((char*)work, ws_used, st, B, m, n, true, chi_c, Qt, m, R, &kk);
+        if (s != MPS_OK) return s;
+        dim3 grid((unsigned)rup(m, 32), (unsigned)rup(k, 32));
+        hipLaunchKernelGGL((k_conj_transpose<T>), grid, dim3(256), 0, st, (const T*)Qt, m, m, k, B_out, k);
+        if (!zgemm<T>(st, OP_N, false, OP_C, false, 2 * chi_l, k, chi_c, C_ONE, A, 2 * chi_l, (const T*)R, k, C_ZERO,
+                      A_out, 2 * chi_l, nullptr, 0))
+            return fail(MPS_EINVAL, "mps_move_centre: gemm form unavailable");
+    }
+    HIPCHK(hipGetLastError(), "mps_move_centre launch");
+    HIPCHK(hipStreamSynchronize(st), "mps_move_centre sync");
+    if (k_out) *k_out = kk;
+    return MPS_OK;
+}
+
+extern "C" mps_status mps_move_centre(int64_t chi_l, int64_t chi_c, int64_t chi_r, mps_precision prec,
+                                      int32_t direction, const void* A, const void* B, void* A_out, void* B_out,
+                                      int64_t* k_out, void* work, int64_t work_bytes, void* hip_stream)
+{
+    if (chi_l < 1 || chi_c < 1 || chi_r < 1) return fail(MPS_EINVAL, "mps_move_centre: dimensions must be >= 1");
+    if (chi_l > (1 << 19) || chi_c > (1 << 20) || chi_r > (1 << 19))
+        return fail(MPS_EINVAL, "mps_move_centre: dimension too large");
+    if (!valid_prec(prec)) return fail(MPS_EINVAL, "mps_move_centre: bad precision %d", (int)prec);
+    if (direction != 1 && direction != -1) return fail(MPS_EINVAL, "mps_move_centre: direction must be +1 or -1");
+    if (!A || !B || !A_out || !B_out || !work) return fail(MPS_EINVAL, "mps_move_centre: null pointer");
+    const int64_t need = mps_move_work_bytes(chi_l, chi_c, chi_r, prec, direction);
+    if (work_bytes < need)
+        return fail(MPS_ENOMEM, "mps_move_centre: need %lld work bytes, got %lld", (long long)need,
+                    (long long)work_bytes);
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (prec == MPS_FP64)
+        return move_impl<double2>(chi_l, chi_c, chi_r, direction, (const double2*)A, (const double2*)B,
+                                  (double2*)A_out, (double2*)B_out, k_out, work, work_bytes, st);
+    return move_impl<float2>(chi_l, chi_c, chi_r, direction, (const float2*)A, (const float2*)B, (float2*)A_out,
+                             (float2*)B_out, k_out, work, work_bytes, st);
 }

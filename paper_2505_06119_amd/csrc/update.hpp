@@ -397,14 +397,22 @@ struct QrcpStats {
     int window_misses = 0;   // window panels cut short by the greedy replay
 };
 
-// a4-a10 on d.A; expects nu/nuref/perm/ctl[PIV] set up (pivoting) and the
-// control block reset.  Waits for the stream once per panel (read_ctl).
+template <typename T> static void run_window_steps(UpdateWs<T>& w, hipStream_t st, int64_t p0, int64_t nsteps, int W,
+                                                     int fixed = 0);
+template <typename T> static void window_reorder(UpdateWs<T>& w, hipStream_t st, int64_t p0, int nbe, int W);
+
 // Householder QR of d.A with the columns in their given order (a centre move,
-// or pivoted QR with a pivot order known in advance).  Only the panel's own
-// columns go through the per-column steps; the trailing columns receive the
-// panel's block reflector I - V T V^H at the panel end, as three MFMA GEMMs
+// or QR with a column order known in advance).  Only the panel's own columns
+// go through per-column steps; the trailing columns receive the panel's block
+// reflector I - V T V^H at the panel end, as three MFMA GEMMs
 //     W = V^H A_t,  W2 = T^H W,  A_t -= V W2      (A_t = A[p0:, pend:]).
-// Nothing depends on data on the host, so no synchronisation is needed.
+// While the rows left fit one window-step block (m - p0 <= 8192), a panel is
+// a window of its own nb columns factorised by right-looking k_window_step
+// launches in column order (one launch per column; the steps also form the
+// Gram matrix V^H V of the panel's reflectors); taller panels take the
+// delayed-update steps (step A + step C, two launches per column) and a GEMM
+// for V^H V.  Nothing depends on data on the host, so no synchronisation is
+// needed.
 template <typename T>
 static hipError_t run_blocked_fixed(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats)
 {
@@ -416,7 +424,14 @@ static hipError_t run_blocked_fixed(UpdateWs<T>& w, hipStream_t st, QrcpStats* s
     for (int64_t p0 = 0; p0 < k; p0 += nb) {
         const int64_t pend = (p0 + nb < k) ? p0 + nb : k;
         const int nbe = (int)(pend - p0);
-        for (int64_t jc = p0; jc < pend; ++jc) {
+        const bool right = m - p0 <= (int64_t)WSTEP_NT * WSTEP_RPT;
+        if (right) {
+            hipLaunchKernelGGL(k_ctl_panel, dim3(1), dim3(64), 0, st, d.ctl, (int32_t)p0);
+            hipLaunchKernelGGL(k_fixed_partials, dim3(1), dim3(1024), 0, st, w.wcp, p0, nbe);
+            run_window_steps<T>(w, st, p0, nbe, nbe, 1);
+            window_reorder<T>(w, st, p0, nbe, nbe);
+        }
+        for (int64_t jc = right ? pend : p0; jc < pend; ++jc) {
             const int jj = (int)(jc - p0);
             hipEvent_t ea = prof_begin(st);
             launch_step_a<T>(d, na, jc, p0, jj, 0, st);
@@ -435,11 +450,13 @@ static hipError_t run_blocked_fixed(UpdateWs<T>& w, hipStream_t st, QrcpStats* s
         T* At = d.A + p0 + d.lda * pend;
         const double rc = (double)rows * (double)cols;
         hipEvent_t eg = prof_begin(st);
-        if (!zgemm<T>(st, OP_C, true, OP_N, true, nbe, nbe, rows, C_ONE, V, d.lda, V, d.lda, C_ZERO, w.Gbuf,
-                      UNGQR_NB, w.gsplit, w.gsplit_bytes))
+        // G = V^H V: the window steps have formed its upper triangle
+        if (!right && !zgemm<T>(st, OP_C, true, OP_N, true, nbe, nbe, rows, C_ONE, V, d.lda, V, d.lda, C_ZERO,
+                                w.Gbuf, UNGQR_NB, w.gsplit, w.gsplit_bytes))
             return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_larft<T>), dim3(1), dim3(256), 0, st, w.Gbuf, d.tau + p0, nbe, w.Tbuf);
-        prof_end(eg, st, PK_REFL, (double)sizeof(T) * rows * nbe, 8.0 * (double)nbe * nbe * rows);
+        prof_end(eg, st, PK_REFL, right ? 0.0 : (double)sizeof(T) * rows * nbe,
+                 right ? 0.0 : 8.0 * (double)nbe * nbe * rows);
         hipEvent_t et = prof_begin(st);
         if (!zgemm<T>(st, OP_C, true, OP_N, false, nbe, cols, rows, C_ONE, V, d.lda, At, d.lda, C_ZERO, w.Wbuf,
                       UNGQR_NB, w.gsplit, w.gsplit_bytes))
@@ -451,7 +468,8 @@ static hipError_t run_blocked_fixed(UpdateWs<T>& w, hipStream_t st, QrcpStats* s
             return hipErrorInvalidValue;
         prof_end(e2, st, PK_REFL, (double)sizeof(T) * 2.0 * nbe * cols, 8.0 * (double)nbe * nbe * cols);
         hipEvent_t eu = prof_begin(st);
-        if (!zgemm<T>(st, OP_N, true, OP_N, false, rows, cols, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, C_ONE,
+        if (!zrank_update<T>(st, true, rows, cols, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, At, d.lda) &&
+            !zgemm<T>(st, OP_N, true, OP_N, false, rows, cols, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, C_ONE,
                       At, d.lda, nullptr, 0))
             return hipErrorInvalidValue;
         prof_end(eu, st, PK_TRAIL, 2.0 * (double)sizeof(T) * rc, 8.0 * nbe * rc);
@@ -587,7 +605,7 @@ static void window_setup(UpdateWs<T>& w, hipStream_t st, int64_t p0, bool save)
 // Right-looking pivot steps p0 .. p0+nsteps-1 inside the window (k_window_step),
 // then the window's columns in their final order: pivots first, in step order.
 template <typename T>
-static void run_window_steps(UpdateWs<T>& w, hipStream_t st, int64_t p0, int64_t nsteps, int W, int fixed = 0)
+static void run_window_steps(UpdateWs<T>& w, hipStream_t st, int64_t p0, int64_t nsteps, int W, int fixed)
 {
     QrcpDev<T>& d = w.d;
     // sampled profiling times the whole run with one event pair

@@ -95,6 +95,10 @@ def lib() -> ctypes.CDLL:
     L.mps_update_bond.restype = i32
     L.mps_update_bond.argtypes = [i64, i64, i64, i64, i32, i32, p, p, pd, p, p, ctypes.c_int,
                                   ctypes.POINTER(LearnedCfg), ctypes.POINTER(UpdateInfo), p, i64, p]
+    L.mps_move_work_bytes.restype = i64
+    L.mps_move_work_bytes.argtypes = [i64, i64, i64, i32, i32]
+    L.mps_move_centre.restype = i32
+    L.mps_move_centre.argtypes = [i64, i64, i64, i32, i32, p, p, p, p, pi64, p, i64, p]
     L.mps_theta.restype = i32
     L.mps_theta.argtypes = [i64, i64, i64, i32, p, p, pd, p, i64, p, i64, p]
     L.pivnet_work_bytes.restype = i64
@@ -321,6 +325,27 @@ def mps_update_bond(A, B, g, chi_l, chi_m, chi_r, chi_cap, prec, renormalize=Tru
                                  _ptr(work), work.numel(), stream if stream is not None else stream_ptr()))
     del gbuf
     return {"A": A_out, "B": B_out, "info": info.as_dict(), "k": int(info.k)}
+
+
+def mps_move_centre(A, B, chi_l, chi_c, chi_r, prec, direction, A_out=None, B_out=None, work=None,
+                    stream=None) -> dict:
+    """One centre move (mps_move_centre) on device sites A (chi_l x 2 x chi_c)
+    and B (chi_c x 2 x chi_r); direction +1 (QR of A) or -1 (LQ of B)."""
+    torch = _torch()
+    cd = cdtype(prec)
+    k = min(2 * chi_l, chi_c) if direction > 0 else min(chi_c, 2 * chi_r)
+    if A_out is None:
+        A_out = torch.empty((k, 2, chi_l), dtype=cd, device=A.device)      # chi_l x 2 x k
+    if B_out is None:
+        B_out = torch.empty((chi_r, 2, k), dtype=cd, device=A.device)
+    if work is None:
+        work = torch.empty(max(1, int(lib().mps_move_work_bytes(chi_l, chi_c, chi_r, prec, direction))),
+                           dtype=torch.uint8, device=A.device)
+    kout = ctypes.c_int64(0)
+    _check(lib().mps_move_centre(chi_l, chi_c, chi_r, prec, direction, _ptr(A), _ptr(B), _ptr(A_out), _ptr(B_out),
+                                 ctypes.byref(kout), _ptr(work), work.numel(),
+                                 stream if stream is not None else stream_ptr()))
+    return {"A": A_out, "B": B_out, "k": int(kout.value)}
 
 
 def mps_theta(A, B, g, chi_l, chi_m, chi_r, prec, work=None, stream=None):

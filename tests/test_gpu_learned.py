@@ -114,7 +114,8 @@ def _proposed_order(M, theta_dev, prec, params, sketch_rows, seed):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("m,n,k,seed", [(96, 80, 40, 50), (300, 260, 130, 51), (130, 300, 100, 52)])
+@pytest.mark.parametrize("m,n,k,seed", [(96, 80, 40, 50), (300, 260, 130, 51), (130, 300, 100, 52),
+                                         (8400, 600, 300, 55), (2048, 1400, 700, 56)])
 def test_known_order_qr_matches_oracle(M, prec, m, n, k, seed):
     """Learned mode of qrcp_truncate with an always-accepting rule: piv is the
     proposed order (the same order the proposal pieces give), and Q, R P^T,

@@ -154,3 +154,46 @@ def test_wide_bonds_exact_without_chains(M, prec):
     tol = 1e-10 if prec == 0 else 1e-4
     assert np.max(np.abs(sv - ref)) <= tol * np.max(np.abs(ref))
     assert abs(st.log_norm_fidelity()) <= tol
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("direction", [1, -1])
+@pytest.mark.parametrize("chl,chc,chr_", [(8, 12, 8), (40, 64, 48), (300, 520, 290), (4200, 640, 320)])
+def test_move_centre_matches_oracle(M, prec, direction, chl, chc, chr_):
+    """mps_move_centre against the oracle's unpivoted QR of the same site
+    matrix (rows l + chi_l s of A for a move right; B^H, columns s + 2r of B,
+    for a move left): the isometry and the absorbing neighbour entry by entry
+    (same reflector convention and row order), and the two-site tensor
+    unchanged.  (4200, 640, 320) has 8400 rows when moving right, so its first
+    panel takes the delayed-update steps."""
+    print(f"case move centre ({chl},{chc},{chr_}) dir={direction} prec={prec}", flush=True)
+    r = synth.rng(chl + chc + chr_)
+    a = synth.cgauss(r, (chl, 2, chc))
+    b = synth.cgauss(r, (chc, 2, chr_))
+    if prec == 1:
+        a = a.astype(np.complex64).astype(np.complex128)
+        b = b.astype(np.complex64).astype(np.complex128)
+    out = M.mps_move_centre(M.site_to_device(a, prec), M.site_to_device(b, prec), chl, chc, chr_, prec, direction)
+    k = out["k"]
+    a2 = M.site_from_device(out["A"], chl, k)
+    b2 = M.site_from_device(out["B"], k, chr_)
+    amat = a.transpose(1, 0, 2).reshape(2 * chl, chc)          # rows l + chl s
+    bmat = b.transpose(0, 2, 1).reshape(chc, 2 * chr_)         # columns s + 2r
+    a2mat = a2.transpose(1, 0, 2).reshape(2 * chl, k)
+    b2mat = b2.transpose(0, 2, 1).reshape(k, 2 * chr_)
+    tol = TOL[prec]
+    if direction > 0:
+        f = oracle.qrcp(amat, min(2 * chl, chc), pivoting=False)
+        ref_a, ref_b = f["Q"], f["R"] @ bmat
+        assert k == f["k"]
+        assert np.max(np.abs(a2mat - ref_a)) <= tol
+        assert np.max(np.abs(b2mat - ref_b)) <= tol * np.max(np.abs(ref_b))
+    else:
+        f = oracle.qrcp(bmat.conj().T, min(chc, 2 * chr_), pivoting=False)
+        ref_b, ref_a = f["Q"].conj().T, amat @ f["R"].conj().T
+        assert k == f["k"]
+        assert np.max(np.abs(b2mat - ref_b)) <= tol
+        assert np.max(np.abs(a2mat - ref_a)) <= tol * np.max(np.abs(ref_a))
+    t_in = np.tensordot(a, b, axes=(2, 0))
+    t_out = np.tensordot(a2, b2, axes=(2, 0))
+    assert np.max(np.abs(t_out - t_in)) <= tol * np.max(np.abs(t_in))
