@@ -394,3 +394,50 @@ def qpe_circuit(t: int, alphas, target_init: str = "plus"):
                 gates.append((p, gate_swap()))
     gates += [g for layer in qft_circuit(t, inverse=True) for g in layer]
     return [[g] for g in gates]
+
+
+# --- the headline pair, reproducible across hosts --------------------------------
+
+# numpy's QR runs in OpenBLAS, whose last bits depend on the kernel family
+# and thread count; with both pinned (Haswell kernels need AVX2, which every
+# x86-64 host here has) the same seed gives the same bytes on any host.
+PINNED_BLAS = {"OPENBLAS_CORETYPE": "Haswell", "OPENBLAS_NUM_THREADS": "8"}
+
+
+def headline_pair(chi: int, seed: int = 0):
+    """canonical_pair(rng(seed), chi, chi, chi, exp_spectrum(chi, 150 chi/1024))
+    and the Haar 4x4 gate drawn after it, built in a child process with the
+    pinned BLAS settings.  Returns (a, b, g) as complex128 numpy arrays."""
+    import os
+    import subprocess
+    import sys
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        env = dict(os.environ, **PINNED_BLAS)
+        subprocess.run([sys.executable, "-m", "paper_2505_06119_amd.synth", "--emit-headline", d, str(chi),
+                        str(seed)], env=env, check=True, cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+        return tuple(np.load(os.path.join(d, n + ".npy")) for n in ("a", "b", "g"))
+
+
+def input_digest(*arrays) -> str:
+    """SHA-256 of the arrays' bytes (complex128, C order)."""
+    import hashlib
+    h = hashlib.sha256()
+    for x in arrays:
+        h.update(np.ascontiguousarray(np.asarray(x, dtype=np.complex128)).tobytes())
+    return h.hexdigest()
+
+
+def _emit_headline(directory: str, chi: int, seed: int):
+    import os
+    r = rng(seed)
+    a, b = canonical_pair(r, chi, chi, chi, exp_spectrum(chi, 150.0 * chi / 1024.0))
+    g = haar_unitary(r, 4)
+    for name, x in (("a", a), ("b", b), ("g", g)):
+        np.save(os.path.join(directory, name + ".npy"), x)
+
+
+if __name__ == "__main__":
+    import sys
+    if len(sys.argv) == 5 and sys.argv[1] == "--emit-headline":
+        _emit_headline(sys.argv[2], int(sys.argv[3]), int(sys.argv[4]))

@@ -9,9 +9,10 @@ The full greedy pivoted QR of the 8192 x 8192 theta takes about ten minutes
 on eight cores, so the result is stored rather than recomputed by the tests.
 
 The isometries come from LAPACK's QR (numpy), whose last bits depend on the
-BLAS kernel and thread count; the inputs are therefore built in a child
-process with OpenBLAS pinned to its Haswell kernels and eight threads, which
-gives the same bytes on any x86-64 host with AVX2.
+BLAS kernel and thread count; the inputs are therefore built by
+synth.headline_pair, in a child process with OpenBLAS pinned to its Haswell
+kernels and eight threads, which gives the same bytes on any x86-64 host
+with AVX2.
 
 Stored: a SHA-256 of the input bytes (a test that regenerates the inputs on
 another host checks it before comparing), k, ||theta||^2, eps^2, the norm
@@ -21,12 +22,9 @@ and theta_T = Q_k R_k P^T at 512 seeded positions (row 2l + a', column
 
     python tests/golden/make_chi4096.py [fp64|c64 ...]
 """
-import hashlib
 import json
 import os
-import subprocess
 import sys
-import tempfile
 import time
 
 import numpy as np
@@ -41,23 +39,9 @@ CHI = 4096
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-PINNED_BLAS = {"OPENBLAS_CORETYPE": "Haswell", "OPENBLAS_NUM_THREADS": "8"}
-
-
-def _emit(directory: str):
-    r = synth.rng(0)
-    a, b = synth.canonical_pair(r, CHI, CHI, CHI, synth.exp_spectrum(CHI, 150.0 * CHI / 1024))
-    g = synth.haar_unitary(r, 4)
-    for name, x in (("a", a), ("b", b), ("g", g)):
-        np.save(os.path.join(directory, name + ".npy"), x)
-
-
 def inputs(prec: str):
     """The headline inputs (seed 0), built with the pinned BLAS settings."""
-    with tempfile.TemporaryDirectory() as d:
-        env = dict(os.environ, **PINNED_BLAS)
-        subprocess.run([sys.executable, os.path.abspath(__file__), "--emit", d], env=env, check=True)
-        a, b, g = (np.load(os.path.join(d, n + ".npy")) for n in ("a", "b", "g"))
+    a, b, g = synth.headline_pair(CHI, 0)
     if prec == "c64":
         a = a.astype(np.complex64).astype(np.complex128)
         b = b.astype(np.complex64).astype(np.complex128)
@@ -65,10 +49,7 @@ def inputs(prec: str):
 
 
 def input_digest(a, b, g) -> str:
-    h = hashlib.sha256()
-    for x in (a, b, np.asarray(g, dtype=np.complex128)):
-        h.update(np.ascontiguousarray(x).tobytes())
-    return h.hexdigest()
+    return synth.input_digest(a, b, g)
 
 
 def sample_positions(n_rows: int, n_cols: int, count: int = 512):
@@ -114,7 +95,4 @@ def main(precs):
 
 
 if __name__ == "__main__":
-    if len(sys.argv) == 3 and sys.argv[1] == "--emit":
-        _emit(sys.argv[2])
-    else:
-        main(sys.argv[1:] or ["fp64", "c64"])
+    main(sys.argv[1:] or ["fp64", "c64"])
