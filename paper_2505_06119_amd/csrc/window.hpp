@@ -530,35 +530,49 @@ __device__ __forceinline__ double block_sum_ws(double v, double* lds)
     return s;
 }
 
-// three block sums in one round
+// four block sums in one round
 template <int NW>
-__device__ __forceinline__ void block_sum_ws3(double& a, double& b, double& c, double* lds /* 3 * NW */)
+__device__ __forceinline__ void block_sum_ws4(double& a, double& b, double& c, double& e, double* lds /* 4 * NW */)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     a = wave_sum(a);
     b = wave_sum(b);
     c = wave_sum(c);
+    e = wave_sum(e);
     __syncthreads();
     if (lane == 0) {
         lds[wid] = a;
         lds[NW + wid] = b;
         lds[2 * NW + wid] = c;
+        lds[3 * NW + wid] = e;
     }
     __syncthreads();
-    double sa = 0.0, sb = 0.0, sc = 0.0;
+    double sa = 0.0, sb = 0.0, sc = 0.0, se = 0.0;
     for (int w = 0; w < NW; ++w) {
         sa += lds[w];
         sb += lds[NW + w];
         sc += lds[2 * NW + w];
+        se += lds[3 * NW + w];
     }
     a = sa;
     b = sb;
     c = sc;
+    e = se;
 }
 
-// fixed != 0: unpivoted QR in column order (a centre move).  The partials
-// then carry W - b instead of the norm, so the live column of smallest
-// position wins every argmax (seeded by k_fixed_partials).
+// fixed != 0: unpivoted QR in column order (a centre move, or a known column
+// order).  The partials then carry W - b instead of the norm, so the live
+// column of smallest position wins every argmax (seeded by k_fixed_partials),
+// and no norm is formed.
+// The new residual norm of a live column comes from the same reduction round
+// as the reflector: with c = conj(tau) (v^H a) scale, the rows below the
+// pivot become a_i - c x_i, so
+//     sum |a_i - c x_i|^2 = sum |a_i|^2 - 2 Re(conj(c) sum conj(x_i) a_i)
+//                            + |c|^2 sum |x_i|^2,
+// all three sums taken over the stored column and pivot column in FP64.  The
+// norm is thus exact for the column as it stood at the step's start, moved
+// by one reflector analytically; when that cancels below 1e-6 of sum |a_i|^2
+// it is recomputed from the updated column instead (a second reduction).
 // NT threads per block with RPT rows each (NT * RPT >= m - j): 512 x 16 for
 // the large factorisations, smaller blocks when few rows remain.
 template <typename T, int NT = WSTEP_NT, int RPT = WSTEP_RPT>
@@ -567,11 +581,10 @@ __global__ __launch_bounds__(NT) void k_window_step(QrcpDev<T> d, int64_t j, int
                                                       int fixed)
 {
     constexpr int NW = NT / 64;
-    __shared__ double s_red[3 * NW];
+    __shared__ double s_red[4 * NW];
     __shared__ ArgBest s_arg[NW];
     __shared__ double2 s_alpha, s_aj;
-    __shared__ int s_dead;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
     const int W = gridDim.x, b = blockIdx.x;
     const int64_t c = p0 + b;
     const int m = (int)d.m, j0 = (int)j;   // rows fit 32 bits here
@@ -583,25 +596,20 @@ __global__ __launch_bounds__(NT) void k_window_step(QrcpDev<T> d, int64_t j, int
     const ArgBest e = cin[tid < W ? tid : 0];
     const int32_t own_slot = cin[b].slot;
     const int32_t key_c = d.perm[c];
-    const double nuref_c = d.nuref[c];
     T a[RPT];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const int i = j0 + tid + NT * q;
         a[q] = colc[i < m ? i : m - 1];
     }
-    ArgBest best;
-    best.val = -1.0;
-    best.key = 0x7fffffff;
-    best.slot = -1;
+    ArgBest best = e0_dead();
     if (tid < W && e.slot >= 0) best = e;
     for (int t = tid + NT; t < W; t += NT) {   // windows wider than the block
         const ArgBest f = cin[t];
         if (f.slot >= 0 && arg_better(f.val, f.key, best.val, best.key)) best = f;
     }
-    if (tid == 0) s_dead = own_slot < 0 ? 1 : 0;
     best = wave_argmax(best);
-    if (lane == 0) s_arg[wid] = best;
+    if (lane == 0) s_arg[tid >> 6] = best;
     __syncthreads();
     ArgBest bb = s_arg[0];
     for (int w = 1; w < NW; ++w)
@@ -609,9 +617,10 @@ __global__ __launch_bounds__(NT) void k_window_step(QrcpDev<T> d, int64_t j, int
     if (stop || bb.slot < 0) return;   // uniform over the block
     // a dead block is the pivot of an earlier step i of this panel: it forms
     // the Gram entry G[i, jj] = v_i^H v_jj of the panel's reflectors instead
-    const int gi = s_dead ? wstep[b] : -1;
-    if (s_dead && tid == 0) cout[b] = e0_dead();
-    if (s_dead && (gi < 0 || gi >= jj)) return;
+    const bool dead = own_slot < 0;
+    const int gi = dead ? wstep[b] : -1;
+    if (dead && tid == 0) cout[b] = e0_dead();
+    if (dead && (gi < 0 || gi >= jj)) return;
     const int64_t p = bb.slot;
 
     // the pivot column and its reflector (identical arithmetic in every block)
@@ -632,26 +641,29 @@ __global__ __launch_bounds__(NT) void k_window_step(QrcpDev<T> d, int64_t j, int
             a[q] = vi[i < m ? i : m - 1];
         }
     }
-    // one reduction round for ||x_rest||^2 and g = sum_{i>j} conj(x_i) a_i;
-    // then v^H a = a_j + conj(scale) g with v = (1, scale * x_rest)
-    double rest = 0.0, gre = 0.0, gim = 0.0;
+    // one reduction round for ||x_rest||^2, g = sum_{i>j} conj(x_i) a_i and
+    // ||a_rest||^2; then v^H a = a_j + conj(scale) g with v = (1, scale * x_rest)
+    const bool want_norm = !fixed && gi < 0;
+    double rest = 0.0, gre = 0.0, gim = 0.0, sa = 0.0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const int i = j0 + tid + NT * q;
         if (i > j0 && i < m) {
             const double2 xi = to_d(x[q]);
+            const double2 ai = to_d(a[q]);
             rest += cabs2(xi);
             // live: conj(x) a; dead: conj(v_i) x
-            const double2 t = gi >= 0 ? cmulc(to_d(a[q]), xi) : cmulc(xi, to_d(a[q]));
+            const double2 t = gi >= 0 ? cmulc(ai, xi) : cmulc(xi, ai);
             gre += t.x;
             gim += t.y;
+            if (want_norm) sa += cabs2(ai);
         }
     }
     if (tid == 0) {
         s_alpha = to_d(x[0]);
         s_aj = to_d(a[0]);
     }
-    block_sum_ws3<NW>(rest, gre, gim, s_red);   // its barriers also publish s_alpha, s_aj
+    block_sum_ws4<NW>(rest, gre, gim, sa, s_red);   // its barriers also publish s_alpha, s_aj
     const double2 alpha = s_alpha;
     double2 tau, scale;
     double beta;
@@ -693,11 +705,23 @@ __global__ __launch_bounds__(NT) void k_window_step(QrcpDev<T> d, int64_t j, int
         return;
     }
 
-    // w = v^H a
-    const double2 wv = cadd(s_aj, cmul(cconj(scale), make_double2(gre, gim)));
+    // w = v^H a, coef = conj(tau) w; the rows below j move by -coef scale x
+    const double2 g = make_double2(gre, gim);
+    const double2 wv = cadd(s_aj, cmul(cconj(scale), g));
     const double2 coef = cmul(cconj(tau), wv);
-    // a -= conj(tau) v (v^H a); exact residual norm of rows > j afterwards
-    double nn = 0.0;
+    const double2 cs = cmul(coef, scale);
+    double nn = sa - 2.0 * (cs.x * g.x + cs.y * g.y) + cabs2(cs) * rest;
+    const bool recompute = want_norm && !(nn > 1e-6 * sa);   // uniform: from block-wide sums
+    if (tid == 0 && !recompute) {
+        ArgBest mine;
+        mine.val = fixed ? (double)(W - b) : (nn > 0.0 ? nn : 0.0);
+        mine.key = key_c;
+        mine.slot = (int32_t)c;
+        cout[b] = mine;
+        if (want_norm) d.nu[c] = mine.val;
+    }
+    // a -= conj(tau) v (v^H a)
+    double ne = 0.0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const int i = j0 + tid + NT * q;
@@ -705,18 +729,19 @@ __global__ __launch_bounds__(NT) void k_window_step(QrcpDev<T> d, int64_t j, int
             const double2 vi = i == j0 ? make_double2(1.0, 0.0) : cmul(scale, to_d(x[q]));
             const T an = from_d<T>(csub(to_d(a[q]), cmul(coef, vi)));
             colc[i] = an;
-            if (i > j0) nn += cabs2(to_d(an));
+            if (recompute && i > j0) ne += cabs2(to_d(an));
         }
     }
-    nn = block_sum_ws<NW>(nn, s_red);
-    if (tid == 0) {
-        d.nu[c] = nn;
-        (void)nuref_c;
-        ArgBest mine;
-        mine.val = fixed ? (double)(W - b) : nn;
-        mine.key = key_c;
-        mine.slot = (int32_t)c;
-        cout[b] = mine;
+    if (recompute) {
+        ne = block_sum_ws<NW>(ne, s_red);
+        if (tid == 0) {
+            ArgBest mine;
+            mine.val = ne;
+            mine.key = key_c;
+            mine.slot = (int32_t)c;
+            cout[b] = mine;
+            d.nu[c] = ne;
+        }
     }
 }
 
