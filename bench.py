@@ -680,8 +680,12 @@ def main():
         lc = M.learned_cfg(params, sketch_rows=64, verify=False, seed=7)
         runs["learned"] = time_path(M, L, torch, "learned", M.MPS_MIXED, a, b, g, chi, args.steps, args.warmup,
                                     learned=lc)
+        # what an accepted proposal costs: the same path with every proposal kept
+        lt = M.learned_cfg(params, sketch_rows=64, verify="trust", seed=7)
+        runs["learned_trusted"] = time_path(M, L, torch, "learned, proposal kept unchecked", M.MPS_MIXED, a, b, g,
+                                            chi, max(3, args.steps // 4), 1, learned=lt)
 
-    rates = {k: args.steps / v["seconds"] for k, v in runs.items()}
+    rates = {k: len(v["per_step"]) / v["seconds"] for k, v in runs.items()}
     oracle_cmp, devs = {}, {}
     for k, v in runs.items():
         prec = 0 if k == "fp64" else 1
@@ -751,9 +755,10 @@ def main():
               "kernels": "k_zgemm W = V^H A and k_zrank A -= V W2 of every panel (8 flops per complex "
                          "multiply-add), event-timed in one extra update"}
         res.setdefault("roofline", {})["trailing_update"] = tu
+    runs_err_q = runs["mixed"]["infos"][-1]["trunc_err_sq"]
     for k, v in runs.items():
         last = v["infos"][-1]
-        res[f"path_{k}"] = {"value": rates[k], "unit": "updates/s", "ms_per_step": 1000.0 * v["seconds"] / args.steps,
+        res[f"path_{k}"] = {"value": rates[k], "unit": "updates/s", "ms_per_step": 1000.0 * v["seconds"] / len(v["per_step"]),
                             "step_ms": step_stats(v["per_step"]),
                             "retained": last["retained"], "panels": last["panels"],
                             "refreshes": last["refreshes"], "window_misses": last["window_misses"],
@@ -762,8 +767,10 @@ def main():
                             "kernels_note": "one extra update outside the timed region with every launch "
                                             "event-timed (markers add to that update: "
                                             f"{1000.0 * v['prof_seconds']:.1f} ms)"}
-        if k == "learned":
+        if k.startswith("learned"):
             res[f"path_{k}"]["learned_err_sq"] = last["learned_err_sq"]
+            res[f"path_{k}"]["eps_ratio_vs_qrcp"] = (float(np.sqrt(last["learned_err_sq"] / runs_err_q))
+                                                    if runs_err_q > 0 else None)
             res[f"path_{k}"]["qrcp_err_sq"] = last["qrcp_err_sq"]
         if oracle_cmp.get(k) is not None:
             res[f"path_{k}"]["vs_oracle"] = oracle_cmp[k]

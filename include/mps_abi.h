@@ -89,14 +89,16 @@ typedef struct {
  *               the smallest |R_jj| of the selected ones (what plain pivoted QR
  *               guarantees by construction);
  *   verify = 1  plain pivoted QR also runs and the proposal is kept only if
- *               its truncation error is at most fallback_ratio times QRCP's.
+ *               its truncation error is at most fallback_ratio times QRCP's;
+ *   verify = 2  trusted: the proposal is kept without a check (its error is
+ *               still reported), to measure what the proposal path costs.
  * A rejected proposal falls back to plain pivoted QR of the same theta. */
 #define MPS_PIVNET_PARAMS 97
 #define MPS_PIVNET_FEATURES 4
 typedef struct {
     const float* params;   /* device, MPS_PIVNET_PARAMS floats */
     int32_t sketch_rows;   /* 1..256 */
-    int32_t verify;        /* 0 or 1, see above */
+    int32_t verify;        /* 0, 1 or 2, see above */
     uint64_t seed;
     double fallback_ratio; /* >= 1, e.g. 1.01 */
 } mps_learned_cfg;
@@ -267,7 +269,7 @@ typedef struct {
     /* learned pivots, optional: the proposal network's parameters (device,
      * MPS_PIVNET_PARAMS float32, must stay valid) and the acceptance rule
      * (learned_verify 0: certificate, 1: verification against plain pivoted
-     * QR).  NULL leaves the network unset until mps_set_pivot_network. */
+     * QR, 2: trusted).  NULL leaves the network unset until mps_set_pivot_network. */
     const float* mlp_weights;
     int32_t learned_verify;
     int32_t pad2;

@@ -160,7 +160,9 @@ static mps_status factorise(UpdateWs<T>& w, LearnWs<T>* L, const mps_learned_cfg
     prof_flush();
     out.eps_s2 = dsc2[DSC_EPS2];
     bool accept;
-    if (lc->verify) {
+    if (lc->verify == 2) {
+        accept = true;   // trusted: kept without a check (measures the proposal's own cost)
+    } else if (lc->verify) {
         HIPCHK(run_qrcp<T>(w, st, &out.stats, nparts), "verification QRCP");
         double dq[DSC_COUNT];
         HIPCHK(hipMemcpyAsync(dq, d.dsc, sizeof(dq), hipMemcpyDeviceToHost, st), "verification readback");
@@ -177,7 +179,7 @@ static mps_status factorise(UpdateWs<T>& w, LearnWs<T>* L, const mps_learned_cfg
         out.stats = s2;
     } else {
         out.fallback = 1;
-        if (!lc->verify) HIPCHK(run_qrcp<T>(w, st, &out.stats, nparts), "fallback QRCP");
+        if (lc->verify == 0) HIPCHK(run_qrcp<T>(w, st, &out.stats, nparts), "fallback QRCP");
     }
     return MPS_OK;
 }
@@ -261,7 +263,7 @@ static mps_status update_core(int64_t chi_l, int64_t chi_m, int64_t chi_r, int64
 static bool learned_cfg_valid(const mps_learned_cfg* lc)
 {
     return lc && lc->params && lc->sketch_rows >= 1 && lc->sketch_rows <= PN_ELL_MAX &&
-           (lc->verify == 0 || lc->verify == 1) && lc->fallback_ratio >= 1.0 && isfinite(lc->fallback_ratio);
+           (lc->verify >= 0 && lc->verify <= 2) && lc->fallback_ratio >= 1.0 && isfinite(lc->fallback_ratio);
 }
 
 extern "C" int64_t mps_update_work_bytes(int64_t chi_l, int64_t chi_m, int64_t chi_r, int64_t chi_cap,

@@ -296,8 +296,11 @@ def mps_update_work_bytes(chi_l, chi_m, chi_r, chi_cap, prec, pivot=MPS_PIVOT_QR
 
 
 def learned_cfg(params, sketch_rows=64, verify=False, seed=1234, fallback_ratio=1.01) -> LearnedCfg:
-    """mps_learned_cfg for a device float32 parameter tensor of PIVNET_PARAMS entries."""
-    return LearnedCfg(params.data_ptr(), int(sketch_rows), 1 if verify else 0, int(seed), float(fallback_ratio))
+    """mps_learned_cfg for a device float32 parameter tensor of PIVNET_PARAMS entries.
+    verify: False (certificate), True (verification against plain pivoted QR)
+    or "trust" (the proposal is kept unchecked)."""
+    v = 2 if verify == "trust" else (1 if verify else 0)
+    return LearnedCfg(params.data_ptr(), int(sketch_rows), v, int(seed), float(fallback_ratio))
 
 
 def mps_update_bond(A, B, g, chi_l, chi_m, chi_r, chi_cap, prec, renormalize=True, A_out=None, B_out=None,
