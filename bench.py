@@ -809,12 +809,21 @@ def main():
         log("[bench] grid random circuit with and without same-bond fusion")
         res["routed_grid"] = routed_grid(M, torch, synth)
     if not args.no_configs:
+        log("[bench] autotuning the pivoted-QR tiles per bond bucket (mixed, chi up to 4096)")
+        t0 = time.perf_counter()
+        table = M.autotune(4096, M.MPS_MIXED)
+        res["autotune"] = {"table": table, "seconds": time.perf_counter() - t0,
+                           "note": "the grid-circuit slices below run with these tiles; the headline ran with "
+                                   "the defaults (32, 256)"}
+        log("[bench] autotune: " + ", ".join(f"n<={e['n_max']}: ({e['panel_width']}, {e['qr_window']}) "
+                                             f"{e['ms']:.2f} ms vs {e['ms_default']:.2f}" for e in table))
         log("[bench] 5x8 grid circuit, chi cap 4096 (time-bounded slice)")
         res["grid_5x8_chi4096"] = grid_slice(M, torch, synth, 5, 8, 14, 4096, args.slice_seconds, 600)
         torch.cuda.empty_cache()
         log("[bench] 6x9 grid circuit, chi cap 8192 (time-bounded slice)")
         res["grid_6x9_chi8192"] = grid_slice(M, torch, synth, 6, 9, 12, 8192, args.slice_seconds, 601)
         torch.cuda.empty_cache()
+        M.clear_autotune()
     if not args.no_cpu_baseline:
         if a_h is None:
             a_h = M.site_from_device(a, chi, chi)

@@ -345,6 +345,35 @@ mps_status mps_get_site(mps_ctx* ctx, int32_t j, void* dst, int64_t dst_bytes);
 mps_status mps_set_tuning(int32_t panel_width, int32_t qr_window);
 
 /* ------------------------------------------------------------------------
+ * Autotuner of the pivoted-QR tiles, process-wide (not thread-safe; affects
+ * later calls).  A circuit layer holds two-site updates of very different
+ * bond dimensions (Sec. III-D: bonds grow from 2 up to the cap); the panel
+ * width and candidate-window width that make the pivoted QR fastest differ
+ * between them.  mps_autotune times, on the caller's stream, one synthetic
+ * update per candidate (panel width 16/32/64 with window 0/128/256/512) for
+ * each bond bucket chi = 128, 256, ... <= chi_max (chi_l = chi_m = chi_r =
+ * chi, a Gaussian pair whose middle bond carries exp(-k / (150 chi / 1024)),
+ * precision prec), keeps the fastest, and from then on every pivoted QR
+ * with n columns uses the entry of the first bucket with n <= n_max.  The
+ * pivots themselves do not depend on the tiles.  mps_set_tuning with
+ * explicit values overrides the table; mps_clear_autotune drops it.
+ *   work: device scratch of mps_autotune_work_bytes(chi_max, prec) bytes;
+ *   table: host, max_entries entries; *n_entries receives the count.
+ * chi_max must lie in [128, 8192].
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n_max;        /* column counts this entry covers (above the previous entry's) */
+    int32_t panel_width;  /* chosen panel width */
+    int32_t qr_window;    /* chosen candidate-window width (0: no window) */
+    double ms;            /* time of the tuning update with these tiles */
+    double ms_default;    /* time with the built-in default (32, 256) */
+} mps_tune_entry;
+int64_t mps_autotune_work_bytes(int32_t chi_max, mps_precision prec);
+mps_status mps_autotune(int32_t chi_max, mps_precision prec, void* work, int64_t work_bytes, void* hip_stream,
+                        mps_tune_entry* table, int32_t max_entries, int32_t* n_entries);
+mps_status mps_clear_autotune(void);
+
+/* ------------------------------------------------------------------------
  * Small-bond chains, process-wide (not thread-safe; affects later calls).
  * mps_apply_gate / mps_apply_layer run a gate sequence as the ordered chain
  * of centre moves (unpivoted QR / LQ, Sec. III-C.1) and two-site updates

@@ -52,6 +52,17 @@ static int g_panel_width = 0;
 static int g_qr_window = -1;
 #define QR_WIN_DEFAULT 256
 
+// Tiles chosen by mps_autotune per bucket of column counts (sorted by n_max;
+// empty: the built-in defaults).  Explicit values of mps_set_tuning win.
+static std::vector<mps_tune_entry> g_tune;
+
+static const mps_tune_entry* tuned_for(int64_t n)
+{
+    for (const mps_tune_entry& e : g_tune)
+        if (n <= e.n_max) return &e;
+    return nullptr;
+}
+
 // Panel width of the delayed-update QRCP: wider panels raise the arithmetic
 // intensity of the rank-nb trailing update but lengthen every pivot step's
 // F-correction.
@@ -60,14 +71,19 @@ static int panel_width(int64_t m, int64_t n)
     (void)m;
     if (g_panel_width > 0) return n <= 64 && g_panel_width > 16 ? 16 : g_panel_width;
     if (n <= 64) return 16;
+    if (const mps_tune_entry* e = tuned_for(n)) return e->panel_width;
     return 32;
 }
 
-// Candidate-window width for a pivoted factorisation with panel width nb
-// (0: no window panels).
-static int qr_window(int nb)
+// Candidate-window width for a pivoted factorisation of n columns with panel
+// width nb (0: no window panels).
+static int qr_window(int nb, int64_t n)
 {
-    const int w = g_qr_window < 0 ? QR_WIN_DEFAULT : g_qr_window;
+    int w = g_qr_window;
+    if (w < 0) {
+        const mps_tune_entry* e = g_panel_width > 0 ? nullptr : tuned_for(n);
+        w = e ? e->qr_window : QR_WIN_DEFAULT;
+    }
     return w >= nb && w <= QR_WIN_MAX ? w : 0;
 }
 
@@ -130,7 +146,7 @@ static mps_status qrcp_impl(int64_t m, int64_t n, int64_t k, mps_precision prec,
     if (lc && !carve_learn_ws<T>(cv, L, m, n, k, lc->sketch_rows))
         return fail(MPS_ENOMEM, "qrcp_truncate: work_bytes %lld too small for learned pivots", (long long)work_bytes);
     w.nb = panel_width(m, n);
-    w.win = qr_window(w.nb);
+    w.win = qr_window(w.nb, n);
     w.d.tol = recompute_tol(prec);
     w.d.pivoting = 1;
     {
@@ -280,6 +296,9 @@ extern "C" mps_status qrcp_truncate_noalloc(int64_t m, int64_t n, int64_t k_max,
 
 // stateful MPS context
 #include "context.hpp"
+
+// autotuner of the pivoted-QR tiles
+#include "autotune.hpp"
 
 // ---------------------------------------------------------------------------
 // per-kernel timing

@@ -220,7 +220,7 @@ static mps_status update_core(int64_t chi_l, int64_t chi_m, int64_t chi_r, int64
     if (lc && !carve_learn_ws<T>(cv, L, m, n, k, lc->sketch_rows))
         return fail(MPS_ENOMEM, "update: workspace too small for the learned path");
     w.nb = panel_width(m, n);
-    w.win = qr_window(w.nb);
+    w.win = qr_window(w.nb, n);
     w.d.tol = recompute_tol(prec);
     w.d.pivoting = 1;
     QrcpDev<T>& d = w.d;

@@ -55,6 +55,14 @@ class LearnedCfg(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
 
 
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("n_max", ctypes.c_int64), ("panel_width", ctypes.c_int32), ("qr_window", ctypes.c_int32),
+                ("ms", ctypes.c_double), ("ms_default", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class Config(ctypes.Structure):
     _fields_ = [("n_sites", ctypes.c_int32), ("chi_max", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("pivot", ctypes.c_int32), ("fallback_ratio", ctypes.c_double), ("sketch_rows", ctypes.c_int32),
@@ -117,6 +125,12 @@ def lib() -> ctypes.CDLL:
     L.mps_set_pivot_network.argtypes = [p, ctypes.POINTER(LearnedCfg)]
     L.mps_set_tuning.restype = i32
     L.mps_set_tuning.argtypes = [i32, i32]
+    L.mps_autotune_work_bytes.restype = i64
+    L.mps_autotune_work_bytes.argtypes = [i32, i32]
+    L.mps_autotune.restype = i32
+    L.mps_autotune.argtypes = [i32, i32, p, i64, p, ctypes.POINTER(TuneEntry), i32, ctypes.POINTER(i32)]
+    L.mps_clear_autotune.restype = i32
+    L.mps_clear_autotune.argtypes = []
     L.mps_set_small_bond_limit.restype = i32
     L.mps_set_small_bond_limit.argtypes = [i32]
     L.mps_set_truncation.restype = i32
@@ -219,6 +233,25 @@ def set_tuning(panel_width: int = 0, qr_window: int = -1):
     """Process-wide pivoted-QR tuning (mps_set_tuning): panel width (0 = automatic)
     and candidate-window width (-1 = automatic, 0 = off)."""
     _check(lib().mps_set_tuning(panel_width, qr_window))
+
+
+def autotune(chi_max: int, prec: int, stream=None) -> list:
+    """Tune the pivoted-QR tiles per bond bucket up to chi_max (mps_autotune);
+    returns the table as a list of dicts.  Process-wide from then on."""
+    torch = _torch()
+    wb = int(lib().mps_autotune_work_bytes(chi_max, prec))
+    if wb < 0:
+        raise MpsError(1, f"mps_autotune_work_bytes({chi_max}, {prec}) rejected its arguments")
+    work = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    table = (TuneEntry * 8)()
+    n = ctypes.c_int32(0)
+    _check(lib().mps_autotune(chi_max, prec, _ptr(work), wb, stream if stream is not None else stream_ptr(),
+                              table, 8, ctypes.byref(n)))
+    return [table[i].as_dict() for i in range(n.value)]
+
+
+def clear_autotune():
+    _check(lib().mps_clear_autotune())
 
 
 def set_small_bond_limit(max_dim: int = 64):

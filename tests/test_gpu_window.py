@@ -111,3 +111,35 @@ def test_window_tall_delayed_steps(M, prec):
     assert abs(g["err"] - o["err"]) <= tol * scale
     approx_o = o["Q"] @ oracle.r_unpivot(o["R"], o["piv"])
     assert np.linalg.norm(g["Q"] @ g["RPt"] - approx_o) <= tol * scale
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_autotune_table_and_invariance(M, prec):
+    """mps_autotune returns one valid entry per bucket up to chi_max, and the
+    tuned tiles change no result: pivots, R_jj and the truncated product equal
+    those of the default tiles."""
+    print(f"case autotune prec={prec}", flush=True)
+    chi = 200
+    r = synth.rng(70)
+    a, b = synth.canonical_pair(r, chi, chi, chi, synth.exp_spectrum(chi, 150.0 * chi / 1024.0))
+    th = oracle.theta(a, b, synth.haar_unitary(r, 4))
+    if prec == 1:
+        th = th.astype(np.complex64).astype(np.complex128)
+    ref = _qrcp(M, th, chi, prec)
+    table = M.autotune(512, prec)
+    try:
+        assert [e["n_max"] for e in table][:2] == [362, 724] and len(table) == 3
+        for e in table:
+            assert e["panel_width"] in (16, 32, 64)
+            assert e["qr_window"] == 0 or 64 <= e["qr_window"] <= 512
+            assert 0 < e["ms"] <= e["ms_default"] * (1 + 1e-9)
+        got = _qrcp(M, th, chi, prec)
+    finally:
+        M.clear_autotune()
+    tol = TOL[prec]
+    scale = np.linalg.norm(th)
+    if prec == 0:   # complex64 norms can order near-ties differently under other tiles
+        assert list(got["piv"][:chi]) == list(ref["piv"][:chi])
+        np.testing.assert_allclose(got["diagR"], ref["diagR"], rtol=tol, atol=tol * scale)
+    assert abs(got["err"] - ref["err"]) <= tol * scale
+    assert np.linalg.norm(got["Q"] @ got["RPt"] - ref["Q"] @ ref["RPt"]) <= tol * scale
