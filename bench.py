@@ -628,6 +628,9 @@ def main():
                     help="wall-time budget of each grid-circuit slice (chi cap 4096 and 8192)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 512 MiB device copy (reference dispatch for HBM counters)")
+    ap.add_argument("--save-inputs", default=None,
+                    help="build the pinned headline pair, save it to this .npz and exit (for profiler runs)")
+    ap.add_argument("--load-inputs", default=None, help="use a headline pair saved by --save-inputs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the two-site update is built for a single MI355X "
@@ -657,9 +660,18 @@ def main():
         a, b = synth.canonical_pair_device(r, chi, chi, chi, synth.exp_spectrum(chi, scale))
         g = synth.haar_unitary(r, 4)
     else:
-        log(f"[bench] building the chi={chi} headline pair on the CPU (pinned BLAS, seed 0)")
         t0 = time.perf_counter()
-        a_h, b_h, g = synth.headline_pair(chi, 0)
+        if args.load_inputs:
+            log(f"[bench] loading the chi={chi} headline pair from {args.load_inputs}")
+            with np.load(args.load_inputs, allow_pickle=False) as z:
+                a_h, b_h, g = z["a"], z["b"], z["g"]
+        else:
+            log(f"[bench] building the chi={chi} headline pair on the CPU (pinned BLAS, seed 0)")
+            a_h, b_h, g = synth.headline_pair(chi, 0)
+        if args.save_inputs:
+            np.savez(args.save_inputs, a=a_h, b=b_h, g=g)
+            log(f"[bench] saved the inputs to {args.save_inputs}")
+            return
         for prec in (0, 1):
             gold = golden(prec)
             if gold is not None:
