@@ -297,6 +297,11 @@ struct UpdateWs {
     QrcpDev<T> d;
     T* Gbuf;       // UNGQR_NB^2
     T* Tbuf;       // UNGQR_NB^2
+    T* Tbuf2;      // UNGQR_NB^2: the T of alternate panels of the unpivoted QR (its update of panel p runs beside panel p+1)
+    T* Wsm;        // UNGQR_NB^2: W = V^H A_t of the next panel's columns only (the lookahead update)
+    T* W2sm;       // UNGQR_NB^2: and T^H W
+    void* gsplit2; // split-K scratch of the GEMMs on the panel's stream while the trailing update runs beside it
+    int64_t gsplit2_bytes;
     T* Gall;       // Q formation: V^H V of every UNGQR_NB block (ceil(k / UNGQR_NB) x UNGQR_NB^2)
     T* Tall;       // and their T factors
     T* Wbuf;       // UNGQR_NB x k
@@ -316,6 +321,8 @@ struct UpdateWs {
     int32_t* worder;         // 1 + 3 QR_WIN_MAX: the panel-end column moves of the window
     T* wtmp;                 // like wsave: the window reordered at the panel end
     T* vbuf;                 // QR_NBMAX columns of lda: beta and v of those steps
+    int32_t* wflag;          // QR_NBMAX: step flags of the one-launch unpivoted panels
+    double2* wscale;         // QR_NBMAX: the FP64 scale of those panels' reflectors
     double* wtnu;            // QR_WIN_MAX
     double* wtnuref;         // QR_WIN_MAX
     int32_t* wtperm;         // QR_WIN_MAX
@@ -354,6 +361,11 @@ static bool carve_update_ws(Carver& cv, UpdateWs<T>& w, int64_t m, int64_t n, in
     d.dsc = (double*)cv.take(8 * DSC_COUNT);
     w.Gbuf = (T*)cv.take((int64_t)sizeof(T) * UNGQR_NB * UNGQR_NB);
     w.Tbuf = (T*)cv.take((int64_t)sizeof(T) * UNGQR_NB * UNGQR_NB);
+    w.Tbuf2 = (T*)cv.take((int64_t)sizeof(T) * UNGQR_NB * UNGQR_NB);
+    w.Wsm = (T*)cv.take((int64_t)sizeof(T) * UNGQR_NB * UNGQR_NB);
+    w.W2sm = (T*)cv.take((int64_t)sizeof(T) * UNGQR_NB * UNGQR_NB);
+    w.gsplit2_bytes = (int64_t)sizeof(T) * 16 * UNGQR_NB * UNGQR_NB;
+    w.gsplit2 = cv.take(w.gsplit2_bytes);
     const int64_t qblocks = (k + UNGQR_NB - 1) / UNGQR_NB > 0 ? (k + UNGQR_NB - 1) / UNGQR_NB : 1;
     w.Gall = (T*)cv.take((int64_t)sizeof(T) * UNGQR_NB * UNGQR_NB * qblocks);
     w.Tall = (T*)cv.take((int64_t)sizeof(T) * UNGQR_NB * UNGQR_NB * qblocks);
@@ -376,14 +388,17 @@ static bool carve_update_ws(Carver& cv, UpdateWs<T>& w, int64_t m, int64_t n, in
     w.worder = (int32_t*)cv.take(4 * (1 + 3 * QR_WIN_MAX));
     w.wtmp = (T*)cv.take((int64_t)sizeof(T) * d.lda * (wmax > 0 ? wmax : 1));
     w.vbuf = (T*)cv.take((int64_t)sizeof(T) * d.lda * QR_NBMAX);
+    w.wflag = (int32_t*)cv.take(4 * QR_NBMAX);
+    w.wscale = (double2*)cv.take(16 * QR_NBMAX);
     w.wtnu = (double*)cv.take(8 * QR_WIN_MAX);
     w.wtnuref = (double*)cv.take(8 * QR_WIN_MAX);
     w.wtperm = (int32_t*)cv.take(4 * QR_WIN_MAX);
     w.win = 0;
     return d.nu && d.nuref && d.perm && d.F && d.tau && d.diagR && d.xbuf && d.xlo && d.apart && d.hh && d.fsave &&
-           d.cpart && d.npart && d.cflag && d.ctl && d.dsc && w.Gbuf && w.Tbuf && w.Gall && w.Tall && w.Wbuf && w.W2buf && w.gsplit &&
+           d.cpart && d.npart && d.cflag && d.ctl && d.dsc && w.Gbuf && w.Tbuf && w.Tbuf2 && w.Wsm && w.W2sm &&
+           w.gsplit2 && w.Gall && w.Tall && w.Wbuf && w.W2buf && w.gsplit &&
            d.pivval && d.pivkey && w.wplan && w.wsave && w.wsnu && w.wsnuref && w.wsperm && w.wcp &&
-           w.wpiv && w.wstep && w.worder && w.wtmp && w.vbuf && w.wtnu && w.wtnuref && w.wtperm &&
+           w.wpiv && w.wstep && w.worder && w.wtmp && w.vbuf && w.wflag && w.wscale && w.wtnu && w.wtnuref && w.wtperm &&
            (!theta_in_ws || d.A);
 }
 
@@ -397,22 +412,94 @@ struct QrcpStats {
     int window_misses = 0;   // window panels cut short by the greedy replay
 };
 
-template <typename T> static void run_window_steps(UpdateWs<T>& w, hipStream_t st, int64_t p0, int64_t nsteps, int W,
-                                                     int fixed = 0);
+template <typename T> static void run_window_steps(UpdateWs<T>& w, hipStream_t st, int64_t p0, int64_t nsteps, int W);
 template <typename T> static void window_reorder(UpdateWs<T>& w, hipStream_t st, int64_t p0, int nbe, int W);
+template <typename T> static void run_fixed_panel(UpdateWs<T>& w, hipStream_t st, int64_t p0, int64_t nsteps, int W);
+
+// Set for the duration of a call that must not allocate: the control-block
+// readback then uses its pinned mailbox only if an earlier call has already
+// allocated it, and the unpivoted QR keeps to the caller's stream.
+static thread_local bool g_no_alloc = false;
+
+// A second stream per device and host thread (default priority, created on
+// first use and kept for the life of the thread) with three events, for the
+// trailing updates that run beside the next panel's factorisation.  Null when
+// it cannot be created or when the caller must not allocate; the work then
+// stays on the caller's stream.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, panel = nullptr, trail = nullptr;
+    bool failed = false;
+};
+#define SIDE_MAX_DEVICES 16
+static SideStream* side_stream()
+{
+    if (g_no_alloc) return nullptr;
+    static thread_local SideStream per_dev[SIDE_MAX_DEVICES];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= SIDE_MAX_DEVICES) return nullptr;
+    SideStream& ss = per_dev[dev];
+    if (ss.failed) return nullptr;
+    if (!ss.s) {
+        if (hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&ss.panel, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&ss.trail, hipEventDisableTiming) != hipSuccess) {
+            ss.failed = true;
+            (void)hipGetLastError();
+            return nullptr;
+        }
+    }
+    return &ss;
+}
+
+// A_t -= V T^H... : the block reflector of one panel applied to the columns
+// A_t (rows x cols, from row p0) as three MFMA GEMMs W = V^H A_t, W2 = T^H W,
+// A_t -= V W2, on stream st with its own W, W2 and split-K scratch.
+template <typename T>
+static bool panel_update(hipStream_t st, const T* V, int64_t lda, const T* Tm, int nbe, int64_t rows, int64_t cols,
+                         T* At, T* Wb, T* W2b, int64_t ldw, void* split, int64_t split_bytes)
+{
+    const double rc = (double)rows * (double)cols;
+    hipEvent_t et = prof_begin(st);
+    if (!zgemm<T>(st, OP_C, true, OP_N, false, nbe, cols, rows, C_ONE, V, lda, At, lda, C_ZERO, Wb, ldw, split,
+                  split_bytes))
+        return false;
+    prof_end(et, st, PK_PANEL, (double)sizeof(T) * rc, 8.0 * nbe * rc);
+    hipEvent_t e2 = prof_begin(st);
+    if (!zgemm<T>(st, OP_C, false, OP_N, false, nbe, cols, nbe, C_ONE, Tm, UNGQR_NB, Wb, ldw, C_ZERO, W2b, ldw,
+                  nullptr, 0))
+        return false;
+    prof_end(e2, st, PK_REFL, (double)sizeof(T) * 2.0 * nbe * cols, 8.0 * (double)nbe * nbe * cols);
+    hipEvent_t eu = prof_begin(st);
+    if (!zrank_update<T>(st, true, rows, cols, nbe, C_MONE, V, lda, W2b, ldw, At, lda) &&
+        !zgemm<T>(st, OP_N, true, OP_N, false, rows, cols, nbe, C_MONE, V, lda, W2b, ldw, C_ONE, At, lda, nullptr, 0))
+        return false;
+    prof_end(eu, st, PK_TRAIL, 2.0 * (double)sizeof(T) * rc, 8.0 * nbe * rc);
+    return true;
+}
 
 // Householder QR of d.A with the columns in their given order (a centre move,
 // or QR with a column order known in advance).  Only the panel's own columns
 // go through per-column steps; the trailing columns receive the panel's block
-// reflector I - V T V^H at the panel end, as three MFMA GEMMs
-//     W = V^H A_t,  W2 = T^H W,  A_t -= V W2      (A_t = A[p0:, pend:]).
+// reflector I - V T V^H at the panel end (panel_update).  With the order
+// fixed, panel p + 1 depends only on its own columns, so the update is split
+// (look-ahead): the next panel's columns are updated on the caller's stream,
+// right before that panel is factorised, while the rest of the trailing
+// block is updated on a second stream, beside the factorisation of panel
+// p + 1.  Events keep the order per column: panel p's update of the far
+// columns waits for panel p's factors, and the next-panel update of panel
+// p + 1's columns waits for panel p - 1's far update, which covered them.
+// T is double-buffered (panel p's far update may still read it while panel
+// p + 1 forms its own), and each stream has its own GEMM scratch.
 // While the rows left fit one window-step block (m - p0 <= 8192), a panel is
-// a window of its own nb columns factorised by right-looking k_window_step
-// launches in column order (one launch per column; the steps also form the
-// Gram matrix V^H V of the panel's reflectors); taller panels take the
-// delayed-update steps (step A + step C, two launches per column) and a GEMM
-// for V^H V.  Nothing depends on data on the host, so no synchronisation is
-// needed.
+// a window of its own nb columns factorised by one k_fixed_panel launch
+// (each column's block applies the panel's earlier reflectors as they are
+// published); taller panels take the delayed-update steps (step A + step C,
+// two launches per column).  Either way a GEMM forms V^H V for T.  Nothing
+// depends on data on the host, so no synchronisation is needed; the caller's
+// stream waits for the second stream before the final norm, so the call
+// keeps stream semantics.
 template <typename T>
 static hipError_t run_blocked_fixed(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats)
 {
@@ -420,15 +507,23 @@ static hipError_t run_blocked_fixed(UpdateWs<T>& w, hipStream_t st, QrcpStats* s
     const int64_t m = d.m, n = d.n, k = d.k;
     const int nb = w.nb < UNGQR_NB ? w.nb : UNGQR_NB;
     const unsigned na = (unsigned)rup(m, 256);
+    SideStream* ss = n > nb ? side_stream() : nullptr;
+    hipStream_t s2 = ss ? ss->s : st;
+    if (ss) {
+        if (hipEventRecord(ss->fork, st) != hipSuccess || hipStreamWaitEvent(s2, ss->fork, 0) != hipSuccess)
+            return hipErrorInvalidValue;
+    }
+    bool far_pending = false;   // a far update has been issued on s2 (ss->trail marks its end)
     hipLaunchKernelGGL(k_ctl_panel, dim3(1), dim3(64), 0, st, d.ctl, (int32_t)0);
-    for (int64_t p0 = 0; p0 < k; p0 += nb) {
+    hipLaunchKernelGGL(k_fixed_flags_reset, dim3(1), dim3(QR_NBMAX), 0, st, w.wflag, (int)QR_NBMAX);
+    int parity = 0;
+    for (int64_t p0 = 0; p0 < k; p0 += nb, parity ^= 1) {
         const int64_t pend = (p0 + nb < k) ? p0 + nb : k;
         const int nbe = (int)(pend - p0);
         const bool right = m - p0 <= (int64_t)WSTEP_NT * WSTEP_RPT;
         if (right) {
             hipLaunchKernelGGL(k_ctl_panel, dim3(1), dim3(64), 0, st, d.ctl, (int32_t)p0);
-            hipLaunchKernelGGL(k_fixed_partials, dim3(1), dim3(1024), 0, st, w.wcp, p0, nbe);
-            run_window_steps<T>(w, st, p0, nbe, nbe, 1);
+            run_fixed_panel<T>(w, st, p0, nbe, nbe);
             window_reorder<T>(w, st, p0, nbe, nbe);
         }
         for (int64_t jc = right ? pend : p0; jc < pend; ++jc) {
@@ -446,34 +541,37 @@ static hipError_t run_blocked_fixed(UpdateWs<T>& w, hipStream_t st, QrcpStats* s
         if (stats) stats->panels++;
         if (pend >= n) continue;
         const T* V = d.A + p0 + d.lda * p0;
-        const int64_t rows = m - p0, cols = n - pend;
-        T* At = d.A + p0 + d.lda * pend;
-        const double rc = (double)rows * (double)cols;
+        const int64_t rows = m - p0;
+        T* Tm = parity ? w.Tbuf2 : w.Tbuf;
         hipEvent_t eg = prof_begin(st);
-        // G = V^H V: the window steps have formed its upper triangle
-        if (!right && !zgemm<T>(st, OP_C, true, OP_N, true, nbe, nbe, rows, C_ONE, V, d.lda, V, d.lda, C_ZERO,
-                                w.Gbuf, UNGQR_NB, w.gsplit, w.gsplit_bytes))
+        // G = V^H V, then T
+        if (!zgemm<T>(st, OP_C, true, OP_N, true, nbe, nbe, rows, C_ONE, V, d.lda, V, d.lda, C_ZERO, w.Gbuf,
+                      UNGQR_NB, w.gsplit2, w.gsplit2_bytes))
             return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_larft<T>), dim3(1), dim3(256), 0, st, w.Gbuf, d.tau + p0, nbe, w.Tbuf);
-        prof_end(eg, st, PK_REFL, right ? 0.0 : (double)sizeof(T) * rows * nbe,
-                 right ? 0.0 : 8.0 * (double)nbe * nbe * rows);
-        hipEvent_t et = prof_begin(st);
-        if (!zgemm<T>(st, OP_C, true, OP_N, false, nbe, cols, rows, C_ONE, V, d.lda, At, d.lda, C_ZERO, w.Wbuf,
-                      UNGQR_NB, w.gsplit, w.gsplit_bytes))
+        hipLaunchKernelGGL((k_larft<T>), dim3(1), dim3(256), 0, st, w.Gbuf, d.tau + p0, nbe, Tm);
+        prof_end(eg, st, PK_REFL, (double)sizeof(T) * rows * nbe, 8.0 * (double)nbe * nbe * rows);
+        // the next panel's columns [pend, pend + nb) on st, after the far
+        // update of the previous panel (which covered them)
+        const int64_t near_end = pend + nb < n ? pend + nb : n;
+        const int64_t far_cols = n - near_end;
+        if (far_pending && hipStreamWaitEvent(st, ss->trail, 0) != hipSuccess) return hipErrorInvalidValue;
+        if (far_cols > 0 && ss && hipEventRecord(ss->panel, st) != hipSuccess) return hipErrorInvalidValue;
+        if (!panel_update<T>(st, V, d.lda, Tm, nbe, rows, near_end - pend, d.A + p0 + d.lda * pend, w.Wsm, w.W2sm,
+                             UNGQR_NB, w.gsplit2, w.gsplit2_bytes))
             return hipErrorInvalidValue;
-        prof_end(et, st, PK_PANEL, (double)sizeof(T) * rc, 8.0 * nbe * rc);
-        hipEvent_t e2 = prof_begin(st);
-        if (!zgemm<T>(st, OP_C, false, OP_N, false, nbe, cols, nbe, C_ONE, w.Tbuf, UNGQR_NB, w.Wbuf, UNGQR_NB,
-                      C_ZERO, w.W2buf, UNGQR_NB, nullptr, 0))
-            return hipErrorInvalidValue;
-        prof_end(e2, st, PK_REFL, (double)sizeof(T) * 2.0 * nbe * cols, 8.0 * (double)nbe * nbe * cols);
-        hipEvent_t eu = prof_begin(st);
-        if (!zrank_update<T>(st, true, rows, cols, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, At, d.lda) &&
-            !zgemm<T>(st, OP_N, true, OP_N, false, rows, cols, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, C_ONE,
-                      At, d.lda, nullptr, 0))
-            return hipErrorInvalidValue;
-        prof_end(eu, st, PK_TRAIL, 2.0 * (double)sizeof(T) * rc, 8.0 * nbe * rc);
+        if (far_cols > 0) {
+            // the rest of the trailing block beside the next panel
+            if (ss && hipStreamWaitEvent(s2, ss->panel, 0) != hipSuccess) return hipErrorInvalidValue;
+            if (!panel_update<T>(s2, V, d.lda, Tm, nbe, rows, far_cols, d.A + p0 + d.lda * near_end, w.Wbuf,
+                                 w.W2buf, UNGQR_NB, w.gsplit, w.gsplit_bytes))
+                return hipErrorInvalidValue;
+            if (ss) {
+                if (hipEventRecord(ss->trail, s2) != hipSuccess) return hipErrorInvalidValue;
+                far_pending = true;
+            }
+        }
     }
+    if (far_pending && hipStreamWaitEvent(st, ss->trail, 0) != hipSuccess) return hipErrorInvalidValue;
     // a10: ||R22||_F^2 over the final trailing block
     if (m > k && n > k) {
         const unsigned nblk = (unsigned)rup(n - k, QR_CW);
@@ -530,9 +628,6 @@ struct CtlMailbox {
     std::mutex mu;
 };
 static CtlMailbox g_ctl_mbox;
-// Set for the duration of a call that must not allocate: the readback then
-// uses the mailbox only if an earlier call has already allocated it.
-static thread_local bool g_no_alloc = false;
 
 __global__ __launch_bounds__(64) void k_ctl_export(const int32_t* ctl, int32_t* hbuf, int32_t seq)
 {
@@ -605,7 +700,7 @@ static void window_setup(UpdateWs<T>& w, hipStream_t st, int64_t p0, bool save)
 // Right-looking pivot steps p0 .. p0+nsteps-1 inside the window (k_window_step),
 // then the window's columns in their final order: pivots first, in step order.
 template <typename T>
-static void run_window_steps(UpdateWs<T>& w, hipStream_t st, int64_t p0, int64_t nsteps, int W, int fixed)
+static void run_window_steps(UpdateWs<T>& w, hipStream_t st, int64_t p0, int64_t nsteps, int W)
 {
     QrcpDev<T>& d = w.d;
     // sampled profiling times the whole run with one event pair
@@ -621,13 +716,13 @@ static void run_window_steps(UpdateWs<T>& w, hipStream_t st, int64_t p0, int64_t
         ArgBest* cout = w.wcp + ((jj + 1) & 1) * QR_WIN_MAX;
         if (rows0 <= 64 * 8)
             hipLaunchKernelGGL((k_window_step<T, 64, 8>), dim3((unsigned)W), dim3(64), 0, st, d, j, p0, (int)jj, cin,
-                               cout, w.wpiv, w.vbuf, w.wstep, w.Gbuf, (int)UNGQR_NB, fixed);
+                               cout, w.wpiv, w.vbuf, w.wstep, w.Gbuf, (int)UNGQR_NB);
         else if (rows0 <= 256 * 8)
             hipLaunchKernelGGL((k_window_step<T, 256, 8>), dim3((unsigned)W), dim3(256), 0, st, d, j, p0, (int)jj,
-                               cin, cout, w.wpiv, w.vbuf, w.wstep, w.Gbuf, (int)UNGQR_NB, fixed);
+                               cin, cout, w.wpiv, w.vbuf, w.wstep, w.Gbuf, (int)UNGQR_NB);
         else
             hipLaunchKernelGGL((k_window_step<T>), dim3((unsigned)W), dim3(WSTEP_NT), 0, st, d, j, p0, (int)jj, cin,
-                               cout, w.wpiv, w.vbuf, w.wstep, w.Gbuf, (int)UNGQR_NB, fixed);
+                               cout, w.wpiv, w.vbuf, w.wstep, w.Gbuf, (int)UNGQR_NB);
         // algorithmic traffic of one step: the window right of the pivot read and written once
         const double cols = (double)(p0 + W - j - 1), rows = (double)(d.m - j);
         prof_end(ec, st, PK_STEP_C, 2.0 * sizeof(T) * rows * cols, 16.0 * rows * cols);
@@ -635,6 +730,36 @@ static void run_window_steps(UpdateWs<T>& w, hipStream_t st, int64_t p0, int64_t
         rflops += 16.0 * rows * cols;
     }
     prof_end(er, st, PK_STEP_C, rbytes, rflops, nsteps);
+}
+
+// Unpivoted steps p0 .. p0+nsteps-1 of a window of W columns in column
+// order: one k_fixed_panel launch (the block shape follows the rows left, as
+// in run_window_steps).  The flags must have been reset for this
+// factorisation (k_fixed_flags_reset); the epoch p0 + 1 is then new to them.
+template <typename T>
+static void run_fixed_panel(UpdateWs<T>& w, hipStream_t st, int64_t p0, int64_t nsteps, int W)
+{
+    QrcpDev<T>& d = w.d;
+    const int64_t rows0 = d.m - p0;
+    const int32_t epoch = (int32_t)(p0 + 1);
+    hipEvent_t ec = prof_begin(st, PK_STEP_C);
+    if (rows0 <= 64 * 8)
+        hipLaunchKernelGGL((k_fixed_panel<T, 64, 8>), dim3((unsigned)W), dim3(64), 0, st, d, p0, (int)nsteps, epoch,
+                           w.wflag, w.wscale, w.wpiv, w.vbuf);
+    else if (rows0 <= 256 * 8)
+        hipLaunchKernelGGL((k_fixed_panel<T, 256, 8>), dim3((unsigned)W), dim3(256), 0, st, d, p0, (int)nsteps, epoch,
+                           w.wflag, w.wscale, w.wpiv, w.vbuf);
+    else
+        hipLaunchKernelGGL((k_fixed_panel<T, WSTEP_NT, WSTEP_RPT>), dim3((unsigned)W), dim3(WSTEP_NT), 0, st, d, p0,
+                           (int)nsteps, epoch, w.wflag, w.wscale, w.wpiv, w.vbuf);
+    // algorithmic traffic: every column of the window read and written once,
+    // each reflector's rows read once per column right of it
+    double by = 2.0 * sizeof(T) * (double)rows0 * W, fl = 0.0;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        by += sizeof(T) * (double)(rows0 - s) * (double)(W - s - 1);
+        fl += 16.0 * (double)(rows0 - s) * (double)(W - s - 1);
+    }
+    prof_end(ec, st, PK_STEP_C, by, fl);
 }
 
 template <typename T>
@@ -653,23 +778,23 @@ static void window_reorder(UpdateWs<T>& w, hipStream_t st, int64_t p0, int nbe, 
 }
 
 // Unpivoted Householder QR with every column in one window (n <= WSTEP_NT,
-// m <= WSTEP_NT * WSTEP_RPT): per panel of nb columns, one k_window_step
-// launch per column in position order (each step applies its reflector to
-// every remaining column, so no trailing update is left), then the panel's
-// reflectors are written into place.  Half the launches of the delayed-update
-// steps, for the centre moves of bonds up to a few hundred.
+// m <= WSTEP_NT * WSTEP_RPT): per panel of nb columns, one k_fixed_panel
+// launch over every remaining column (each reflector reaches every column
+// right of it, so no trailing update is left), then the panel's reflectors
+// are written into place.  For the centre moves of bonds up to a few
+// hundred.
 template <typename T>
 static hipError_t run_window_fixed(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats)
 {
     QrcpDev<T>& d = w.d;
     const int64_t n = d.n, k = d.k;
     const int nb = w.nb > 0 && w.nb < QR_NBMAX ? w.nb : 32;
+    hipLaunchKernelGGL(k_fixed_flags_reset, dim3(1), dim3(QR_NBMAX), 0, st, w.wflag, (int)QR_NBMAX);
     for (int64_t p0 = 0; p0 < k; p0 += nb) {
         const int64_t nsteps = (p0 + nb < k ? p0 + nb : k) - p0;
         const int W = (int)(n - p0);
         hipLaunchKernelGGL(k_ctl_panel, dim3(1), dim3(64), 0, st, d.ctl, (int32_t)p0);
-        hipLaunchKernelGGL(k_fixed_partials, dim3(1), dim3(1024), 0, st, w.wcp, p0, W);
-        run_window_steps<T>(w, st, p0, nsteps, W, 1);
+        run_fixed_panel<T>(w, st, p0, nsteps, W);
         window_reorder<T>(w, st, p0, (int)nsteps, W);
         if (stats) stats->panels++;
     }

@@ -560,10 +560,6 @@ __device__ __forceinline__ void block_sum_ws4(double& a, double& b, double& c, d
     e = se;
 }
 
-// fixed != 0: unpivoted QR in column order (a centre move, or a known column
-// order).  The partials then carry W - b instead of the norm, so the live
-// column of smallest position wins every argmax (seeded by k_fixed_partials),
-// and no norm is formed.
 // The new residual norm of a live column comes from the same reduction round
 // as the reflector: with c = conj(tau) (v^H a) scale, the rows below the
 // pivot become a_i - c x_i, so
@@ -577,8 +573,7 @@ __device__ __forceinline__ void block_sum_ws4(double& a, double& b, double& c, d
 // the large factorisations, smaller blocks when few rows remain.
 template <typename T, int NT = WSTEP_NT, int RPT = WSTEP_RPT>
 __global__ __launch_bounds__(NT) void k_window_step(QrcpDev<T> d, int64_t j, int64_t p0, int jj, const ArgBest* cin,
-                                                      ArgBest* cout, int32_t* wpiv, T* vbuf, int32_t* wstep, T* gbuf, int ldg,
-                                                      int fixed)
+                                                      ArgBest* cout, int32_t* wpiv, T* vbuf, int32_t* wstep, T* gbuf, int ldg)
 {
     constexpr int NW = NT / 64;
     __shared__ double s_red[4 * NW];
@@ -643,7 +638,7 @@ __global__ __launch_bounds__(NT) void k_window_step(QrcpDev<T> d, int64_t j, int
     }
     // one reduction round for ||x_rest||^2, g = sum_{i>j} conj(x_i) a_i and
     // ||a_rest||^2; then v^H a = a_j + conj(scale) g with v = (1, scale * x_rest)
-    const bool want_norm = !fixed && gi < 0;
+    const bool want_norm = gi < 0;
     double rest = 0.0, gre = 0.0, gim = 0.0, sa = 0.0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
@@ -714,7 +709,7 @@ __global__ __launch_bounds__(NT) void k_window_step(QrcpDev<T> d, int64_t j, int
     const bool recompute = want_norm && !(nn > 1e-6 * sa);   // uniform: from block-wide sums
     if (tid == 0 && !recompute) {
         ArgBest mine;
-        mine.val = fixed ? (double)(W - b) : (nn > 0.0 ? nn : 0.0);
+        mine.val = nn > 0.0 ? nn : 0.0;
         mine.key = key_c;
         mine.slot = (int32_t)c;
         cout[b] = mine;
@@ -745,6 +740,202 @@ __global__ __launch_bounds__(NT) void k_window_step(QrcpDev<T> d, int64_t j, int
     }
 }
 
+// ---------------------------------------------------------------------------
+// Unpivoted panel in column order as one launch (a centre move, or QR with a
+// known column order).  Block b owns column p0 + b of the window [p0, p0 + W)
+// and keeps its rows p0.. in registers for the whole panel.  Step s belongs
+// to block s (s < nsteps): it waits for steps 0 .. s-1, applies each
+// reflector to its column as it arrives, forms its own Householder reflector
+// (xLARFG convention, FP64), stores the column (R rows above the diagonal,
+// the reflected rows from the diagonal on: the x that later blocks read),
+// beta and v into vbuf[:, s], tau, R_ss and the FP64 scale of v, and then
+// publishes flags[s] = epoch.  Blocks from nsteps on apply all nsteps
+// reflectors and store their column.  Each reflector reaches a column with
+// the arithmetic of a right-looking step: w = a_j + conj(scale) x^H a over
+// the rows below j, a -= conj(tau) w v with v = (1, scale x).
+//
+// Block b only ever waits for blocks below b.  Workgroups are dispatched in
+// index order, so the lowest unfinished block always runs and the panel
+// makes progress whatever the number of resident blocks.  Each wait is
+// bounded all the same: a wait that runs out (which correct operation never
+// reaches) poisons the block's column and the factorisation's epsilon with
+// NaN instead of hanging, so the caller's finiteness checks report it.
+// Publication: every thread of the pivot block fences its stores at agent
+// scope (the L2s of the chip's dies are not coherent with one another),
+// then one thread stores the flag with release semantics; a waiting block's
+// thread 0 reads the flag and fences with acquire semantics before the
+// block barrier that releases its other threads to read the column.
+// flags[] must hold values other than epoch when the panel starts.
+// ---------------------------------------------------------------------------
+#define FIXED_WAIT_LIMIT (1 << 20)   // polls of one flag (about a second): far beyond any panel
+
+template <int NW>
+__device__ __forceinline__ void block_sum_ws2(double& a, double& b, double* lds /* 2 * NW */)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    __syncthreads();
+    if (lane == 0) {
+        lds[wid] = a;
+        lds[NW + wid] = b;
+    }
+    __syncthreads();
+    double sa = 0.0, sb = 0.0;
+    for (int w = 0; w < NW; ++w) {
+        sa += lds[w];
+        sb += lds[NW + w];
+    }
+    a = sa;
+    b = sb;
+}
+
+// A double2 written by another block of the running kernel: two relaxed
+// agent-scope atomic loads, so the compiler cannot serve it from the scalar
+// cache (which the acquire fence does not make coherent).
+__device__ __forceinline__ double2 ld_published(const double2* p)
+{
+    const double* q = (const double*)p;
+    return make_double2(__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                        __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+template <typename T, int NT, int RPT>
+__global__ __launch_bounds__(NT) void k_fixed_panel(QrcpDev<T> d, int64_t p0, int nsteps, int32_t epoch,
+                                                     int32_t* flags, double2* vscale, int32_t* wpiv, T* vbuf)
+{
+    constexpr int NW = NT / 64;
+    __shared__ double s_red[2 * NW];
+    __shared__ double2 s_aj;
+    __shared__ int s_fail;
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x;
+    const int64_t c = p0 + b;
+    const int m = (int)d.m, r0 = (int)p0;   // rows fit 32 bits here
+    const T zero = from_d<T>(czero());
+    T* colc = d.A + d.lda * c;
+    T a[RPT];   // rows r0 + tid + NT q; zeros past the matrix
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int i = r0 + tid + NT * q;
+        const T v = colc[i < m ? i : m - 1];
+        a[q] = i < m ? v : zero;
+    }
+    if (tid == 0) s_fail = 0;
+    __syncthreads();
+    const int nref = b < nsteps ? b : nsteps;
+    for (int s = 0; s < nref; ++s) {
+        const int js = r0 + s;
+        if (tid == 0) {
+            int it = 0;
+            while (__hip_atomic_load(flags + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+                if (++it >= FIXED_WAIT_LIMIT) {
+                    s_fail = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+        if (s_fail) break;   // uniform: read after the barrier
+        // x: the rows of column p0 + s below js (zeros elsewhere)
+        const T* xs = d.A + d.lda * (p0 + s);
+        T x[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int i = r0 + tid + NT * q;
+            const T v = xs[i < m ? i : m - 1];
+            x[q] = (i > js && i < m) ? v : zero;
+        }
+        const double2 sc = ld_published(vscale + s);
+        const double2 tau = ld_published(d.tau + js);
+        if (tid == s) s_aj = to_d(a[0]);   // row js of this column
+        double gre = 0.0, gim = 0.0;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const double2 g = cmulc(to_d(x[q]), to_d(a[q]));
+            gre += g.x;
+            gim += g.y;
+        }
+        block_sum_ws2<NW>(gre, gim, s_red);   // its barriers also publish s_aj
+        const double2 wv = cadd(s_aj, cmul(cconj(sc), make_double2(gre, gim)));
+        const double2 coef = cmul(cconj(tau), wv);
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            double2 vi = cmul(sc, to_d(x[q]));
+            if (q == 0 && tid == s) vi = make_double2(1.0, 0.0);
+            a[q] = from_d<T>(csub(to_d(a[q]), cmul(coef, vi)));
+        }
+        __syncthreads();   // s_aj is rewritten by the next step
+    }
+    if (s_fail) {
+        const T bad = from_d<T>(make_double2(__builtin_nan(""), 0.0));
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) a[q] = bad;
+        if (tid == 0) d.dsc[DSC_EPS2] = __builtin_nan("");
+    }
+    if (b >= nsteps) {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int i = r0 + tid + NT * q;
+            if (i < m) colc[i] = a[q];
+        }
+        return;
+    }
+    // this block's own step: reflector of rows jb.. of its column
+    const int jb = r0 + b;
+    if (tid == b) s_aj = to_d(a[0]);
+    double rest = 0.0, dummy = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        double2 ai = to_d(a[q]);
+        if (q == 0 && tid <= b) ai = czero();
+        rest += cabs2(ai);
+    }
+    block_sum_ws2<NW>(rest, dummy, s_red);
+    const double2 alpha = s_aj;
+    double2 tau, scale;
+    double beta;
+    if (rest == 0.0 && alpha.y == 0.0) {
+        tau = czero();
+        scale = czero();
+        beta = alpha.x;
+    } else {
+        const double nrm = sqrt(cabs2(alpha) + rest);
+        beta = alpha.x >= 0.0 ? -nrm : nrm;
+        tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+        scale = cdiv(make_double2(1.0, 0.0), make_double2(alpha.x - beta, alpha.y));
+    }
+    T* vb = vbuf + d.lda * b;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int i = r0 + tid + NT * q;
+        if (i < m) {
+            colc[i] = a[q];
+            if (i == jb) vb[i] = from_d<T>(make_double2(beta, 0.0));
+            else if (i > jb) vb[i] = from_d<T>(cmul(scale, to_d(a[q])));
+        }
+    }
+    if (tid == 0) {
+        d.tau[jb] = tau;
+        d.diagR[jb] = beta;
+        vscale[b] = scale;
+        wpiv[b] = (int32_t)c;
+        if (b == nsteps - 1) d.ctl[CTL_JDONE] = r0 + nsteps;
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(flags + b, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// flags of k_fixed_panel set to a value no panel uses (epochs are p0 + 1 >= 1)
+__global__ void k_fixed_flags_reset(int32_t* flags, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flags[i] = 0;
+}
+
 // First partials of a pivoted panel whose window is every remaining column
 // (one per column, from the current norms).  One block of W <= 1024 threads.
 template <typename T>
@@ -755,20 +946,6 @@ __global__ __launch_bounds__(1024) void k_nu_partials(QrcpDev<T> d, ArgBest* cp,
         ArgBest a;
         a.val = d.nu[p0 + b];
         a.key = d.perm[p0 + b];
-        a.slot = (int32_t)(p0 + b);
-        cp[b] = a;
-    }
-}
-
-// First partials of an unpivoted window panel: column p0 + b gets priority
-// W - b.  One block of W <= 1024 threads.
-__global__ __launch_bounds__(1024) void k_fixed_partials(ArgBest* cp, int64_t p0, int W)
-{
-    const int b = threadIdx.x;
-    if (b < W) {
-        ArgBest a;
-        a.val = (double)(W - b);
-        a.key = b;
         a.slot = (int32_t)(p0 + b);
         cp[b] = a;
     }
