@@ -42,11 +42,38 @@ __device__ __forceinline__ double2 czero() { return make_double2(0.0, 0.0); }
 
 // ---- reductions ----
 
+// DPP row shift: lane l of each row of 16 lanes receives lane l - N of the
+// same row; lanes without such a source receive `own` instead.  (Cross-lane
+// data moves inside the VALU: no LDS round trip as with a shuffle.)
+template <int N>
+__device__ __forceinline__ int dpp_row_shr(int v, int own)
+{
+    return __builtin_amdgcn_update_dpp(own, v, 0x110 + N, 0xf, 0xf, false);
+}
+template <int N>
+__device__ __forceinline__ double dpp_row_shr(double v, double own)
+{
+    const int lo = dpp_row_shr<N>(__double2loint(v), __double2loint(own));
+    const int hi = dpp_row_shr<N>(__double2hiint(v), __double2hiint(own));
+    return __hiloint2double(hi, lo);
+}
+// The value lane L holds (L a constant), in every lane.
+__device__ __forceinline__ double lane_value(double v, int L)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), L),
+                            __builtin_amdgcn_readlane(__double2loint(v), L));
+}
+
+// Wavefront sum, every lane receiving it: a scan inside each row of 16 lanes
+// (row shifts 1, 2, 4, 8) leaves the row sums in lanes 15, 31, 47 and 63,
+// which are then added in row order.  Called by all 64 lanes.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, MPS_WAVE);
-    return v;
+    v += dpp_row_shr<1>(v, 0.0);
+    v += dpp_row_shr<2>(v, 0.0);
+    v += dpp_row_shr<4>(v, 0.0);
+    v += dpp_row_shr<8>(v, 0.0);
+    return ((lane_value(v, 15) + lane_value(v, 31)) + lane_value(v, 47)) + lane_value(v, 63);
 }
 
 __device__ __forceinline__ double2 wave_sum(double2 v)
@@ -195,18 +222,45 @@ __device__ __forceinline__ bool arg_better_exact(double v1, int32_t k1, double v
     return v1 > v2 || (v1 == v2 && k1 < k2);
 }
 
+template <bool EXACT, int N>
+__device__ __forceinline__ void argmax_row_step(ArgBest& a)
+{
+    const double v = dpp_row_shr<N>(a.val, a.val);
+    const int32_t k = dpp_row_shr<N>(a.key, a.key);
+    const int32_t s = dpp_row_shr<N>(a.slot, a.slot);
+    const bool better = EXACT ? arg_better_exact(v, k, a.val, a.key) : arg_better(v, k, a.val, a.key);
+    if (better) { a.val = v; a.key = k; a.slot = s; }
+}
+
+template <bool EXACT>
+__device__ __forceinline__ void argmax_take_lane(ArgBest& b, const ArgBest& a, int L)
+{
+    const double v = lane_value(a.val, L);
+    const int32_t k = __builtin_amdgcn_readlane(a.key, L);
+    const int32_t s = __builtin_amdgcn_readlane(a.slot, L);
+    const bool better = EXACT ? arg_better_exact(v, k, b.val, b.key) : arg_better(v, k, b.val, b.key);
+    if (better) { b.val = v; b.key = k; b.slot = s; }
+}
+
+// Wavefront argmax, every lane receiving it: a max-scan inside each row of
+// 16 lanes, then the four row winners (lanes 15, 31, 47, 63).  The order is
+// total (keys are distinct), so the winner does not depend on the grouping.
+// Called by all 64 lanes.
 template <bool EXACT = false>
 __device__ __forceinline__ ArgBest wave_argmax(ArgBest a)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        double v = __shfl_xor(a.val, off, MPS_WAVE);
-        int32_t k = __shfl_xor(a.key, off, MPS_WAVE);
-        int32_t s = __shfl_xor(a.slot, off, MPS_WAVE);
-        const bool better = EXACT ? arg_better_exact(v, k, a.val, a.key) : arg_better(v, k, a.val, a.key);
-        if (better) { a.val = v; a.key = k; a.slot = s; }
-    }
-    return a;
+    argmax_row_step<EXACT, 1>(a);
+    argmax_row_step<EXACT, 2>(a);
+    argmax_row_step<EXACT, 4>(a);
+    argmax_row_step<EXACT, 8>(a);
+    ArgBest b;
+    b.val = lane_value(a.val, 15);
+    b.key = __builtin_amdgcn_readlane(a.key, 15);
+    b.slot = __builtin_amdgcn_readlane(a.slot, 15);
+    argmax_take_lane<EXACT>(b, a, 31);
+    argmax_take_lane<EXACT>(b, a, 47);
+    argmax_take_lane<EXACT>(b, a, 63);
+    return b;
 }
 
 // Block (256 threads) argmax; result valid in every thread.  EXACT: on the
