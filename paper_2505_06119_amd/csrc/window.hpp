@@ -748,11 +748,12 @@ __global__ __launch_bounds__(NT) void k_window_step(QrcpDev<T> d, int64_t j, int
 // reflector to its column as it arrives, forms its own Householder reflector
 // (xLARFG convention, FP64), stores the column (R rows above the diagonal,
 // the reflected rows from the diagonal on: the x that later blocks read),
-// beta and v into vbuf[:, s], tau, R_ss and the FP64 scale of v, and then
-// publishes flags[s] = epoch.  Blocks from nsteps on apply all nsteps
-// reflectors and store their column.  Each reflector reaches a column with
-// the arithmetic of a right-looking step: w = a_j + conj(scale) x^H a over
-// the rows below j, a -= conj(tau) w v with v = (1, scale x).
+// tau, R_ss and the FP64 scale of v, publishes flags[s] = epoch, and only
+// then writes beta and v into vbuf[:, s] (read after the launch).  Blocks
+// from nsteps on apply all nsteps reflectors and store their column.  Each
+// reflector reaches a column with the arithmetic of a right-looking step:
+// w = a_j + conj(scale) x^H a over the rows below j, a -= conj(tau) w v with
+// v = (1, scale x).
 //
 // Block b only ever waits for blocks below b.  Workgroups are dispatched in
 // index order, so the lowest unfinished block always runs and the panel
@@ -907,15 +908,12 @@ __global__ __launch_bounds__(NT) void k_fixed_panel(QrcpDev<T> d, int64_t p0, in
         tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
         scale = cdiv(make_double2(1.0, 0.0), make_double2(alpha.x - beta, alpha.y));
     }
-    T* vb = vbuf + d.lda * b;
+    // what the later blocks read first (the column, its scalars), then the
+    // flag; beta and v are read only after the launch
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const int i = r0 + tid + NT * q;
-        if (i < m) {
-            colc[i] = a[q];
-            if (i == jb) vb[i] = from_d<T>(make_double2(beta, 0.0));
-            else if (i > jb) vb[i] = from_d<T>(cmul(scale, to_d(a[q])));
-        }
+        if (i < m) colc[i] = a[q];
     }
     if (tid == 0) {
         d.tau[jb] = tau;
@@ -927,6 +925,13 @@ __global__ __launch_bounds__(NT) void k_fixed_panel(QrcpDev<T> d, int64_t p0, in
     __threadfence();
     __syncthreads();
     if (tid == 0) __hip_atomic_store(flags + b, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    T* vb = vbuf + d.lda * b;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int i = r0 + tid + NT * q;
+        if (i == jb) vb[i] = from_d<T>(make_double2(beta, 0.0));
+        else if (i > jb && i < m) vb[i] = from_d<T>(cmul(scale, to_d(a[q])));
+    }
 }
 
 // flags of k_fixed_panel set to a value no panel uses (epochs are p0 + 1 >= 1)
