@@ -26,6 +26,9 @@ Pieces and the passages they follow (arXiv 2505.06119):
   orthogonality centre) and Sec. III-C.2 application of two-site gates; the
   state is kept unnormalised so that ``norm_fidelity`` is the paper's
   norm fidelity <Psi_T|Psi_T> (Sec. III-E) by its definition.
+* ``MPS.apply_mpo``     -- Sec. III-C.3 MPO application by zip-up, each
+  site's contraction truncated by pivoted QR (Table III); ``mpo_operator``
+  and ``apply_mpo_dense`` give the dense operator for pins.
 * ``amplitude``         -- Eq. (2): product of the site matrices selected by
   the bits.
 * ``overlap``           -- Sec. III-E overlap fidelity, by transfer matrices.
@@ -293,6 +296,47 @@ class MPS:
             for i, g in layer:
                 self.apply_gate(i, g)
 
+    def apply_mpo(self, first: int, ws, chi_cap: int | None = None) -> dict:
+        """Zip-up application of an MPO (Sec. III-C.3) with site tensors
+        ws[t][a, s', s, b] on sites first .. first + len(ws) - 1.
+
+        With the centre at ``first``, a matrix C[l', (a, l)] is carried right:
+        T[l', s', r, b] = sum C[l', a, l] A[l, s, r] W[a, s', s, b]; T as a
+        (2 chi') x (m_b chi_r) matrix (row 2 l' + s', column b chi_r + r) is
+        truncated by pivoted QR; Q is the new site and R P^T the next C.  At
+        the last site T is the new site and the centre.  Nothing is
+        renormalised, so the state's norm afterwards carries the truncation
+        (the norm fidelity of a unitary MPO applied to a normalised state)."""
+        self.move_centre(first)
+        cap = self.chi_cap if chi_cap is None else int(chi_cap)
+        c = None
+        steps = []
+        for t, w in enumerate(ws):
+            i = first + t
+            a = self.sites[i]
+            chi_l, _, chi_r = a.shape
+            w = np.asarray(w, dtype=np.complex128)
+            ma, mb = w.shape[0], w.shape[3]
+            if c is None:
+                x = a[None]                                                   # [a, l', s, r], C = 1
+            else:
+                x = np.einsum("pal,lsr->apsr", c.reshape(c.shape[0], ma, chi_l), a)
+            tt = np.einsum("apsr,atsb->ptrb", x, w)                           # [l', s', r, b]
+            chip = tt.shape[0]
+            if t == len(ws) - 1:
+                self.sites[i] = np.ascontiguousarray(tt[:, :, :, 0])
+                self.centre = i
+                break
+            m = tt.transpose(0, 1, 3, 2).reshape(2 * chip, mb * chi_r)
+            f = qrcp(m, min(cap, 2 * chip, mb * chi_r), pivoting=True)
+            k = f["k"]
+            self.sites[i] = f["Q"].reshape(chip, 2, k)
+            c = r_unpivot(f["R"], f["piv"])                                   # k x (m_b chi_r), columns (b, r)
+            steps.append({"i": i, "k": k, "err": f["err"], "norm2": float(np.vdot(m, m).real)})
+        rec = {"first": first, "steps": steps}
+        self.history.append(rec)
+        return rec
+
     def bond_dims(self):
         return [s.shape[2] for s in self.sites[:-1]]
 
@@ -350,6 +394,26 @@ def brute_force_ops(n: int, ops) -> np.ndarray:
             g4 = np.asarray(u, dtype=np.complex128).reshape(2, 2, 2, 2)
             psi = np.moveaxis(np.tensordot(g4, psi, axes=([2, 3], [a, b])), [0, 1], [a, b])
     return psi.reshape(-1)
+
+
+def mpo_operator(ws) -> np.ndarray:
+    """The dense operator of an MPO on L sites: O[(s'_0..s'_{L-1}), (s_0..s_{L-1})]
+    = sum over the bonds of prod_t W_t[a_t, s'_t, s_t, a_{t+1}] (site 0 the
+    most significant bit), 2^L x 2^L."""
+    o = np.ones((1, 1, 1), dtype=np.complex128)                 # [out, in, bond]
+    for w in ws:
+        w = np.asarray(w, dtype=np.complex128)
+        t = np.einsum("xya,atsb->xtysb", o, w)                   # [out, s', in, s, b]
+        o = t.reshape(o.shape[0] * 2, o.shape[1] * 2, w.shape[3])
+    return o[:, :, 0]
+
+
+def apply_mpo_dense(psi: np.ndarray, n: int, first: int, ws) -> np.ndarray:
+    """The MPO applied to a dense statevector on qubits first .. first+L-1."""
+    L = len(ws)
+    op = mpo_operator(ws).reshape((2,) * (2 * L))
+    t = np.tensordot(op, psi.reshape((2,) * n), axes=(list(range(L, 2 * L)), list(range(first, first + L))))
+    return np.moveaxis(t, list(range(L)), list(range(first, first + L))).reshape(-1)
 
 
 def brute_force(n: int, layers, bits=None) -> np.ndarray:

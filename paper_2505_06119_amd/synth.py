@@ -283,6 +283,46 @@ def qft_circuit(n: int, inverse: bool = False):
     return [[g] for g in gates]
 
 
+def iqft_mpo_ops(n: int):
+    """The inverse of the textbook QFT (without its final bit reversal) as n
+    MPOs of bond 2 (Sec. III-D.1): for qubit j = n-1 down to 0, the
+    controlled phases diag(1, exp(-2 pi i / 2^(t-j+1))) between j and every
+    t > j, then H on j, as one MPO on sites j .. n-1 -- [H Pi_0, H Pi_1] on
+    site j, diag(I, P_t) on the sites between, [I; P_t] on the last (Pi_s the
+    projector on |s>).  Returns [(first, [W_t[a, s', s, b], ...]), ...] in
+    application order."""
+    h = gate_h()
+    eye = np.eye(2, dtype=np.complex128)
+    ops = []
+    for j in range(n - 1, -1, -1):
+        if j == n - 1:
+            ops.append((j, [h.reshape(1, 2, 2, 1)]))
+            continue
+        w0 = np.zeros((1, 2, 2, 2), dtype=np.complex128)
+        for s in range(2):
+            w0[0, :, s, s] = h[:, s]
+        ws = [w0]
+        for t in range(j + 1, n):
+            p = np.diag([1.0, np.exp(-2j * np.pi / 2 ** (t - j + 1))]).astype(np.complex128)
+            w = np.zeros((2, 2, 2, 2 if t < n - 1 else 1), dtype=np.complex128)
+            w[0, :, :, 0] = eye
+            w[1, :, :, w.shape[3] - 1] = p
+            ws.append(w)
+        ops.append((j, ws))
+    return ops
+
+
+def saturated_sites(r: np.random.Generator, n: int, chi: int, sigma: float) -> list:
+    """Random input of the inverse QFT at saturation sigma (Sec. III-D.1):
+    site tensors whose first chi_i x chi_i block, chi_i = sigma chi capped by
+    the structural bound min(2^b, 2^(n-b)) of each bond, is filled with
+    complex Gaussian entries for each physical index (the rest of a chi x chi
+    site would be zero, so only the block is stored)."""
+    ci = max(1, int(round(sigma * chi)))
+    dims = [1] + [min(ci, 2 ** min(b, n - b)) for b in range(1, n)] + [1]
+    return [cgauss(r, (dims[j], 2, dims[j + 1])) for j in range(n)]
+
+
 def grid_couplers(rows: int, cols: int, pattern: str):
     """Coupler pairs (qubit labels y*cols + x) of one entangling pattern on a
     rectangular grid: A/B horizontal pairs starting at even/odd x, C/D vertical
