@@ -312,6 +312,37 @@ mps_status mps_apply_gate(mps_ctx* ctx, int32_t i, const double* g, mps_update_i
 mps_status mps_apply_layer(mps_ctx* ctx, int64_t n, const int32_t* i, const double* g,
                            mps_update_info* info);
 
+/* Apply a matrix product operator (Sec. III-C.3, MPO application: long-range
+ * operators of small bond m, contracted with the state by the zip-up
+ * algorithm) to the sites first .. first + n_sites - 1.  mdims (host, n_sites
+ * + 1 int32): the MPO bonds, mdims[0] = mdims[n_sites] = 1 and 1 <= mdims[t]
+ * <= 2 (the bond of the inverse QFT's MPOs; it is what the context's bond
+ * storage leaves room for during a sweep).  W (host, FP64 complex as (re, im) pairs): the site tensors in order,
+ * site t holding 4 mdims[t] mdims[t+1] entries W_t[a, s', s, b] at index
+ * a + mdims[t] (s' + 2 (s + 2 b)) (s the input, s' the output physical
+ * index; e.g. the controlled-phase MPO of the inverse QFT, Sec. III-D.1, has
+ * m = 2).  The centre moves to `first`; a carried matrix is swept from left
+ * to right, each site's contraction truncated by pivoted QR to the bond cap
+ * (Table III), leaving left-canonical sites and the centre on the last site.
+ * The squared norm of the result there is the norm fidelity factor of the
+ * application (Sec. III-E; exact for a unitary MPO such as the inverse QFT's):
+ * its log goes to *log_retained (host, may be NULL) and into the log norm
+ * fidelity, and the state is normalised.  MPS_EINVAL: sites out of range, bad mdims or NULL
+ * arrays (no state change); MPS_ENUMERIC: non-finite entry (refused before
+ * any change) or non-finite intermediate (the context is then poisoned). */
+mps_status mps_apply_mpo(mps_ctx* ctx, int32_t first, int32_t n_sites, const int32_t* mdims, const double* W,
+                         double* log_retained);
+
+/* Replace the state: dims (host, n_sites + 1 int64, dims[0] = dims[n] = 1,
+ * each within the context's bond cap) and data (host, FP64 complex pairs):
+ * the sites in order, site j holding dims[j] x 2 x dims[j+1] entries at
+ * l + dims[j] (s + 2 r).  The state is brought to right-canonical form by
+ * LQ moves (Sec. III-C.1) with the centre on site 0, normalised, and the
+ * norm fidelity restarts at 1 (the random-saturation input of the inverse
+ * QFT experiment, Sec. III-D.1, is loaded this way).  MPS_EINVAL: bad dims
+ * or NULL arrays; MPS_ENUMERIC: non-finite or zero state. */
+mps_status mps_load_state(mps_ctx* ctx, const int64_t* dims, const double* data);
+
 /* <x|Psi_T> for the bit string x (host, n_sites bytes of 0/1; site 0 first),
  * where Psi_T is the stored normalised state times sqrt(norm fidelity), i.e.
  * the paper's unnormalised truncated state.  out: host, 2 doubles. */

@@ -297,6 +297,9 @@ extern "C" mps_status qrcp_truncate_noalloc(int64_t m, int64_t n, int64_t k_max,
 // stateful MPS context
 #include "context.hpp"
 
+// MPO application by zip-up, state loading
+#include "mpo.hpp"
+
 // autotuner of the pivoted-QR tiles
 #include "autotune.hpp"
 

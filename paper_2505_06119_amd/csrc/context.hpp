@@ -77,10 +77,15 @@ struct mps_ctx {
     int32_t trunc;         // mps_truncation of the two-site updates
 };
 
+// Storage bound of bond b (between sites b-1 and b): the cap chi, the
+// Schmidt bound 2^b of the b sites on its left, and twice the Schmidt bound
+// 2^(n-b) of the sites on its right.  The factor 2 is the room an MPO of bond
+// 2 needs while a left-to-right zip-up sweep crosses the bond: the matrix
+// truncated there still carries the MPO bond on its right (see mpo.hpp).
 static int64_t max_bond(int n, int b, int64_t chi)
 {
     int64_t d = chi;
-    const int e1 = b, e2 = n - b;
+    const int e1 = b, e2 = n - b + 1;
     if (e1 < 62 && ((int64_t)1 << e1) < d) d = (int64_t)1 << e1;
     if (e2 < 62 && ((int64_t)1 << e2) < d) d = (int64_t)1 << e2;
     return d;

@@ -159,6 +159,10 @@ def lib() -> ctypes.CDLL:
     L.mps_centre.argtypes = [p, ctypes.POINTER(ctypes.c_int32)]
     L.mps_get_site.restype = i32
     L.mps_get_site.argtypes = [p, i32, p, i64]
+    L.mps_apply_mpo.restype = i32
+    L.mps_apply_mpo.argtypes = [p, i32, i32, ctypes.POINTER(ctypes.c_int32), pd, pd]
+    L.mps_load_state.restype = i32
+    L.mps_load_state.argtypes = [p, pi64, pd]
     _lib = L
     return L
 
@@ -516,6 +520,37 @@ class MPS:
         for layer in layers:
             out += self.apply_layer(sorted(layer, key=lambda ig: ig[0]))
         return out
+
+    def apply_mpo(self, first: int, ws) -> float:
+        """MPO on sites first .. first + len(ws) - 1 (mps_apply_mpo): ws[t] is
+        W_t[a, s', s, b] with shape (m_t, 2, 2, m_{t+1}), m_0 = m_len = 1.
+        Returns the log of the norm fidelity this application retained."""
+        ws = [np.asarray(w, dtype=np.complex128) for w in ws]
+        md = [ws[0].shape[0]] + [w.shape[3] for w in ws]
+        for t, w in enumerate(ws):
+            if w.ndim != 4 or w.shape[1:3] != (2, 2) or w.shape[0] != md[t]:
+                raise ValueError(f"MPO site {t} has shape {w.shape}")
+        # a + m_t (s' + 2 (s + 2 b)): a fastest, i.e. Fortran order of [a, s', s, b]
+        flat = np.concatenate([w.reshape(-1, order="F") for w in ws])
+        buf = np.ascontiguousarray(flat.view(np.float64))
+        mdims = (ctypes.c_int32 * len(md))(*md)
+        out = ctypes.c_double(0)
+        _check(lib().mps_apply_mpo(self._h, int(first), len(ws), mdims,
+                                   buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(out)))
+        return float(out.value)
+
+    def load_state(self, sites):
+        """Replace the state by the sites [l, s, r] (mps_load_state): right-
+        canonical, centre 0, normalised, norm fidelity 1."""
+        sites = [np.asarray(a, dtype=np.complex128) for a in sites]
+        if len(sites) != self.n:
+            raise ValueError("one site per qubit")
+        dims = [sites[0].shape[0]] + [a.shape[2] for a in sites]
+        # entry (l, s, r) at l + chi_l (s + 2 r): Fortran order of [l, s, r]
+        flat = np.concatenate([a.reshape(-1, order="F") for a in sites])
+        buf = np.ascontiguousarray(flat.view(np.float64))
+        d = (ctypes.c_int64 * len(dims))(*dims)
+        _check(lib().mps_load_state(self._h, d, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
     def amplitude(self, bits) -> complex:
         b = (ctypes.c_uint8 * self.n)(*[int(x) for x in bits])
