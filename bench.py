@@ -33,9 +33,10 @@ sample of the headline update for cpu_baseline.
 
 Further legs (each can be skipped): the headline on more seeds, the chi=1024
 microbenchmark over 100 seeds, centre moves at chi=4096, small-bond circuit
-layers, QR against SVD truncation, routed grid circuits, and time-bounded
-slices of the 5x8 grid circuit at chi cap 4096 and the 6x9 grid circuit at
-chi cap 8192 (one mps_apply_layer per layer).
+layers, QR against SVD truncation, routed grid circuits, the random-saturation
+inverse QFT by MPO zip-up (and against SWAP routing), and time-bounded slices
+of the 5x8 grid circuit at chi cap 4096 and the 6x9 grid circuit at chi cap
+8192 (one mps_apply_layer per layer).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--chi 4096]
 """
@@ -591,6 +592,65 @@ def routed_grid(M, torch, synth):
     return out
 
 
+def iqft_saturation(M, torch, synth, n=32, chi=256, sigmas=(0.125, 0.25, 0.5, 1.0), swap_n=20, swap_chi=128):
+    """The random-saturation inverse QFT (Sec. III-D.1 input, Sec. IV
+    output-fidelity experiment): n qubits whose input sites are Gaussian
+    blocks of bond sigma chi (synth.saturated_sites), the inverse QFT applied
+    as n bond-2 MPOs by zip-up (mps_apply_mpo) at chi cap chi, mixed
+    precision; wall time and norm fidelity per sigma.  Beside it, at
+    (swap_n, swap_chi, sigma = 0.25), the same transform by SWAP routing of
+    its two-qubit gates (synth.qft_circuit without the bit reversal), the
+    alternative the paper contrasts with MPOs."""
+    out = {"workload": f"{n} qubits, random input of saturation sigma (bond sigma*chi), inverse QFT as {n} "
+                       f"controlled-phase MPOs of bond 2 by zip-up, chi cap {chi}, mixed", "runs": []}
+    for sg in sigmas:
+        sites = synth.saturated_sites(synth.rng(700), n, chi, sg)
+        st = M.MPS(n, chi, M.MPS_MIXED)
+        st.load_state(sites)
+        ops = synth.iqft_mpo_ops(n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for first, ws in ops:
+            st.apply_mpo(first, ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rec = {"sigma": sg, "seconds": dt, "mpos": len(ops), "site_steps": sum(len(w) for _, w in ops),
+               "norm_fidelity": float(np.exp(st.log_norm_fidelity())), "max_bond": max(st.bond_dims())}
+        st.close()
+        out["runs"].append(rec)
+        log(f"[bench] iqft n={n} chi={chi} sigma={sg}: {dt:.2f} s, Fbar {rec['norm_fidelity']:.6f}")
+    # MPO route against SWAP routing on one smaller case
+    sg = 0.25
+    sites = synth.saturated_sites(synth.rng(701), swap_n, swap_chi, sg)
+    cmp = {"workload": f"{swap_n} qubits, sigma {sg}, chi cap {swap_chi}, mixed, inverse QFT without the bit "
+                       f"reversal"}
+    st = M.MPS(swap_n, swap_chi, M.MPS_MIXED)
+    st.load_state(sites)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for first, ws in synth.iqft_mpo_ops(swap_n):
+        st.apply_mpo(first, ws)
+    torch.cuda.synchronize()
+    cmp["mpo"] = {"seconds": time.perf_counter() - t0, "norm_fidelity": float(np.exp(st.log_norm_fidelity()))}
+    st.close()
+    layers = synth.qft_circuit(swap_n, inverse=True, bit_reversal=False)
+    st = M.MPS(swap_n, swap_chi, M.MPS_MIXED)
+    st.load_state(sites)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.apply_layers(layers)
+    torch.cuda.synchronize()
+    cmp["swap"] = {"seconds": time.perf_counter() - t0, "gates": len(layers),
+                   "norm_fidelity": float(np.exp(st.log_norm_fidelity()))}
+    st.close()
+    cmp["swap_over_mpo_time"] = cmp["swap"]["seconds"] / cmp["mpo"]["seconds"]
+    out["mpo_vs_swap"] = cmp
+    log(f"[bench] iqft n={swap_n} chi={swap_chi}: MPO {cmp['mpo']['seconds']:.2f} s (Fbar "
+        f"{cmp['mpo']['norm_fidelity']:.6f}), SWAP {cmp['swap']['seconds']:.2f} s (Fbar "
+        f"{cmp['swap']['norm_fidelity']:.6f})")
+    return out
+
+
 def leftover_children():
     """Child processes of this one still alive (e.g. a build step): ended and
     waited for, so nothing outlives the benchmark."""
@@ -820,6 +880,8 @@ def main():
         res["truncation_compare"] = truncation_compare(M, torch, synth)
         log("[bench] grid random circuit with and without same-bond fusion")
         res["routed_grid"] = routed_grid(M, torch, synth)
+        log("[bench] random-saturation inverse QFT by MPO zip-up")
+        res["iqft_saturation"] = iqft_saturation(M, torch, synth)
     if not args.no_configs:
         log("[bench] autotuning the pivoted-QR tiles per bond bucket (mixed, chi up to 4096)")
         t0 = time.perf_counter()

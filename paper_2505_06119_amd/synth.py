@@ -254,14 +254,16 @@ def one_qubit_as_two_site(n: int, q: int, g1: np.ndarray):
     return (q - 1, kron1(g1, False))
 
 
-def qft_circuit(n: int, inverse: bool = False):
+def qft_circuit(n: int, inverse: bool = False, bit_reversal: bool = True):
     """Quantum Fourier transform on a 1D chain with SWAP routing.
 
     Textbook circuit (H on qubit j, controlled R_{t-j+1} from every later
     qubit t, final bit reversal), with R_k = diag(1, exp(2 pi i / 2^k)) as in
     Appendix A.  A controlled phase between non-neighbours is applied by
     swapping qubit t next to j and back.  The inverse uses the adjoint gates in
-    reverse order.  Returns a flat list of layers with one gate each."""
+    reverse order; bit_reversal=False leaves out the final reversal (the
+    inverse then matches the MPO form of iqft_mpo_ops).  Returns a flat list
+    of layers with one gate each."""
     gates = []
     for j in range(n):
         gates.append(one_qubit_as_two_site(n, j, gate_h()))
@@ -272,7 +274,7 @@ def qft_circuit(n: int, inverse: bool = False):
             gates.append((j, gate_cphase(phi)))
             for s in range(j + 1, t):              # and back
                 gates.append((s, gate_swap()))
-    for i in range(n // 2):                          # bit reversal
+    for i in range(n // 2 if bit_reversal else 0):   # bit reversal
         a, b = i, n - 1 - i
         for s in range(a, b):
             gates.append((s, gate_swap()))
