@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -116,6 +117,9 @@ static int64_t update_ws_bytes(int64_t m, int64_t n, int64_t k)
 
 // two-site update, learned proposal entry points
 #include "bond.hpp"
+
+// truncated-SVD updates beyond the small-bond chains
+#include "svd.hpp"
 
 // ---------------------------------------------------------------------------
 // qrcp_truncate

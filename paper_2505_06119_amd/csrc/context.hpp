@@ -408,13 +408,6 @@ static mps_status ctx_run_gates(mps_ctx* c, int64_t ng, const int32_t* idx, cons
         centre = i + 1;
     }
     if ((int64_t)ops.size() > c->chain_cap) return fail(MPS_EINVAL, "gates: too many chained operations");
-    if (c->trunc == MPS_TRUNC_SVD)
-        for (const Step& st : steps)
-            if (st.kind == CH_UPDATE && !st.fused)
-                return fail(MPS_EINVAL,
-                            "gates: SVD truncation runs only inside small-bond chains (gate %d on bond %d exceeds "
-                            "bond dimension %lld)",
-                            st.t, st.s, (long long)half);
     if (!ops.empty())
         HIPCHK(hipMemcpyAsync(c->chain_ops, ops.data(), sizeof(ChainOp) * ops.size(), hipMemcpyHostToDevice, c->st),
                "chain upload");
@@ -466,9 +459,14 @@ static mps_status ctx_run_gates(mps_ctx* c, int64_t ng, const int32_t* idx, cons
             mps_update_info loc;
             const int i = st.s;
             const mps_learned_cfg* lc = c->cfg.pivot == MPS_PIVOT_LEARNED ? &c->lcfg : nullptr;
-            r = update_core<T>(c->dims[i], c->dims[i + 1], c->dims[i + 2], c->chi_max, c->prec,
-                               (const T*)c->site[i], (const T*)c->site[i + 1], g + 32 * st.t, (T*)c->site[i],
-                               (T*)c->site[i + 1], 1, lc, &loc, c->ws, c->ws_bytes, c->st);
+            if (c->trunc == MPS_TRUNC_SVD)
+                r = svd_update<T>(c->dims[i], c->dims[i + 1], c->dims[i + 2], c->chi_max, (const T*)c->site[i],
+                                  (const T*)c->site[i + 1], g + 32 * st.t, (T*)c->site[i], (T*)c->site[i + 1], &loc,
+                                  c->ws, c->ws_bytes, c->st);
+            else
+                r = update_core<T>(c->dims[i], c->dims[i + 1], c->dims[i + 2], c->chi_max, c->prec,
+                                   (const T*)c->site[i], (const T*)c->site[i + 1], g + 32 * st.t, (T*)c->site[i],
+                                   (T*)c->site[i + 1], 1, lc, &loc, c->ws, c->ws_bytes, c->st);
             if (r == MPS_OK) {
                 c->dims[i + 1] = loc.k;
                 c->centre = i + 1;

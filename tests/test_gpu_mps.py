@@ -38,11 +38,11 @@ def test_brickwork_exact_vs_statevector(M, prec):
     ref = oracle.brute_force(n, layers)
     tol = TOL[prec]
     sv = _gpu_statevector(st)
-    assert np.max(np.abs(sv - ref)) <= tol * np.max(np.abs(ref)) * 10
+    assert np.max(np.abs(sv - ref)) <= tol * np.max(np.abs(ref))
     assert abs(st.log_norm_fidelity()) <= tol
     for x in synth.rng(101).integers(0, 2 ** n, size=12):
         amp = st.amplitude(_bits(int(x), n))
-        assert abs(amp - ref[int(x)]) <= tol * np.max(np.abs(ref)) * 10
+        assert abs(amp - ref[int(x)]) <= tol * np.max(np.abs(ref))
 
 
 @pytest.mark.parametrize("prec", [0, 1])

@@ -1,6 +1,7 @@
 """GPU parity of the SVD truncation (mps_set_truncation, MPS_TRUNC_SVD): the
-Jacobi SVD updates of the small-bond chains against brute-force
-statevectors and the oracle's SVD MPS, update by update."""
+Jacobi SVD updates of the small-bond chains and of the multi-kernel path
+(larger bonds, or chains off) against brute-force statevectors and the
+oracle's SVD MPS, update by update."""
 import numpy as np
 import pytest
 
@@ -91,23 +92,71 @@ def test_svd_first_truncation_no_worse_than_qr(M):
     assert ia[t]["trunc_err_sq"] > 0.0
 
 
-def test_svd_outside_chains_rejected(M):
-    """With chains off every update would take the multi-kernel path, which has
-    no SVD: EINVAL before anything changes."""
-    print("case svd rejected", flush=True)
+def test_svd_outside_chains_runs(M):
+    """With chains off every update takes the multi-kernel SVD: same result as
+    the chained one."""
+    print("case svd multi-kernel single gate", flush=True)
+    g = synth.haar_unitary(synth.rng(9), 4)
+    ref = _svd_state(M, 6, 8, 0)
+    ref.apply_gate(2, g)
     st = _svd_state(M, 6, 8, 0)
     M.set_small_bond_limit(0)
     try:
-        with pytest.raises(M.MpsError) as e:
-            st.apply_gate(2, synth.haar_unitary(synth.rng(9), 4))
-        assert e.value.status == 1
-        assert st.bond_dims() == [1] * 7
-        assert st.centre() == 0
-        assert st.log_norm_fidelity() == 0.0
+        info = st.apply_gate(2, g)
     finally:
         M.set_small_bond_limit(64)
-    st.apply_gate(2, synth.haar_unitary(synth.rng(9), 4))
-    assert st.bond_dims()[3] == 2
+    assert info["k"] == 2 and info["qrcp_err_sq"] == -1.0
+    assert st.bond_dims() == ref.bond_dims()
+    a, b = _sv(st), _sv(ref)
+    assert np.max(np.abs(a - b)) <= TOL[0] * np.max(np.abs(b))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_svd_multikernel_truncated_vs_oracle(M, prec):
+    """The chi cap 16 circuit with chains off: every update is a multi-kernel
+    Jacobi SVD; ranks, retained norms, F-bar and the state against the oracle."""
+    print(f"case svd multi-kernel truncated prec={prec}", flush=True)
+    n = 12
+    layers = synth.brickwork(synth.rng(311), n, 10)
+    st = _svd_state(M, n, 16, prec)
+    M.set_small_bond_limit(0)
+    try:
+        infos = st.apply_layers(layers)
+    finally:
+        M.set_small_bond_limit(64)
+    om = oracle.MPS(synth.product_state_sites(n), chi_cap=16, truncation="svd")
+    om.apply_layers(layers)
+    tol = TOL[prec]
+    for gi, rec in zip(infos, om.history):
+        assert gi["k"] == rec["k"]
+        assert abs(gi["retained"] - (1.0 - rec["err"] ** 2 / rec["norm2"])) <= tol
+    fbar_o = oracle.norm_fidelity(om.sites)
+    assert abs(np.exp(st.log_norm_fidelity()) - fbar_o) <= tol * fbar_o
+    assert st.bond_dims() == [1] + om.bond_dims() + [1]
+    assert 1 - _fid(oracle.statevector(om.sites), _sv(st)) <= tol
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_svd_bonds_above_the_chains_vs_oracle(M, prec):
+    """14 qubits, brickwork depth 12, chi cap 96: the middle bonds pass 64, so
+    their updates run as multi-kernel SVDs between chained runs."""
+    print(f"case svd large bonds prec={prec}", flush=True)
+    n, cap = 14, 96
+    layers = synth.brickwork(synth.rng(312), n, 12)
+    st = _svd_state(M, n, cap, prec)
+    infos = st.apply_layers(layers)
+    om = oracle.MPS(synth.product_state_sites(n), chi_cap=cap, truncation="svd")
+    om.apply_layers(layers)
+    assert max(om.bond_dims()) > 64
+    tol = TOL[prec]
+    for gi, rec in zip(infos, om.history):
+        assert gi["k"] == rec["k"]
+        assert abs(gi["retained"] - (1.0 - rec["err"] ** 2 / rec["norm2"])) <= tol
+    fbar_o = oracle.norm_fidelity(om.sites)
+    assert fbar_o < 0.9999
+    assert abs(np.exp(st.log_norm_fidelity()) - fbar_o) <= tol * fbar_o
+    assert st.bond_dims() == [1] + om.bond_dims() + [1]
+    assert 1 - _fid(oracle.statevector(om.sites), _sv(st)) <= tol
 
 
 def test_set_truncation_validation(M):
