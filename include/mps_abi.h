@@ -433,10 +433,11 @@ mps_status mps_set_small_bond_limit(int32_t max_dim);
  *                  row of theta^H's Jacobi order), site i <- U_k,
  *                  site i+1 <- S_k V_k^dagger; eps^2 = the sum of the
  *                  discarded squared singular values.  Computed by one-sided
- *                  Jacobi in FP64 inside the small-bond chains only: a call
- *                  with an update whose bond dimensions exceed the chain
- *                  limit (mps_set_small_bond_limit) returns MPS_EINVAL before
- *                  anything changes.  Needs pivot = MPS_PIVOT_QRCP.
+ *                  Jacobi in FP64: inside a small-bond chain when the bonds
+ *                  are within the chain limit (mps_set_small_bond_limit),
+ *                  otherwise by the multi-kernel Jacobi (a launch per round
+ *                  of column pairs, a host check per sweep; meant for bonds
+ *                  up to a few hundred).  Needs pivot = MPS_PIVOT_QRCP.
  * The renormalisation, norm-fidelity bookkeeping and update info are those
  * of the QR updates (qrcp_err_sq reads -1 for an SVD update).  Returns
  * MPS_EINVAL for a NULL context, an unknown mode or SVD with learned pivots.
