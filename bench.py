@@ -685,6 +685,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-layers", action="store_true", help="skip the small-bond circuit measurements")
+    ap.add_argument("--moves", action="store_true", help="time the centre moves even with --no-configs")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the chi=1024 microbenchmark, the centre moves and the grid-circuit slices")
     ap.add_argument("--cfg2-seeds", type=int, default=100)
@@ -854,7 +855,7 @@ def main():
             res[f"path_{k}"]["deviation_vs_fp64"] = devs[k]
     if "fp64" in rates:
         res["speedup_vs_fp64_qrcp"] = rates[head] / rates["fp64"]
-    if not args.no_configs:
+    if not args.no_configs or args.moves:
         log("[bench] centre moves at the headline size")
         res["centre_moves"] = centre_moves(M, torch, a, b, chi)
     if "fp64" in runs and args.seeds > 1:
