@@ -407,7 +407,7 @@ def grid_rcs_logical(r: np.random.Generator, rows: int, cols: int, cycles: int, 
     return ops
 
 
-def qpe_circuit(t: int, alphas, target_init: str = "plus"):
+def qpe_circuit(t: int, alphas, target_init: str = "plus", reversed_powers: bool = False):
     """Quantum phase estimation on a chain: t counting qubits (positions
     0..t-1, position 0 the most significant) and one target qubit per angle
     in ``alphas`` (positions t..), for U = tensor_q diag(1, exp(i alpha_q)).
@@ -415,7 +415,10 @@ def qpe_circuit(t: int, alphas, target_init: str = "plus"):
     Targets start in |+> (target_init="plus") or |1> ("one", an eigenstate
     with eigenphase sum(alphas)); counting qubit j controls U^(2^(t-1-j)) as
     controlled phases routed by SWAPs; the inverse QFT of Appendix A (with the
-    adjoint phase gates) finishes.  Returns a flat list of one-gate layers."""
+    adjoint phase gates) finishes.  reversed_powers: counting qubit j controls
+    U^(2^j) instead, the order for which the inverse QFT without its final bit
+    reversal (iqft_mpo_ops) reads the phase in natural order.  Returns a flat
+    list of one-gate layers."""
     s = len(alphas)
     n = t + s
     gates = []
@@ -426,7 +429,7 @@ def qpe_circuit(t: int, alphas, target_init: str = "plus"):
         g1 = gate_h() if target_init == "plus" else xg
         gates.append(one_qubit_as_two_site(n, t + q, g1))
     for j in range(t):
-        power = 2 ** (t - 1 - j)
+        power = 2 ** j if reversed_powers else 2 ** (t - 1 - j)
         for q in range(s):
             tpos = t + q
             for p in range(tpos - 1, j, -1):

@@ -178,3 +178,37 @@ def test_qpe_gpu_exact_phase():
     st.apply_layers(layers)
     bits = [(mm >> (t - 1 - j)) & 1 for j in range(t)] + [1]
     assert abs(abs(st.amplitude(bits)) - 1.0) < 1e-4
+
+
+def _qpe_prefix(t, alphas, target_init):
+    """Phase estimation up to its inverse QFT (the gates before it), with the
+    controlled powers in the order the MPO inverse QFT (no final bit
+    reversal) reads in natural order."""
+    layers = synth.qpe_circuit(t, alphas, target_init=target_init, reversed_powers=True)
+    return layers[:len(layers) - len(synth.qft_circuit(t, inverse=True))]
+
+
+def test_qpe_with_mpo_iqft_oracle():
+    """Phase estimation with the inverse QFT as bond-2 MPOs (Sec. III-D.1),
+    on the oracle MPS: the counting register reads the exact phase m / 2^t."""
+    t, mm = 5, 19
+    n = t + 1
+    om = oracle.MPS(synth.product_state_sites(n), chi_cap=32)
+    om.apply_layers(_qpe_prefix(t, [2 * np.pi * mm / 2 ** t], "one"))
+    for first, ws in synth.iqft_mpo_ops(t):
+        om.apply_mpo(first, ws)
+    bits = [(mm >> (t - 1 - j)) & 1 for j in range(t)] + [1]
+    assert abs(abs(oracle.amplitude(om.sites, bits)) - 1.0) < 1e-12
+
+
+@pytest.mark.gpu
+def test_qpe_gpu_with_mpo_iqft():
+    from paper_2505_06119_amd import mps
+    print("case qpe mpo", flush=True)
+    t, mm = 6, 45
+    st = mps.MPS(t + 1, 32, mps.MPS_MIXED)
+    st.apply_layers(_qpe_prefix(t, [2 * np.pi * mm / 2 ** t], "one"))
+    for first, ws in synth.iqft_mpo_ops(t):
+        st.apply_mpo(first, ws)
+    bits = [(mm >> (t - 1 - j)) & 1 for j in range(t)] + [1]
+    assert abs(abs(st.amplitude(bits)) - 1.0) < 1e-4
