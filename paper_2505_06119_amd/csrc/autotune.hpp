@@ -77,16 +77,25 @@ static mps_status tune_bucket(int32_t chi, mps_precision prec, char* work, int64
         g_qr_window = g_tune_cands[q][1];
         float ms = 0.0f, tot = 0.0f;
         for (int rep = 0; rep < 3 && s == MPS_OK; ++rep) {   // one warm-up, two timed
-            hipEventRecord(e0, st);
+            if (hipEventRecord(e0, st) != hipSuccess) {
+                s = fail(MPS_EDEVICE, "autotune: event record failed");
+                break;
+            }
             s = update_core<T>(c, c, c, c, prec, A, B, gate, Ao, Bo, 1, nullptr, nullptr, work + ows,
                                work_bytes - ows, st);
-            hipEventRecord(e1, st);
             if (s != MPS_OK) break;
+            if (hipEventRecord(e1, st) != hipSuccess) {
+                s = fail(MPS_EDEVICE, "autotune: event record failed");
+                break;
+            }
             if (hipEventSynchronize(e1) != hipSuccess) {
                 s = fail(MPS_EDEVICE, "autotune: event synchronisation failed");
                 break;
             }
-            hipEventElapsedTime(&ms, e0, e1);
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                s = fail(MPS_EDEVICE, "autotune: event timing failed");
+                break;
+            }
             if (rep > 0) tot += ms;
         }
         const double t = tot / 2.0;
@@ -99,8 +108,8 @@ static mps_status tune_bucket(int32_t chi, mps_precision prec, char* work, int64
     }
     g_panel_width = save_nb;
     g_qr_window = save_win;
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (s != MPS_OK) return s;
     e->n_max = 0;
     e->panel_width = best_nb;
