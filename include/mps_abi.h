@@ -376,6 +376,22 @@ mps_status mps_get_site(mps_ctx* ctx, int32_t j, void* dst, int64_t dst_bytes);
 mps_status mps_set_tuning(int32_t panel_width, int32_t qr_window);
 
 /* ------------------------------------------------------------------------
+ * How the pivoted window panels take their pivot steps, process-wide (not
+ * thread-safe; affects later calls).  mode 0 (default): one launch per pivot
+ * step (the right-looking window kernel).  mode 1: the pivots of a panel
+ * from pivoted Cholesky of the window's Gram matrix A_w^H A_w (greedy
+ * pivoting picks the column of largest residual norm, and those norms and
+ * the R rows are fixed by the inner products: Table III's QR with pivoting),
+ * then CholeskyQR2 of the chosen columns and a Householder reconstruction
+ * with the xLARFG sign convention, so R, the reflectors and tau are those of
+ * the Householder QR of the chosen columns.  Used for windows of at most 256
+ * columns and panels of at most 32 steps while the rows fit one window-step
+ * block; a replay miss or a failed Cholesky sends the panel back to mode 0.
+ * Returns MPS_EINVAL for other modes.
+ * ------------------------------------------------------------------------ */
+mps_status mps_set_panel_mode(int32_t mode);
+
+/* ------------------------------------------------------------------------
  * Autotuner of the pivoted-QR tiles, process-wide (not thread-safe; affects
  * later calls).  A circuit layer holds two-site updates of very different
  * bond dimensions (Sec. III-D: bonds grow from 2 up to the cap); the panel

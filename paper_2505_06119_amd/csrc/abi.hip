@@ -88,6 +88,13 @@ static int qr_window(int nb, int64_t n)
     return w >= nb && w <= QR_WIN_MAX ? w : 0;
 }
 
+extern "C" mps_status mps_set_panel_mode(int32_t mode)
+{
+    if (mode != 0 && mode != 1) return fail(MPS_EINVAL, "mps_set_panel_mode: mode %d not 0 or 1", (int)mode);
+    g_panel_mode = mode;
+    return MPS_OK;
+}
+
 extern "C" mps_status mps_set_tuning(int32_t panel_width_, int32_t qr_window_)
 {
     if (panel_width_ != 0 && panel_width_ != 16 && panel_width_ != 32 && panel_width_ != 64)

@@ -21,6 +21,7 @@
 #include "prof.hpp"
 #include "qrcp.hpp"
 #include "window.hpp"
+#include "gram.hpp"
 #include <stdarg.h>
 #include <stdio.h>
 
@@ -326,6 +327,9 @@ struct UpdateWs {
     double* wtnu;            // QR_WIN_MAX
     double* wtnuref;         // QR_WIN_MAX
     int32_t* wtperm;         // QR_WIN_MAX
+    T* gw;                   // GRAM_W_MAX^2: the Gram matrix of a window (Gram panels)
+    double2* gq;             // GRAM_NB_MAX columns of lda: Q of the panel's pivots in FP64 (Gram panels)
+    double2* gsm;            // GSM_COUNT: the panel's small FP64 factors (Gram panels)
 };
 
 static inline int64_t rup(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -393,12 +397,16 @@ static bool carve_update_ws(Carver& cv, UpdateWs<T>& w, int64_t m, int64_t n, in
     w.wtnu = (double*)cv.take(8 * QR_WIN_MAX);
     w.wtnuref = (double*)cv.take(8 * QR_WIN_MAX);
     w.wtperm = (int32_t*)cv.take(4 * QR_WIN_MAX);
+    w.gw = (T*)cv.take((int64_t)sizeof(T) * GRAM_W_MAX * GRAM_W_MAX);
+    w.gq = (double2*)cv.take((int64_t)16 * d.lda * GRAM_NB_MAX);
+    w.gsm = (double2*)cv.take((int64_t)16 * GSM_COUNT);
     w.win = 0;
     return d.nu && d.nuref && d.perm && d.F && d.tau && d.diagR && d.xbuf && d.xlo && d.apart && d.hh && d.fsave &&
            d.cpart && d.npart && d.cflag && d.ctl && d.dsc && w.Gbuf && w.Tbuf && w.Tbuf2 && w.Wsm && w.W2sm &&
            w.gsplit2 && w.Gall && w.Tall && w.Wbuf && w.W2buf && w.gsplit &&
            d.pivval && d.pivkey && w.wplan && w.wsave && w.wsnu && w.wsnuref && w.wsperm && w.wcp &&
            w.wpiv && w.wstep && w.worder && w.wtmp && w.vbuf && w.wflag && w.wscale && w.wtnu && w.wtnuref && w.wtperm &&
+           w.gw && w.gq && w.gsm &&
            (!theta_in_ws || d.A);
 }
 
@@ -420,6 +428,11 @@ template <typename T> static void run_fixed_panel(UpdateWs<T>& w, hipStream_t st
 // readback then uses its pinned mailbox only if an earlier call has already
 // allocated it, and the unpivoted QR keeps to the caller's stream.
 static thread_local bool g_no_alloc = false;
+
+// How the pivoted window panels take their steps (mps_set_panel_mode):
+// 0 one launch per pivot step, 1 pivots from the window's Gram matrix.
+// Process-wide.
+static int g_panel_mode = 0;
 
 // A second stream per device and host thread (default priority, created on
 // first use and kept for the life of the thread) with three events, for the
@@ -801,32 +814,97 @@ static hipError_t run_window_fixed(UpdateWs<T>& w, hipStream_t st, QrcpStats* st
     return hipGetLastError();
 }
 
+// The window's columns and their norms and keys back from the state saved at
+// the panel's set-up.
+template <typename T>
+static void window_restore(UpdateWs<T>& w, hipStream_t st, int64_t p0, int W)
+{
+    QrcpDev<T>& d = w.d;
+    dim3 grid((unsigned)(rup(d.m, 256) < 64 ? rup(d.m, 256) : 64), (unsigned)W);
+    hipLaunchKernelGGL((k_copy_cols<T>), grid, dim3(256), 0, st, (const T*)w.wsave, d.lda, d.A + d.lda * p0, d.lda,
+                       d.m);
+    hipLaunchKernelGGL((k_window_meta<T>), dim3((unsigned)rup(W, 256)), dim3(256), 0, st, d, p0, W, w.wsnu,
+                       w.wsnuref, w.wsperm, 1);
+}
+
+// Up to nsteps pivot steps of the window at p0 from its Gram matrix
+// (gram.hpp): exact norms and G, pivoted Cholesky, CholeskyQR2 of the chosen
+// columns, Householder reconstruction.  Leaves what the right-looking steps
+// leave for the window reorder (ctl JDONE, wpiv, vbuf, the R rows above the
+// diagonal in the pivot columns, tau, diagR, pivval, pivkey) and the panel's
+// T factor in w.Tbuf; the window's other columns keep their panel-start
+// values.  ctl JDONE = p0 when no step could be taken.
+template <typename T>
+static hipError_t gram_panel_steps(UpdateWs<T>& w, hipStream_t st, int64_t p0, int nsteps, int W)
+{
+    QrcpDev<T>& d = w.d;
+    const int64_t rows = d.m - p0;
+    const unsigned rb = (unsigned)rup(rows, GRAM_ROWS_NT);
+    hipEvent_t eg = prof_begin(st, PK_STEP_C);
+    hipLaunchKernelGGL((k_win_norms<T>), dim3((unsigned)W), dim3(256), 0, st, d, p0);
+    const T* Aw = d.A + p0 + d.lda * p0;
+    if (!zgemm<T>(st, OP_C, false, OP_N, false, W, W, rows, C_ONE, Aw, d.lda, Aw, d.lda, C_ZERO, w.gw,
+                  GRAM_W_MAX, w.gsplit, w.gsplit_bytes))
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_gram_pivots<T>), dim3(1), dim3(256), 0, st, d, (const T*)w.gw, (int64_t)GRAM_W_MAX, p0, W,
+                       nsteps, w.wpiv, w.gsm + GSM_R1);
+    hipLaunchKernelGGL((k_cqr_trsm<T, true>), dim3(rb), dim3(GRAM_ROWS_NT), 0, st, d, p0, (const int32_t*)w.wpiv,
+                       (const double2*)(w.gsm + GSM_R1), w.gq, d.lda);
+    if (!zgemm<double2>(st, OP_C, false, OP_N, false, nsteps, nsteps, rows, C_ONE, w.gq, d.lda, w.gq, d.lda, C_ZERO,
+                        w.gsm + GSM_G2, GRAM_NB_MAX, w.gsplit, w.gsplit_bytes))
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cqr_chol, dim3(1), dim3(1024), 0, st, d.ctl, p0, w.gsm);
+    hipLaunchKernelGGL((k_cqr_trsm<T, false>), dim3(rb), dim3(GRAM_ROWS_NT), 0, st, d, p0, (const int32_t*)nullptr,
+                       (const double2*)(w.gsm + GSM_R2), w.gq, d.lda);
+    hipLaunchKernelGGL((k_recon<T>), dim3(1), dim3(1024), 0, st, d, p0, (const double2*)w.gq, d.lda, w.gsm, w.Tbuf,
+                       (int)UNGQR_NB);
+    hipLaunchKernelGGL((k_recon_rows<T>), dim3(rb), dim3(GRAM_ROWS_NT), 0, st, d, p0, (const int32_t*)w.wpiv,
+                       (const double2*)w.gq, d.lda, (const double2*)w.gsm, w.vbuf);
+    const double wr = (double)rows * W;
+    prof_end(eg, st, PK_STEP_C, (double)sizeof(T) * (wr + 2.0 * rows * nsteps) + 16.0 * 6.0 * rows * nsteps,
+             8.0 * wr * W + 16.0 * (double)rows * nsteps * nsteps);
+    return hipGetLastError();
+}
+
 // One candidate-window panel at p0 (see window.hpp).  On return *jend is the
 // first column of the next panel and *nparts the argmax partials for its
 // first step (0 when there are none: the next panel then starts from nu).
 template <typename T>
 static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats, int64_t p0, int64_t* jend_out,
-                               int* nparts)
+                               int* nparts, bool allow_gram = true)
 {
     QrcpDev<T>& d = w.d;
     const int64_t m = d.m, n = d.n, k = d.k;
     const int W = w.win;
-    const int64_t cend = p0 + W, nout = n - cend;
+    const int64_t cend = p0 + W;
+    int64_t nout = n - cend;
     const int64_t nsteps = (p0 + w.nb < k ? p0 + w.nb : k) - p0;
     // right-looking steps keep the window current (one launch per step) while
     // the rows fit one 1024-thread block; otherwise delayed-update steps
     const bool right = m - p0 <= WSTEP_NT * WSTEP_RPT;
+    // pivots from the window's Gram matrix (gram.hpp) instead of per-step launches
+    const bool gram = allow_gram && g_panel_mode == 1 && right && W <= GRAM_W_MAX && nsteps <= GRAM_NB_MAX;
 
     hipEvent_t ew = prof_begin(st);
     window_setup<T>(w, st, p0, true);
     prof_end(ew, st, PK_WINDOW, (double)sizeof(T) * 4.0 * (double)m * W, 0.0);
     hipLaunchKernelGGL(k_ctl_panel, dim3(1), dim3(64), 0, st, d.ctl, (int32_t)p0);
-    if (right) run_window_steps<T>(w, st, p0, nsteps, W);
-    else run_panel_steps<T>(d, st, p0, nsteps, cend, true, 1);
+    if (gram) {
+        hipError_t eg = gram_panel_steps<T>(w, st, p0, (int)nsteps, W);
+        if (eg != hipSuccess) return eg;
+    } else if (right) {
+        run_window_steps<T>(w, st, p0, nsteps, W);
+    } else {
+        run_panel_steps<T>(d, st, p0, nsteps, cend, true, 1);
+    }
     int32_t hctl[CTL_COUNT];
     hipError_t e = read_ctl<T>(d, st, hctl);
     if (e != hipSuccess) return e;
     int64_t jend = hctl[CTL_JDONE];
+    if (gram && jend == p0) {   // no pivot passed the Cholesky: the per-step path takes the panel
+        window_restore<T>(w, st, p0, W);
+        return window_panel<T>(w, st, stats, p0, jend_out, nparts, false);
+    }
     if (jend <= p0 || jend > p0 + nsteps) {   // no progress: corrupt state
         qr_diag("window panel p0=%lld: %lld steps done of %lld (right-looking %d, m=%lld n=%lld k=%lld)",
                 (long long)p0, (long long)(jend - p0), (long long)nsteps, (int)right, (long long)m, (long long)n,
@@ -836,11 +914,15 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
     int nbe = (int)(jend - p0);
     bool refresh = hctl[CTL_STOP] != 0;
     if (right) window_reorder<T>(w, st, p0, nbe, W);
+    // the columns the block update and the replay cover: those outside the
+    // window, and with Gram pivots also the window's non-pivot columns
+    const int64_t c_o = gram ? jend : cend;
+    nout = n - c_o;
 
     // block reflector of the panel and the R rows of the outside columns
     const T* V = d.A + p0 + d.lda * p0;
     const int64_t rows = m - p0;
-    T* Ao = d.A + p0 + d.lda * cend;
+    T* Ao = d.A + p0 + d.lda * c_o;
     const double ro = (double)rows * (double)nout;
     hipEvent_t eg = prof_begin(st);
     // G = V^H V: the right-looking steps have formed its upper triangle (the
@@ -848,7 +930,7 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
     if (!right && !zgemm<T>(st, OP_C, true, OP_N, true, nbe, nbe, rows, C_ONE, V, d.lda, V, d.lda, C_ZERO, w.Gbuf,
                             UNGQR_NB, w.gsplit, w.gsplit_bytes))
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_larft<T>), dim3(1), dim3(256), 0, st, w.Gbuf, d.tau + p0, nbe, w.Tbuf);
+    if (!gram) hipLaunchKernelGGL((k_larft<T>), dim3(1), dim3(256), 0, st, w.Gbuf, d.tau + p0, nbe, w.Tbuf);
     prof_end(eg, st, PK_REFL, right ? 0.0 : (double)sizeof(T) * rows * nbe,
              right ? 0.0 : 8.0 * (double)nbe * nbe * rows);
     hipEvent_t et = prof_begin(st);
@@ -886,7 +968,7 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
     hipEvent_t ek = prof_begin(st);
     const unsigned nchk = (unsigned)rup(nout, 256);
     hipLaunchKernelGGL((k_window_check<T>), dim3(nchk), dim3(256), 0, st, d, (const T*)w.Wbuf, (int64_t)UNGQR_NB,
-                       cend, nout, nbe);
+                       c_o, nout, nbe);
     prof_end(ek, st, PK_WINDOW, 8.0 * (double)nbe * nout, 0.0);
     e = read_ctl<T>(d, st, hctl);
     if (e != hipSuccess) return e;
@@ -898,6 +980,13 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
                 "k=%lld)", (long long)p0, nbe, (int)hctl[CTL_TFAIL], (int)hctl[CTL_TFLAG], (long long)m,
                 (long long)n, (long long)k);
         return hipErrorUnknown;
+    }
+    if (tstar < nbe && gram) {
+        // a column outside the Gram pivots would have been chosen at step
+        // tstar: the per-step path takes the panel from its saved state
+        window_restore<T>(w, st, p0, W);
+        if (stats) stats->window_misses++;
+        return window_panel<T>(w, st, stats, p0, jend_out, nparts, false);
     }
     if (hctl[CTL_TFLAG] <= tstar) refresh = true;
     if (tstar < nbe) {
@@ -951,7 +1040,7 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
         if (stats) stats->refreshes++;
     } else {
         hipLaunchKernelGGL((k_window_commit<T>), dim3(nchk), dim3(256), 0, st, d, (const T*)w.Wbuf,
-                           (int64_t)UNGQR_NB, cend, nout, nbe);
+                           (int64_t)UNGQR_NB, c_o, nout, nbe);
         *nparts = 0;
     }
     *jend_out = jend;

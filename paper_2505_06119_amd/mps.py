@@ -125,6 +125,8 @@ def lib() -> ctypes.CDLL:
     L.mps_set_pivot_network.argtypes = [p, ctypes.POINTER(LearnedCfg)]
     L.mps_set_tuning.restype = i32
     L.mps_set_tuning.argtypes = [i32, i32]
+    L.mps_set_panel_mode.restype = i32
+    L.mps_set_panel_mode.argtypes = [i32]
     L.mps_autotune_work_bytes.restype = i64
     L.mps_autotune_work_bytes.argtypes = [i32, i32]
     L.mps_autotune.restype = i32
@@ -237,6 +239,12 @@ def set_tuning(panel_width: int = 0, qr_window: int = -1):
     """Process-wide pivoted-QR tuning (mps_set_tuning): panel width (0 = automatic)
     and candidate-window width (-1 = automatic, 0 = off)."""
     _check(lib().mps_set_tuning(panel_width, qr_window))
+
+
+def set_panel_mode(mode: int) -> None:
+    """Process-wide (mps_set_panel_mode): 0 = one launch per pivot step,
+    1 = a panel's pivots from its window's Gram matrix."""
+    _check(lib().mps_set_panel_mode(mode))
 
 
 def autotune(chi_max: int, prec: int, stream=None) -> list:
