@@ -14,15 +14,18 @@ checked against the oracle on its own input: the norm fidelity factor (the
 1e-4 bar), the pivot sequence (first step where it parts from the oracle's,
 and the oracle's margin there) and theta_T at 512 stored positions.
 
-Three paths run on the same inputs:
-  mixed    complex64 storage and MFMA, FP64 norms / reflectors / fidelity,
-           plain pivoted QR (QRCP);
-  fp64     complex128 throughout, plain QRCP (the comparison path);
-  learned  mixed precision with the trained pivot-proposal network
-           (certificate mode: a rejected proposal falls back to QRCP inside
-           the timed step).
-The headline value is the fastest mixed path whose norm fidelity stays within
-1e-4 (relative) of the oracle's.
+These paths run on the same inputs:
+  mixed       complex64 storage and MFMA, FP64 norms / reflectors / fidelity,
+              plain pivoted QR (QRCP);
+  fp64        complex128 throughout, plain QRCP (the comparison path);
+  mixed_gram  mixed QRCP whose window panels take their pivots from the
+              window's Gram matrix (panel mode 1; reported, never the
+              headline);
+  learned     mixed precision with the trained pivot-proposal network
+              (certificate mode: a rejected proposal falls back to QRCP inside
+              the timed step), and learned_trusted with every proposal kept.
+The headline value is the fastest of mixed and learned whose norm fidelity
+stays within 1e-4 (relative) of the oracle's.
 The roofline of the pivot-step kernel (k_window_step) comes from HIP events on
 the launch stream of the timed steps: one event pair around one panel's run of
 back-to-back step launches in 8 (mps_profile(8)), so the figure is the kernel's
@@ -684,6 +687,7 @@ def main():
     ap.add_argument("--zgeqp3-full", action="store_true", help="also time zgeqp3 at the headline size")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-gram", action="store_true", help="skip the Gram-matrix panel path (panel mode 1)")
     ap.add_argument("--no-layers", action="store_true", help="skip the small-bond circuit measurements")
     ap.add_argument("--moves", action="store_true", help="time the centre moves even with --no-configs")
     ap.add_argument("--no-configs", action="store_true",
@@ -752,6 +756,15 @@ def main():
     runs = {"mixed": time_path(M, L, torch, "mixed", M.MPS_MIXED, a, b, g, chi, args.steps, args.warmup)}
     if not args.no_fp64:
         runs["fp64"] = time_path(M, L, torch, "fp64", M.MPS_FP64, a, b, g, chi, args.steps, args.warmup)
+    if not args.no_gram:
+        # the same mixed QRCP with the panels' pivots from the window's Gram
+        # matrix (exact, reported beside the headline, not eligible for it)
+        M.set_panel_mode(1)
+        try:
+            runs["mixed_gram"] = time_path(M, L, torch, "mixed, Gram-matrix panels", M.MPS_MIXED, a, b, g, chi,
+                                           args.steps, 1)
+        finally:
+            M.set_panel_mode(0)
     if not args.no_learned and os.path.exists(pivnet.DEFAULT_WEIGHTS):
         params = pivnet.to_device(pivnet.load())
         lc = M.learned_cfg(params, sketch_rows=64, verify=False, seed=7)

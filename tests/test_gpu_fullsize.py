@@ -196,14 +196,16 @@ def cpu_inputs():
 
 
 @pytest.mark.timeout(900)
+@pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_fullsize_update_matches_oracle(cpu_inputs, prec):
+def test_fullsize_update_matches_oracle(cpu_inputs, prec, mode):
     """The whole chi = 4096 update that bench.py times (same construction, same
     launch configuration) against the oracle's stored result for the same input
     bytes (tests/golden/make_chi4096.py): pivots up to the first near tie,
     eps^2, ||theta||^2 and the norm-fidelity factor, and theta_T at 512 stored
     positions where the pivot sets agree.  The first step where the pivots
-    part, with its oracle margin, is printed."""
+    part, with its oracle margin, is printed.  mode: the window panels' pivot
+    steps (0 one launch per step, 1 from the window's Gram matrix)."""
     import torch
     from paper_2505_06119_amd import mps
     mk, (a, b, g) = cpu_inputs
@@ -213,12 +215,16 @@ def test_fullsize_update_matches_oracle(cpu_inputs, prec):
         b = b.astype(np.complex64).astype(np.complex128)
     if mk.input_digest(a, b, g) != gold["input_sha256"]:
         pytest.skip("this host's LAPACK built other input bytes than the stored oracle run's")
-    print(f"case full-size update vs stored oracle prec={prec}", flush=True)
+    print(f"case full-size update vs stored oracle prec={prec} panel mode {mode}", flush=True)
     A, B = mps.site_to_device(a, prec), mps.site_to_device(b, prec)
-    out = mps.mps_update_bond(A, B, g, CHI, CHI, CHI, CHI, prec, renormalize=False)
-    th = mps.mps_theta(A, B, g, CHI, CHI, CHI, prec)
-    q = mps.qrcp_truncate(th, CHI, prec)
-    torch.cuda.synchronize()
+    mps.set_panel_mode(mode)
+    try:
+        out = mps.mps_update_bond(A, B, g, CHI, CHI, CHI, CHI, prec, renormalize=False)
+        th = mps.mps_theta(A, B, g, CHI, CHI, CHI, prec)
+        q = mps.qrcp_truncate(th, CHI, prec)
+        torch.cuda.synchronize()
+    finally:
+        mps.set_panel_mode(0)
     info = out["info"]
     k = gold["k"]
     assert out["k"] == k
