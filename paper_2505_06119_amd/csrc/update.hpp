@@ -898,9 +898,19 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
         run_panel_steps<T>(d, st, p0, nsteps, cend, true, 1);
     }
     int32_t hctl[CTL_COUNT];
-    hipError_t e = read_ctl<T>(d, st, hctl);
-    if (e != hipSuccess) return e;
-    int64_t jend = hctl[CTL_JDONE];
+    hipError_t e = hipSuccess;
+    // The right-looking steps always take all nsteps steps (a 256-column
+    // window cannot run out of live columns in 32 steps, and they never set
+    // the stop flag), so the host goes on without reading the control block
+    // here; the replay's read-back below checks the step count.
+    const bool assume_full = right && !gram;
+    int64_t jend = p0 + nsteps;
+    hctl[CTL_STOP] = 0;
+    if (!assume_full) {
+        e = read_ctl<T>(d, st, hctl);
+        if (e != hipSuccess) return e;
+        jend = hctl[CTL_JDONE];
+    }
     if (gram && jend == p0) {   // no pivot passed the Cholesky: the per-step path takes the panel
         window_restore<T>(w, st, p0, W);
         return window_panel<T>(w, st, stats, p0, jend_out, nparts, false);
@@ -972,6 +982,13 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
     prof_end(ek, st, PK_WINDOW, 8.0 * (double)nbe * nout, 0.0);
     e = read_ctl<T>(d, st, hctl);
     if (e != hipSuccess) return e;
+    if (assume_full && hctl[CTL_JDONE] != jend) {
+        qr_diag("window panel p0=%lld: the right-looking steps ended at %d of %lld (m=%lld n=%lld k=%lld)",
+                (long long)p0, (int)(hctl[CTL_JDONE] - p0), (long long)nsteps, (long long)m, (long long)n,
+                (long long)k);
+        return hipErrorUnknown;
+    }
+    if (assume_full && hctl[CTL_STOP]) refresh = true;
     int tstar = nbe;
     if (hctl[CTL_TFAIL] < tstar) tstar = hctl[CTL_TFAIL];
     if (hctl[CTL_TFLAG] < tstar) tstar = hctl[CTL_TFLAG];
