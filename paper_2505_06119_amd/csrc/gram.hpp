@@ -1,4 +1,5 @@
-// Candidate-window panels whose pivots come from the window's Gram matrix.
+// Candidate-window panels whose pivots come from the window's Gram matrix:
+// a second way to run the truncated QR with column pivoting of Table III.
 //
 // Greedy column pivoting picks at each step the column of largest residual
 // norm.  Those residual norms, and the R rows that downdate them, are fixed
