@@ -814,6 +814,36 @@ static hipError_t run_window_fixed(UpdateWs<T>& w, hipStream_t st, QrcpStats* st
     return hipGetLastError();
 }
 
+// The replay's outcome applied on the device, before the host has read it:
+// t* = min(nbe, first failing step, first flag) as the host computes it, the
+// rows t >= t* of W2 (UNGQR_NB x nout) set to zero, so that the rank-nbe
+// update A_o -= V W2 that follows is exactly the rank-t* one, and, unless a
+// norm refresh is due (stop flag or first flag <= t*, with p0 + t* < k), the
+// outside columns' norms downdated by their R rows 0 .. t*-1 in R12 (the
+// arithmetic of k_window_commit).  One thread per outside column c0 + q.
+template <typename T>
+__global__ __launch_bounds__(256) void k_replay_commit(QrcpDev<T> d, int64_t p0, int nbe, T* W2, const T* R12,
+                                                       int64_t ldw, int64_t c0, int64_t nout)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= nout) return;
+    int tstar = nbe;
+    if (d.ctl[CTL_TFAIL] < tstar) tstar = d.ctl[CTL_TFAIL];
+    if (d.ctl[CTL_TFLAG] < tstar) tstar = d.ctl[CTL_TFLAG];
+    if (tstar < 0) tstar = 0;
+    const bool refresh = d.ctl[CTL_STOP] != 0 || d.ctl[CTL_TFLAG] <= tstar;
+    for (int t = tstar; t < nbe; ++t) W2[t + ldw * q] = from_d<T>(czero());
+    if (refresh && p0 + tstar < d.k) return;
+    const int64_t c = c0 + q;
+    const T* rq = R12 + ldw * q;
+    double s = d.nu[c];
+    for (int t = 0; t < tstar; ++t) {
+        const double nn = s - cabs2(to_d(rq[t]));
+        s = nn < 0.0 ? 0.0 : nn;
+    }
+    d.nu[c] = s;
+}
+
 // The window's columns and their norms and keys back from the state saved at
 // the panel's set-up.
 template <typename T>
@@ -980,6 +1010,21 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
     hipLaunchKernelGGL((k_window_check<T>), dim3(nchk), dim3(256), 0, st, d, (const T*)w.Wbuf, (int64_t)UNGQR_NB,
                        c_o, nout, nbe);
     prof_end(ek, st, PK_WINDOW, 8.0 * (double)nbe * nout, 0.0);
+    // Right-looking panels enqueue the outside columns' update and norm
+    // commit before the host reads the replay's outcome: they take it from the
+    // control block (k_replay_commit), and a replay miss later redoes only the
+    // window, whose first t* reflectors come out bit-identical.
+    const bool spec = assume_full;
+    if (spec) {
+        hipLaunchKernelGGL((k_replay_commit<T>), dim3(nchk), dim3(256), 0, st, d, p0, nbe, w.W2buf,
+                           (const T*)w.Wbuf, (int64_t)UNGQR_NB, c_o, nout);
+        hipEvent_t eu = prof_begin(st);
+        if (!zrank_update<T>(st, true, rows, nout, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, Ao, d.lda) &&
+            !zgemm<T>(st, OP_N, true, OP_N, false, rows, nout, nbe, C_MONE, V, d.lda, w.W2buf, UNGQR_NB, C_ONE, Ao,
+                      d.lda, nullptr, 0))
+            return hipErrorInvalidValue;
+        prof_end(eu, st, PK_TRAIL, 2.0 * sizeof(T) * ro, 8.0 * ro * nbe);
+    }
     e = read_ctl<T>(d, st, hctl);
     if (e != hipSuccess) return e;
     if (assume_full && hctl[CTL_JDONE] != jend) {
@@ -1031,6 +1076,22 @@ static hipError_t window_panel(UpdateWs<T>& w, hipStream_t st, QrcpStats* stats,
         nbe = tstar;
         jend = p0 + tstar;
         if (stats) stats->window_misses++;
+    }
+
+    if (spec) {   // the update and the commit are already on the stream
+        if (stats) stats->panels++;
+        if (refresh && jend < k) {
+            const unsigned nblk = (unsigned)rup(n - jend, QR_CW);
+            hipEvent_t en = prof_begin(st);
+            hipLaunchKernelGGL((k_colnorms<T>), dim3(nblk), dim3(256), 0, st, d, jend, jend, 1, 0);
+            prof_end(en, st, PK_NORMS, (double)sizeof(T) * (double)(m - jend) * (double)(n - jend), 0.0);
+            *nparts = (int)nblk;
+            if (stats) stats->refreshes++;
+        } else {
+            *nparts = 0;
+        }
+        *jend_out = jend;
+        return hipSuccess;
     }
 
     // updates: the window's remaining columns from F (right-looking steps have
