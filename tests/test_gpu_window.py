@@ -143,3 +143,32 @@ def test_autotune_table_and_invariance(M, prec):
         np.testing.assert_allclose(got["diagR"], ref["diagR"], rtol=tol, atol=tol * scale)
     assert abs(got["err"] - ref["err"]) <= tol * scale
     assert np.linalg.norm(got["Q"] @ got["RPt"] - ref["Q"] @ ref["RPt"]) <= tol * scale
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("rank", [40, 64, 75])
+def test_window_rank_deficient_refreshes(M, prec, rank):
+    """Window panels past the rank: the replay flags the norms that fall under
+    the recomputation threshold, the panel's outside update and norm commit
+    (enqueued before the host reads the replay) leave the norms to a refresh,
+    and the factorisation still reproduces the matrix with pivots equal to the
+    oracle's up to the rank (FP64)."""
+    print(f"case window rank deficient rank={rank} prec={prec}", flush=True)
+    r = synth.rng(80 + rank)
+    a = synth.cgauss(r, (700, rank)) @ synth.cgauss(r, (rank, 600))
+    if prec == 1:
+        a = a.astype(np.complex64).astype(np.complex128)
+    k = 120
+    out = M.qrcp_truncate(M.colmajor(a, prec), k, prec)
+    q, rpt = _host(out["Q"]), _host(out["RPt"])
+    info = out["info"]
+    tol = TOL[prec]
+    scale = np.linalg.norm(a)
+    assert info["refreshes"] > 0
+    np.testing.assert_allclose(q.conj().T @ q, np.eye(k), atol=tol)
+    assert np.linalg.norm(a - q @ rpt) <= tol * scale
+    d = out["diagR"].cpu().numpy()
+    assert np.all(np.abs(d[rank:]) <= tol * abs(d[0]))
+    if prec == 0:
+        o = oracle.qrcp(a, rank)
+        assert list(out["piv"].cpu().numpy()[:rank]) == list(o["piv"][:rank])
