@@ -149,3 +149,26 @@ def test_gram_panels_two_site_update_matches_oracle(M, prec):
         tt = np.einsum("lak,kbr->labr", a2, b2)
         tr = np.einsum("lak,kbr->labr", ref["A"], ref["B"])
         assert np.max(np.abs(tt - tr)) <= tol * np.max(np.abs(tr))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("m,n,k,seed", [(300, 257, 257, 21), (513, 300, 200, 22), (290, 600, 280, 23),
+                                         (257, 290, 257, 24), (1025, 333, 333, 25)])
+def test_gram_panels_ragged_shapes(M, prec, m, n, k, seed):
+    """Ragged sizes: a window with one or a few outside columns, row counts
+    that are not multiples of the tiles, wide matrices, full factorisations."""
+    print(f"case gram ragged m={m} n={n} k={k} prec={prec}", flush=True)
+    a = synth.cgauss(synth.rng(seed), (m, n))
+    if prec == 1:
+        a = a.astype(np.complex64).astype(np.complex128)
+    g = _run(M, a, k, prec)
+    o = oracle.qrcp(a, k)
+    assert g["k"] == o["k"] == min(k, m, n)
+    tol = TOL[prec]
+    scale = np.linalg.norm(a)
+    if prec == 0:
+        assert list(g["piv"][:g["k"]]) == list(o["piv"][:o["k"]])
+    approx_o = o["Q"] @ oracle.r_unpivot(o["R"], o["piv"])
+    assert np.linalg.norm(g["Q"] @ g["RPt"] - approx_o) <= tol * scale
+    assert abs(g["err"] - o["err"]) <= tol * scale
+    np.testing.assert_allclose(g["Q"].conj().T @ g["Q"], np.eye(g["k"]), atol=tol)
